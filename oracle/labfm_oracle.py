@@ -1,0 +1,460 @@
+"""FP64 CPU oracle for the LABFM hot path (King & Lind, arXiv 2102.02019).
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import or call this
+module; only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark do. It shares no code, table or constant generator with the HIP
+library: every routine here is written from the paper's equations.
+
+The method has no cheaper closed form than its own definition, so each routine
+restates the paper's steps in its order and notation, in float64, with LAPACK
+``gesv`` (through ``numpy.linalg.solve``) for the local systems, as the paper
+does. Loops are vectorised over nodes only where that changes no per-node
+arithmetic.
+
+Readings of silent or garbled passages (each one is also listed in the design
+notes of the repository):
+
+* Wendland C2 kernel (section "New ABFs", cited, not printed):
+  psi(q) = (1 - q/2)^4 (1 + 2q) for q = |r|/h < 2, else 0 (support 2h, the
+  stencil radius).
+* The stencil excludes the node itself (it contributes exactly zero) and
+  includes ties at |r_ji| = 2h (the paper writes <=).
+* Operators beyond x, y, L needed by the momentum equation (xx, xy) come from
+  other choices of C^d, as the filter section allows; yy = L - xx.
+* The hyperviscous filter operator is nabla^m for even m and nabla^(m-1) for
+  odd m; its C vector puts binom(m'/2, p) at the monomial x^(2p) y^(m'-2p).
+* The filter is calibrated on the mode of wavenumber 2/3 of the Nyquist
+  wavenumber pi/s (the printed phase would put it above Nyquist; see
+  ``filter_coefficient``).
+* The pressure term -(1/rho) dp/dx with p = c^2 rho is evaluated as
+  -c^2 d(ln rho)/dx.
+* The time step is evaluated once, on the initial state.
+* RK3(2)4[2R+]C coefficients (named, not printed, in the paper) are those of
+  Kennedy, Carpenter & Lewis (2000); they are pinned by the third-order
+  conditions in the tests.
+
+Parity of the Taylor-Green run is pinned by trends only (the paper prints
+figures, not values); every other routine is pinned by closed forms,
+invariants, library routines or brute force in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+OPS = ("x", "y", "L", "xx", "xy", "hyp")
+OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
+
+STATUS_OK = 0
+STATUS_SINGULAR = 1
+STATUS_FEW_NEIGHBOURS = 2
+STATUS_BAD_FILTER = 3
+
+
+# ---------------------------------------------------------------------------
+# Section "The Local Anisotropic Basis Function Method": index order
+# ---------------------------------------------------------------------------
+
+def n_moments(m: int) -> int:
+    """Length of the monomial vector X for order m: (m^2 + 3m)/2."""
+    return (m * m + 3 * m) // 2
+
+
+def monomial_exponents(m: int) -> list:
+    """(a, b) for each entry of X = [x, y, x^2/2, xy, y^2/2, x^3/6, ...]:
+    ordered by total degree, then by decreasing power of x."""
+    out = []
+    for d in range(1, m + 1):
+        for b in range(0, d + 1):
+            out.append((d - b, b))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Section "Stencil": neighbour sets
+# ---------------------------------------------------------------------------
+
+def min_image(d: np.ndarray, L: float, periodic: bool) -> np.ndarray:
+    """Nearest periodic image of a coordinate difference."""
+    if not periodic:
+        return d
+    half = 0.5 * L
+    return np.where(d > half, d - L, np.where(d < -half, d + L, d))
+
+
+def in_stencil(dx: np.ndarray, dy: np.ndarray, h_i) -> np.ndarray:
+    """|r_ji| <= 2 h_i evaluated as dx*dx + dy*dy <= (2h)*(2h), each product
+    and the sum rounded separately (no fused multiply-add)."""
+    d2 = np.multiply(dx, dx) + np.multiply(dy, dy)
+    r = 2.0 * h_i
+    return d2 <= r * r
+
+
+def neighbours_bruteforce(x, y, h, box) -> tuple:
+    """All j != i with |r_ji| <= 2 h_i, by testing every pair. Rows list j in
+    ascending order. Returns CSR (row_ptr int64[N+1], col int64[nnz])."""
+    n = x.size
+    rows = []
+    for i in range(n):
+        dx = min_image(x - x[i], box.Lx, box.periodic_x)
+        dy = min_image(y - y[i], box.Ly, box.periodic_y)
+        sel = in_stencil(dx, dy, h[i])
+        sel[i] = False
+        rows.append(np.nonzero(sel)[0])
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([r.size for r in rows])
+    col = np.concatenate(rows).astype(np.int64) if n else np.zeros(0, np.int64)
+    return row_ptr, col
+
+
+def neighbours(x, y, h, box) -> tuple:
+    """Same set as ``neighbours_bruteforce``. Above a few thousand nodes the
+    candidates come from scipy's k-d tree with a slightly enlarged radius and
+    every candidate is then tested with the exact predicate above."""
+    n = x.size
+    if n <= 4096:
+        return neighbours_bruteforce(x, y, h, box)
+    from scipy.spatial import cKDTree
+
+    pts = np.stack([x, y], axis=1)
+    boxsize = None
+    if box.periodic_x and box.periodic_y:
+        boxsize = [box.Lx, box.Ly]
+    elif box.periodic_x or box.periodic_y:
+        raise NotImplementedError("mixed periodicity needs the brute-force path")
+    tree = cKDTree(pts, boxsize=boxsize)
+    rows = []
+    hmax = float(h.max())
+    # candidates within the largest radius, then the per-node predicate
+    cand = tree.query_ball_point(pts, r=2.0 * hmax * (1.0 + 1e-9), return_sorted=True)
+    for i in range(n):
+        c = np.asarray(cand[i], dtype=np.int64)
+        c = c[c != i]
+        dx = min_image(x[c] - x[i], box.Lx, box.periodic_x)
+        dy = min_image(y[c] - y[i], box.Ly, box.periodic_y)
+        rows.append(np.sort(c[in_stencil(dx, dy, h[i])]))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([r.size for r in rows])
+    col = np.concatenate(rows).astype(np.int64)
+    return row_ptr, col
+
+
+# ---------------------------------------------------------------------------
+# Sections "LABFM" and "New ABFs": basis functions, moment matrix, weights
+# ---------------------------------------------------------------------------
+
+def wendland_c2(q: np.ndarray) -> np.ndarray:
+    """Wendland C2 radial function of q = |r|/h with support q < 2."""
+    t = np.clip(1.0 - 0.5 * q, 0.0, None)
+    return np.where(q < 2.0, t ** 4 * (1.0 + 2.0 * q), 0.0)
+
+
+def hermite_phys(a: int, z: np.ndarray) -> np.ndarray:
+    """Physicists' Hermite polynomial H_a(z): H_0 = 1, H_1 = 2z,
+    H_{k+1} = 2z H_k - 2k H_{k-1}."""
+    h0 = np.ones_like(z)
+    if a == 0:
+        return h0
+    h1 = 2.0 * z
+    for k in range(1, a):
+        h0, h1 = h1, 2.0 * z * h1 - 2.0 * k * h0
+    return h1
+
+
+def taylor_monomials(xs: np.ndarray, ys: np.ndarray, m: int) -> np.ndarray:
+    """Scaled monomial vector X~_ji = X_ji . H_i: entry (a, b) is
+    (x/h)^a (y/h)^b / (a! b!) for the already scaled xs = x/h, ys = y/h.
+    Shape (..., n)."""
+    cols = []
+    for a, b in monomial_exponents(m):
+        cols.append(xs ** a * ys ** b / (math.factorial(a) * math.factorial(b)))
+    return np.stack(cols, axis=-1)
+
+
+def hermite_abfs(xs: np.ndarray, ys: np.ndarray, m: int) -> np.ndarray:
+    """Hermite ABFs: W^q = psi(|r|/h) H_a(x/(h sqrt2)) H_b(y/(h sqrt2)) / sqrt(2^(a+b)).
+    Shape (..., n)."""
+    psi = wendland_c2(np.sqrt(xs * xs + ys * ys))
+    r2 = math.sqrt(2.0)
+    cols = []
+    for a, b in monomial_exponents(m):
+        cols.append(psi * hermite_phys(a, xs / r2) * hermite_phys(b, ys / r2)
+                    / math.sqrt(2.0 ** (a + b)))
+    return np.stack(cols, axis=-1)
+
+
+def filter_power(m: int) -> int:
+    """Order of the hyperviscous filter operator: m if even, else m - 1."""
+    return m if m % 2 == 0 else m - 1
+
+
+def target_vectors(m: int, h: float) -> np.ndarray:
+    """C~^d = C^d . H for d in (x, y, L, xx, xy, hyp); shape (n, 6).
+
+    C^x, C^y, C^L as printed; xx and xy select one second derivative; hyp is
+    nabla^m' = sum_p binom(m'/2, p) d^m'/dx^(2p) dy^(m'-2p)."""
+    ex = monomial_exponents(m)
+    idx = {ab: q for q, ab in enumerate(ex)}
+    C = np.zeros((len(ex), 6))
+    C[idx[(1, 0)], OP_X] = 1.0
+    C[idx[(0, 1)], OP_Y] = 1.0
+    if m >= 2:
+        C[idx[(2, 0)], OP_L] = 1.0
+        C[idx[(0, 2)], OP_L] = 1.0
+        C[idx[(2, 0)], OP_XX] = 1.0
+        C[idx[(1, 1)], OP_XY] = 1.0
+    mp = filter_power(m)
+    if mp >= 2:
+        half = mp // 2
+        for p in range(half + 1):
+            C[idx[(2 * p, mp - 2 * p)], OP_HYP] = float(math.comb(half, p))
+    scale = np.array([h ** (-(a + b)) for a, b in ex])
+    return C * scale[:, None]
+
+
+def moment_matrix(Xt: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """M_i = sum_j X~_ji (outer) W_ji: rows are monomials, columns basis
+    functions. Xt, W have shape (K, n)."""
+    return Xt.T @ W
+
+
+def node_weights(dx: np.ndarray, dy: np.ndarray, h: float, s: float, m: int) -> dict:
+    """One node's weights w^d_ji for the six operators, its filter coefficient
+    and a status code, from the offsets r_ji = (dx, dy) of its K neighbours."""
+    n = n_moments(m)
+    K = dx.size
+    xs, ys = dx / h, dy / h
+    Xt = taylor_monomials(xs, ys, m)
+    W = hermite_abfs(xs, ys, m)
+    M = moment_matrix(Xt, W)
+    C = target_vectors(m, h)
+    status = STATUS_OK
+    if K < n:
+        status = STATUS_FEW_NEIGHBOURS
+    try:
+        Psi = np.linalg.solve(M, C)
+    except np.linalg.LinAlgError:
+        Psi = np.full((n, 6), np.nan)
+        status = STATUS_SINGULAR
+    w = (W @ Psi).T  # (6, K): w^d_ji = W_ji . Psi^d_i
+    kappa, fstat = filter_coefficient(dx, dy, s, w[OP_HYP])
+    if status == STATUS_OK and fstat != STATUS_OK:
+        status = fstat
+    return {"w": w, "kappa": kappa, "status": status, "M": M, "C": C, "Psi": Psi}
+
+
+def filter_coefficient(dx, dy, s: float, w_hyp: np.ndarray) -> tuple:
+    """F_0 = sum_j [1 - cos(k x_ji) cos(k y_ji)] w^hyp_ji and kappa = 2/(3 F_0),
+    so that the filter leaves 1/3 of that mode, with k two-thirds of the
+    Nyquist wavenumber pi/s, i.e. k = 2 pi / (3 s).
+
+    The paper's printed phase 3 pi x / (2 s) is 1.5 times the Nyquist
+    wavenumber; on a near-lattice it aliases to a low wavenumber, F_0 gets
+    small at some nodes and the filter then amplifies the highest modes. Its
+    text also names "two-thirds the Nyquist wavenumber", which is the reading
+    taken here."""
+    a = 2.0 * math.pi / (3.0 * s)
+    phi = 1.0 - np.cos(a * dx) * np.cos(a * dy)
+    F0 = float(np.sum(phi * w_hyp))
+    if not np.isfinite(F0) or F0 == 0.0:
+        return 0.0, STATUS_BAD_FILTER
+    return 2.0 / (3.0 * F0), STATUS_OK
+
+
+def stencil_offsets(x, y, box, row_ptr, col, i) -> tuple:
+    """r_ji = r_j - r_i (nearest periodic image) for the neighbours of i."""
+    c = col[row_ptr[i]:row_ptr[i + 1]]
+    dx = min_image(x[c] - x[i], box.Lx, box.periodic_x)
+    dy = min_image(y[c] - y[i], box.Ly, box.periodic_y)
+    return dx, dy
+
+
+def weights(x, y, h, s, m, row_ptr, col, box, nodes=None) -> dict:
+    """Weights for every node (or the listed ``nodes``).
+
+    Returns w (6, nnz) laid out like ``col`` (entries of unlisted nodes are
+    NaN), kappa (N,), rowsum (6, N) = sum_j w^d_ji, status (N,)."""
+    N = x.size
+    nnz = int(row_ptr[-1])
+    m = np.broadcast_to(np.asarray(m), (N,))
+    w = np.full((6, nnz), np.nan)
+    kappa = np.full(N, np.nan)
+    rowsum = np.full((6, N), np.nan)
+    status = np.full(N, -1, dtype=np.int8)
+    it = range(N) if nodes is None else nodes
+    for i in it:
+        dx, dy = stencil_offsets(x, y, box, row_ptr, col, i)
+        r = node_weights(dx, dy, float(h[i]), float(s[i]), int(m[i]))
+        w[:, row_ptr[i]:row_ptr[i + 1]] = r["w"]
+        kappa[i] = r["kappa"]
+        rowsum[:, i] = r["w"].sum(axis=1)
+        status[i] = r["status"]
+    return {"w": w, "kappa": kappa, "rowsum": rowsum, "status": status}
+
+
+def weights_batched(x, y, h, s, m: int, row_ptr, col, box, chunk: int = 4096) -> dict:
+    """Same steps as ``weights`` for a uniform order m, run over a stack of
+    nodes at once. Rows are padded to the longest row of the stack and padded
+    entries are masked out of every sum."""
+    N = x.size
+    nnz = int(row_ptr[-1])
+    n = n_moments(m)
+    K = np.diff(row_ptr)
+    w = np.empty((6, nnz))
+    kappa = np.empty(N)
+    rowsum = np.empty((6, N))
+    status = np.zeros(N, dtype=np.int8)
+    for lo in range(0, N, chunk):
+        hi = min(N, lo + chunk)
+        Kmax = int(K[lo:hi].max()) if hi > lo else 0
+        B = hi - lo
+        idx = np.arange(Kmax)[None, :]
+        valid = idx < K[lo:hi, None]
+        e = np.where(valid, row_ptr[lo:hi, None] + idx, 0)
+        cj = col[e]
+        ii = np.arange(lo, hi)[:, None]
+        dx = min_image(x[cj] - x[ii], box.Lx, box.periodic_x)
+        dy = min_image(y[cj] - y[ii], box.Ly, box.periodic_y)
+        hh = h[lo:hi, None]
+        Xt = taylor_monomials(dx / hh, dy / hh, m) * valid[..., None]
+        Wb = hermite_abfs(dx / hh, dy / hh, m) * valid[..., None]
+        M = np.einsum("bkp,bkq->bpq", Xt, Wb)
+        C = np.stack([target_vectors(m, float(h[i])) for i in range(lo, hi)])
+        try:
+            Psi = np.linalg.solve(M, C)
+        except np.linalg.LinAlgError:
+            Psi = np.empty((B, n, 6))
+            for b in range(B):
+                try:
+                    Psi[b] = np.linalg.solve(M[b], C[b])
+                except np.linalg.LinAlgError:
+                    Psi[b] = np.nan
+                    status[lo + b] = STATUS_SINGULAR
+        wb = np.einsum("bkq,bqd->bdk", Wb, Psi) * valid[:, None, :]
+        a = 2.0 * math.pi / (3.0 * s[lo:hi, None])
+        phi = (1.0 - np.cos(a * dx) * np.cos(a * dy)) * valid
+        F0 = np.sum(phi * wb[:, OP_HYP, :], axis=1)
+        bad = ~np.isfinite(F0) | (F0 == 0.0)
+        kappa[lo:hi] = np.where(bad, 0.0, 2.0 / (3.0 * np.where(bad, 1.0, F0)))
+        status[lo:hi] = np.where((status[lo:hi] == 0) & bad, STATUS_BAD_FILTER, status[lo:hi])
+        status[lo:hi] = np.where((status[lo:hi] == 0) & (K[lo:hi] < n),
+                                 STATUS_FEW_NEIGHBOURS, status[lo:hi])
+        rowsum[:, lo:hi] = wb.sum(axis=2).T
+        for b in range(B):
+            k = K[lo + b]
+            w[:, row_ptr[lo + b]:row_ptr[lo + b] + k] = wb[b, :, :k]
+    return {"w": w, "kappa": kappa, "rowsum": rowsum, "status": status}
+
+
+# ---------------------------------------------------------------------------
+# Equation general_do: the discrete operator
+# ---------------------------------------------------------------------------
+
+def apply_op(row_ptr, col, w_d: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """L^d_i(phi) = sum_j (phi_j - phi_i) w^d_ji, summed in ascending j."""
+    N = row_ptr.size - 1
+    K = np.diff(row_ptr)
+    rows = np.repeat(np.arange(N), K)
+    terms = (phi[col] - phi[rows]) * w_d
+    # bincount adds the terms one after another in storage order, i.e. each
+    # row in ascending j
+    if np.iscomplexobj(terms):
+        return (np.bincount(rows, weights=terms.real, minlength=N)
+                + 1j * np.bincount(rows, weights=terms.imag, minlength=N))
+    return np.bincount(rows, weights=terms, minlength=N)
+
+
+# ---------------------------------------------------------------------------
+# Section "Implementation for isothermal flows": right-hand side, RK, filter
+# ---------------------------------------------------------------------------
+
+# RK3(2)4[2R+]C of Kennedy, Carpenter & Lewis (2000), in 2R form: the Butcher
+# matrix has a_{i,j} = b_j for j < i-1, so only a_{i+1,i} and b_i are needed.
+RK_A_SUB = (Fraction(11847461282814, 36547543011857),
+            Fraction(3943225443063, 7078155732230),
+            Fraction(-346793006927, 4029903576067))
+RK_B = (Fraction(1017324711453, 9774461848756),
+        Fraction(8237718856693, 13685301971492),
+        Fraction(57731312506979, 19404895981398),
+        Fraction(-101169746363290, 37734290219643))
+
+
+def butcher_tableau() -> tuple:
+    """Full (A, b, c) of the 2R scheme as exact fractions."""
+    s = 4
+    A = [[Fraction(0)] * s for _ in range(s)]
+    for i in range(1, s):
+        for j in range(i - 1):
+            A[i][j] = RK_B[j]
+        A[i][i - 1] = RK_A_SUB[i - 1]
+    c = [sum(row) for row in A]
+    return A, list(RK_B), c
+
+
+def ns_rhs(lnrho, u, v, W: dict, prm) -> tuple:
+    """Right-hand side of the isothermal Navier-Stokes equations in
+    (ln rho, u, v) with the full viscous stress (equation icns).
+
+    W holds row_ptr, col and the operator weights w (6, nnz)."""
+    rp, col, w = W["row_ptr"], W["col"], W["w"]
+
+    def L(d, f):
+        return apply_op(rp, col, w[d], f)
+
+    lx, ly = L(OP_X, lnrho), L(OP_Y, lnrho)
+    ux, uy, uL, uxx, uxy = (L(OP_X, u), L(OP_Y, u), L(OP_L, u), L(OP_XX, u), L(OP_XY, u))
+    vx, vy, vL, vxx, vxy = (L(OP_X, v), L(OP_Y, v), L(OP_L, v), L(OP_XX, v), L(OP_XY, v))
+    uyy = uL - uxx
+    vyy = vL - vxx
+    rho = np.exp(lnrho)
+    nu = prm.mu / rho
+    r_l = -(u * lx + v * ly) - (ux + vy)
+    r_u = (-(u * ux + v * uy) - prm.c2 * lx
+           + nu * (4.0 / 3.0 * uxx + uyy + 1.0 / 3.0 * vxy) + prm.gx)
+    r_v = (-(u * vx + v * vy) - prm.c2 * ly
+           + nu * (4.0 / 3.0 * vyy + vxx + 1.0 / 3.0 * uxy) + prm.gy)
+    return r_l, r_u, r_v
+
+
+def filter_fields(fields: tuple, W: dict) -> tuple:
+    """phi~_i = phi_i + kappa_i L^hyp_i(phi) for each evolved field."""
+    rp, col, w, kappa = W["row_ptr"], W["col"], W["w"], W["kappa"]
+    return tuple(f + kappa * apply_op(rp, col, w[OP_HYP], f) for f in fields)
+
+
+def time_step(s, lnrho, u, v, prm) -> float:
+    """Equation dt: min over nodes of min(1.0 s/(|u|+c), 0.4 s^2 rho / mu)."""
+    c = math.sqrt(prm.c2)
+    speed = np.sqrt(u * u + v * v)
+    conv = 1.0 * s / (speed + c)
+    visc = 0.4 * s * s * np.exp(lnrho) / prm.mu
+    return float(np.min(np.minimum(conv, visc)))
+
+
+def rk_integrate(q: tuple, rhs, dt: float, n_steps: int, after_step=None) -> tuple:
+    """n_steps of the four-stage low-storage scheme: two registers, q (the
+    solution) and Y (the stage value). At stage i: F = rhs(Y); Y = q + dt
+    a_{i+1,i} F (stages 1-3, using q before its update); q = q + dt b_i F.
+    ``after_step`` (the filter) maps the new q after every complete step."""
+    a = [float(v) for v in RK_A_SUB]
+    b = [float(v) for v in RK_B]
+    q = tuple(np.array(f, dtype=np.result_type(f, float), copy=True) for f in q)
+    for _ in range(n_steps):
+        Y = q
+        for i in range(4):
+            F = rhs(*Y)
+            if i < 3:
+                Y = tuple(qk + (dt * a[i]) * fk for qk, fk in zip(q, F))
+            q = tuple(qk + (dt * b[i]) * fk for qk, fk in zip(q, F))
+        if after_step is not None:
+            q = after_step(q)
+    return q
+
+
+def rk_run(lnrho, u, v, W: dict, prm, dt: float, n_steps: int, filt: bool = True) -> tuple:
+    """Evolve (ln rho, u, v) by n_steps RK steps with the filter after each."""
+    rhs = lambda l_, u_, v_: ns_rhs(l_, u_, v_, W, prm)  # noqa: E731
+    post = (lambda q: filter_fields(q, W)) if filt else None
+    return rk_integrate((lnrho, u, v), rhs, dt, n_steps, post)

@@ -1,0 +1,211 @@
+"""Seeded synthetic workloads shared by the HIP path, its tests and the oracle's tests.
+
+This module holds only input generation: node positions, resolution fields and
+initial flow fields. It contains none of the LABFM arithmetic (no basis
+functions, no moment matrices, no operators), so that the oracle and the GPU
+path can both be fed the identical arrays without sharing any of the method.
+
+Node sets follow the uniform-resolution recipe of the paper's section on node
+generation (a Cartesian lattice, each node shifted by a random vector), with a
+per-coordinate uniform jitter of +/-0.3 s and no iterative shifting. Nodes are
+returned in Morton (Z-curve) order of their lattice cell so that nodes close in
+space are close in memory.
+
+Random numbers come from numpy's PCG64 generator seeded through SeedSequence.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Stencil scale h/s per LABFM order m for the periodic Taylor-Green workloads.
+# Chosen so that the mean stencil population on a +/-0.3 s jittered lattice is
+# ~30 (m=4), ~60 (m=6), ~90 (m=8) and ~130 (m=10) neighbours.
+H_OVER_S = {2: 1.2, 4: 1.55, 6: 2.2, 8: 2.68, 10: 3.2}
+
+
+@dataclass(frozen=True)
+class Box:
+    """Rectangular domain [0, Lx) x [0, Ly), each axis periodic or not."""
+
+    Lx: float
+    Ly: float
+    periodic_x: bool = True
+    periodic_y: bool = True
+
+
+@dataclass
+class NodeSet:
+    """Structure-of-arrays node description (all float64 except m)."""
+
+    x: np.ndarray
+    y: np.ndarray
+    s: np.ndarray  # local distribution length scale s_i
+    h: np.ndarray  # stencil length scale h_i (stencil radius is 2 h_i)
+    m: np.ndarray  # int8 LABFM order per node
+    box: Box
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def morton_key_2d(ix: np.ndarray, iy: np.ndarray) -> np.ndarray:
+    """Z-order key of non-negative integer cell coordinates (< 2**21)."""
+
+    def part1by1(a: np.ndarray) -> np.ndarray:
+        a = a.astype(np.uint64) & np.uint64(0xFFFFFFFF)
+        a = (a | (a << np.uint64(16))) & np.uint64(0x0000FFFF0000FFFF)
+        a = (a | (a << np.uint64(8))) & np.uint64(0x00FF00FF00FF00FF)
+        a = (a | (a << np.uint64(4))) & np.uint64(0x0F0F0F0F0F0F0F0F)
+        a = (a | (a << np.uint64(2))) & np.uint64(0x3333333333333333)
+        a = (a | (a << np.uint64(1))) & np.uint64(0x5555555555555555)
+        return a
+
+    return part1by1(ix) | (part1by1(iy) << np.uint64(1))
+
+
+def morton_order(x: np.ndarray, y: np.ndarray, box: Box, cell: float) -> np.ndarray:
+    """Stable permutation sorting points by the Morton key of their cell."""
+    nx = max(1, int(math.ceil(box.Lx / cell)))
+    ny = max(1, int(math.ceil(box.Ly / cell)))
+    ix = np.minimum(np.floor(x / cell).astype(np.int64), nx - 1).clip(0)
+    iy = np.minimum(np.floor(y / cell).astype(np.int64), ny - 1).clip(0)
+    key = morton_key_2d(ix, iy)
+    return np.argsort(key, kind="stable")
+
+
+def jittered_lattice(n_side: int, L: float = 2.0 * math.pi, jitter: float = 0.3,
+                     seed: int = 1, m: int = 4, h_over_s: float | None = None,
+                     periodic: bool = True, morton: bool = True) -> NodeSet:
+    """n_side x n_side lattice on [0, L)^2 with each coordinate shifted by
+    U(-jitter*s, +jitter*s), wrapped into the box when periodic.
+
+    Non-periodic boxes keep the jittered points inside [0, L) by clipping the
+    shift at the walls (only used for exactness tests on global polynomials).
+    """
+    s = L / n_side
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    iy, ix = np.meshgrid(np.arange(n_side), np.arange(n_side), indexing="ij")
+    ix = ix.ravel()
+    iy = iy.ravel()
+    ex = rng.uniform(-jitter, jitter, ix.size) * s
+    ey = rng.uniform(-jitter, jitter, ix.size) * s
+    x = (ix + 0.5) * s + ex
+    y = (iy + 0.5) * s + ey
+    if periodic:
+        x = np.mod(x, L)
+        y = np.mod(y, L)
+        # np.mod can return L itself for tiny negative inputs; fold that to 0
+        x[x >= L] -= L
+        y[y >= L] -= L
+    if morton:
+        order = np.argsort(morton_key_2d(ix, iy), kind="stable")
+        x, y = x[order], y[order]
+    hs = H_OVER_S[m] if h_over_s is None else h_over_s
+    n = x.size
+    return NodeSet(
+        x=np.ascontiguousarray(x, dtype=np.float64),
+        y=np.ascontiguousarray(y, dtype=np.float64),
+        s=np.full(n, s, dtype=np.float64),
+        h=np.full(n, hs * s, dtype=np.float64),
+        m=np.full(n, m, dtype=np.int8),
+        box=Box(L, L, periodic, periodic),
+        meta={"n_side": n_side, "L": L, "jitter": jitter, "seed": seed,
+              "m": m, "h_over_s": hs, "spacing": s},
+    )
+
+
+def random_cloud(n: int, L: float = 1.0, seed: int = 0, periodic: bool = True) -> tuple:
+    """Uniform random points (for neighbour-search tests with clustered or
+    duplicate-prone layouts)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    x = rng.uniform(0.0, L, n)
+    y = rng.uniform(0.0, L, n)
+    return np.ascontiguousarray(x), np.ascontiguousarray(y), Box(L, L, periodic, periodic)
+
+
+# --------------------------------------------------------------------------
+# Initial flow fields
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class FlowParams:
+    """Isothermal flow constants: sound speed squared, viscosity, body force."""
+
+    c2: float
+    mu: float
+    gx: float = 0.0
+    gy: float = 0.0
+
+
+def taylor_green_params(Re: float = 100.0, Ma: float = 0.1, L: float = 2.0 * math.pi,
+                        U0: float = 1.0, rho0: float = 1.0) -> FlowParams:
+    """Reynolds number on the unit velocity and the domain half-width L/2;
+    Mach number U0/c."""
+    c = U0 / Ma
+    mu = rho0 * U0 * (0.5 * L) / Re
+    return FlowParams(c2=c * c, mu=mu)
+
+
+def taylor_green_state(x: np.ndarray, y: np.ndarray, L: float = 2.0 * math.pi) -> tuple:
+    """u = sin(kx) cos(ky), v = -cos(kx) sin(ky), rho = 1 with k = 2 pi / L.
+
+    Returns (rho, u, v)."""
+    k = 2.0 * math.pi / L
+    u = np.sin(k * x) * np.cos(k * y)
+    v = -np.cos(k * x) * np.sin(k * y)
+    rho = np.ones_like(x)
+    return rho, u, v
+
+
+def fourier_perturbation(x: np.ndarray, y: np.ndarray, seed: int, amp: float = 0.01,
+                         kmax: int = 4, L: float = 2.0 * math.pi) -> tuple:
+    """Three smooth periodic perturbations: amp * sum over integer wave vectors
+    with 1 <= max(|kx|,|ky|) <= kmax of Gaussian-weighted sin and cos modes."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    base = 2.0 * math.pi / L
+    out = []
+    for _ in range(3):
+        f = np.zeros_like(x)
+        for kx in range(-kmax, kmax + 1):
+            for ky in range(0, kmax + 1):
+                if max(abs(kx), abs(ky)) == 0 or (ky == 0 and kx < 0):
+                    continue
+                a, b = rng.standard_normal(2)
+                ph = base * (kx * x + ky * y)
+                f += a * np.sin(ph) + b * np.cos(ph)
+        out.append(amp * f / math.sqrt(2 * (2 * kmax + 1) * (kmax + 1)))
+    return tuple(out)
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n_side: int
+    m: int
+    seed: int
+    steps: int
+    L: float = 2.0 * math.pi
+
+    def nodes(self) -> NodeSet:
+        return jittered_lattice(self.n_side, L=self.L, seed=self.seed, m=self.m)
+
+
+# Small periodic Taylor-Green case (4,096 nodes, m=4, 20 RK steps).
+TG64_M4 = Workload("tg64_m4", 64, 4, seed=1, steps=20)
+# Main periodic Taylor-Green case (262,144 nodes, m=8, 1000 RK steps).
+TG512_M8 = Workload("tg512_m8", 512, 8, seed=2, steps=1000)
+# Large mixed-precision case (4,194,304 nodes, m=8, 500 RK steps).
+TG2048_M8 = Workload("tg2048_m8", 2048, 8, seed=4, steps=500)
+# Adjoint case (65,536 nodes, m=6, 200 RK steps).
+TG256_M6 = Workload("tg256_m6", 256, 6, seed=5, steps=200)
+
+WORKLOADS = {w.name: w for w in (TG64_M4, TG512_M8, TG2048_M8, TG256_M6)}

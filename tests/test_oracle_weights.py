@@ -1,0 +1,239 @@
+"""Pins of the oracle's weight construction (equations disc_form, lsys, w_abf
+and hermite of the paper) by exactness, extended-precision solves and
+invariants (CPU only)."""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import sympy
+
+from oracle import labfm_oracle as O
+from paper_2102_02019_amd import inputs
+
+OP_ORDER = {O.OP_X: 1, O.OP_Y: 1, O.OP_L: 2, O.OP_XX: 2, O.OP_XY: 2}
+
+
+def _node(nodes, rp, col, i):
+    dx, dy = O.stencil_offsets(nodes.x, nodes.y, nodes.box, rp, col, i)
+    return dx, dy
+
+
+@pytest.fixture(scope="module")
+def tg64():
+    nodes = inputs.jittered_lattice(64, seed=1, m=4)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, 4, rp, col, nodes.box)
+    return nodes, rp, col, W
+
+
+def test_batched_equals_per_node(tg64):
+    nodes, rp, col, W = tg64
+    sample = [0, 17, 1000, 4095]
+    Wp = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, 4, rp, col, nodes.box, nodes=sample)
+    for i in sample:
+        a, b = rp[i], rp[i + 1]
+        np.testing.assert_allclose(W["w"][:, a:b], Wp["w"][:, a:b], rtol=1e-11,
+                                   atol=1e-11 * np.abs(Wp["w"][:, a:b]).max())
+        assert W["kappa"][i] == pytest.approx(Wp["kappa"][i], rel=1e-10)
+
+
+@pytest.mark.parametrize("m", [4, 6, 8])
+def test_polynomial_reproduction(m):
+    """sum_j X_ji w^d_ji = C^d for every monomial of degree <= m (the
+    defining property of the weights, eq. lsys with eq. w_abf)."""
+    nodes = inputs.jittered_lattice(24, seed=2, m=m)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    sample = range(0, nodes.n, 37)
+    W = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box, nodes=sample)
+    for i in sample:
+        dx, dy = _node(nodes, rp, col, i)
+        h = nodes.h[i]
+        w = W["w"][:, rp[i]:rp[i + 1]]
+        X = O.taylor_monomials(dx, dy, m)  # unscaled X_ji
+        mom = X.T @ w.T  # (n, 6)
+        C = O.target_vectors(m, 1.0)  # unscaled C^d
+        for d in range(6):
+            # size of the individual terms sets the rounding scale
+            scale = np.abs(X).T @ np.abs(w[d]) + 1e-300
+            assert np.all(np.abs(mom[:, d] - C[:, d]) <= 1e-10 * scale), (m, i, d)
+        assert W["status"][i] == 0
+
+
+def _exact_weights(dx, dy, h, m, digits=40):
+    """Weights from a 40-digit solve with mpmath's own Hermite polynomials."""
+    with mpmath.workdps(digits):
+        ex = O.monomial_exponents(m)
+        n = len(ex)
+        hm = mpmath.mpf(h)
+        K = dx.size
+        Xt = mpmath.matrix(K, n)
+        Wm = mpmath.matrix(K, n)
+        for k in range(K):
+            xs = mpmath.mpf(dx[k]) / hm
+            ys = mpmath.mpf(dy[k]) / hm
+            q = mpmath.sqrt(xs * xs + ys * ys)
+            psi = (1 - q / 2) ** 4 * (1 + 2 * q) if q < 2 else mpmath.mpf(0)
+            for c, (a, b) in enumerate(ex):
+                Xt[k, c] = xs ** a * ys ** b / (mpmath.factorial(a) * mpmath.factorial(b))
+                Wm[k, c] = (psi * mpmath.hermite(a, xs / mpmath.sqrt(2))
+                            * mpmath.hermite(b, ys / mpmath.sqrt(2)) / mpmath.sqrt(2) ** (a + b))
+        M = Xt.T * Wm
+        C = O.target_vectors(m, 1.0)
+        out = np.zeros((6, K))
+        for d in range(6):
+            c = mpmath.matrix([mpmath.mpf(C[p, d]) / hm ** sum(ex[p]) for p in range(n)])
+            psi_d = mpmath.lu_solve(M, c)
+            wd = Wm * psi_d
+            out[d] = [float(wd[k]) for k in range(K)]
+        Mf = np.array([[float(M[r, c]) for c in range(n)] for r in range(n)])
+    return out, np.linalg.cond(Mf)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m,nside", [(4, 16), (6, 16), (8, 20), (10, 20)])
+def test_weights_match_extended_precision_solve(m, nside):
+    nodes = inputs.jittered_lattice(nside, seed=3, m=m)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    for i in (0, nodes.n // 3, nodes.n - 1):
+        dx, dy = _node(nodes, rp, col, i)
+        r = O.node_weights(dx, dy, nodes.h[i], nodes.s[i], m)
+        ex, cond = _exact_weights(dx, dy, nodes.h[i], m)
+        for d in range(6):
+            err = np.linalg.norm(r["w"][d] - ex[d]) / np.linalg.norm(ex[d])
+            assert err <= max(1e-13, 50 * cond * 2.2e-16), (m, i, d, err, cond)
+
+
+def test_h_scaling_leaves_solution_unchanged():
+    """Solving with unscaled X and C gives the same weights (the exact
+    solution is unchanged by the row scaling)."""
+    m = 6
+    nodes = inputs.jittered_lattice(16, seed=4, m=m)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    i = 77
+    dx, dy = _node(nodes, rp, col, i)
+    h = nodes.h[i]
+    r = O.node_weights(dx, dy, h, nodes.s[i], m)
+    X = O.taylor_monomials(dx, dy, m)  # unscaled
+    W = O.hermite_abfs(dx / h, dy / h, m)
+    Psi = np.linalg.solve(X.T @ W, O.target_vectors(m, 1.0))
+    w_unscaled = (W @ Psi).T
+    for d in range(6):
+        np.testing.assert_allclose(w_unscaled[d], r["w"][d], rtol=0,
+                                   atol=1e-7 * np.abs(r["w"][d]).max())
+
+
+def test_rbf_scale_invariance():
+    m = 4
+    nodes = inputs.jittered_lattice(16, seed=5, m=m)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    dx, dy = _node(nodes, rp, col, 50)
+    r1 = O.node_weights(dx, dy, nodes.h[50], nodes.s[50], m)
+    orig = O.wendland_c2
+    try:
+        O.wendland_c2 = lambda q: 7.5 * orig(q)
+        r2 = O.node_weights(dx, dy, nodes.h[50], nodes.s[50], m)
+    finally:
+        O.wendland_c2 = orig
+    np.testing.assert_allclose(r2["w"], r1["w"], rtol=1e-11, atol=1e-9)
+
+
+def test_scaling_law():
+    """Scaling offsets and h by lambda scales w^d by lambda^-l (l = order of
+    the derivative), and the filter coefficient is unchanged in units of s."""
+    m = 6
+    nodes = inputs.jittered_lattice(16, seed=6, m=m)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    dx, dy = _node(nodes, rp, col, 20)
+    h, s = nodes.h[20], nodes.s[20]
+    lam = 0.25  # a power of two: all offsets scale exactly
+    r1 = O.node_weights(dx, dy, h, s, m)
+    r2 = O.node_weights(lam * dx, lam * dy, lam * h, lam * s, m)
+    for d, l in OP_ORDER.items():
+        np.testing.assert_allclose(r2["w"][d], r1["w"][d] * lam ** (-l), rtol=1e-9,
+                                   atol=1e-9 * np.abs(r1["w"][d]).max() * lam ** (-l))
+    np.testing.assert_allclose(r2["w"][O.OP_HYP], r1["w"][O.OP_HYP] * lam ** (-m), rtol=1e-8,
+                               atol=1e-8 * np.abs(r1["w"][O.OP_HYP]).max() * lam ** (-m))
+    assert r2["kappa"] == pytest.approx(r1["kappa"] * lam ** m, rel=1e-8)
+
+
+def test_lattice_symmetries():
+    """On a perfect lattice: w^x is odd in x and even in y, w^y(x,y) =
+    w^x(y,x), and w^L is invariant under the square's symmetries."""
+    m = 4
+    nodes = inputs.jittered_lattice(16, seed=0, m=m, jitter=0.0)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    i = 100
+    dx, dy = _node(nodes, rp, col, i)
+    r = O.node_weights(dx, dy, nodes.h[i], nodes.s[i], m)
+    s = nodes.s[i]
+    key = {(round(a / s), round(b / s)): k for k, (a, b) in enumerate(zip(dx, dy))}
+    wx, wy, wL = r["w"][O.OP_X], r["w"][O.OP_Y], r["w"][O.OP_L]
+    tol = 1e-9 * np.abs(r["w"][:3]).max()
+    for (a, b), k in key.items():
+        assert abs(wx[k] + wx[key[(-a, b)]]) <= tol
+        assert abs(wx[k] - wx[key[(a, -b)]]) <= tol
+        assert abs(wy[k] - wx[key[(b, a)]]) <= tol
+        assert abs(wL[k] - wL[key[(-b, a)]]) <= tol
+        assert abs(wL[k] - wL[key[(b, a)]]) <= tol
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_hyperviscous_operator_on_monomials(m):
+    """L^hyp applied to a global polynomial of degree m gives nabla^m of it,
+    with nabla^m computed symbolically by sympy."""
+    X, Y = sympy.symbols("x y")
+    nodes = inputs.jittered_lattice(20, L=1.0, seed=8, m=m, periodic=False)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    # interior nodes: full stencils
+    inner = [i for i in range(nodes.n)
+             if 0.35 < nodes.x[i] < 0.65 and 0.35 < nodes.y[i] < 0.65]
+    W = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box, nodes=inner)
+    rng = np.random.default_rng(9)
+    coeffs = rng.standard_normal(m + 1)
+    poly = sum(c * X ** (m - k) * Y ** k for k, c in enumerate(coeffs)) + X * Y + 3
+    lap = lambda f: sympy.diff(f, X, 2) + sympy.diff(f, Y, 2)  # noqa: E731
+    hyp = poly
+    for _ in range(m // 2):
+        hyp = lap(hyp)
+    target = float(hyp)  # a constant for a degree-m polynomial
+    f = sympy.lambdify((X, Y), poly, "numpy")
+    phi = f(nodes.x, nodes.y)
+    for i in inner:
+        a, b = rp[i], rp[i + 1]
+        val = np.sum((phi[col[a:b]] - phi[i]) * W["w"][O.OP_HYP, a:b])
+        scale = np.sum(np.abs(phi[col[a:b]] - phi[i]) * np.abs(W["w"][O.OP_HYP, a:b]))
+        assert abs(val - target) <= 1e-9 * scale + 1e-9 * abs(target)
+
+
+def test_global_polynomials_nonperiodic():
+    """First and second derivatives of every monomial of degree <= 4 are
+    exact at nodes with complete stencils on a non-periodic box."""
+    m = 4
+    X, Y = sympy.symbols("x y")
+    nodes = inputs.jittered_lattice(24, L=1.0, seed=10, m=m, periodic=False)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    inner = [i for i in range(nodes.n)
+             if 0.3 < nodes.x[i] < 0.7 and 0.3 < nodes.y[i] < 0.7]
+    W = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box, nodes=inner)
+    ops = {O.OP_X: lambda f: sympy.diff(f, X), O.OP_Y: lambda f: sympy.diff(f, Y),
+           O.OP_L: lambda f: sympy.diff(f, X, 2) + sympy.diff(f, Y, 2),
+           O.OP_XX: lambda f: sympy.diff(f, X, 2), O.OP_XY: lambda f: sympy.diff(f, X, Y)}
+    idx = np.array(inner)
+    for deg in range(0, m + 1):
+        for a in range(deg + 1):
+            poly = X ** (deg - a) * Y ** a
+            phi = sympy.lambdify((X, Y), poly, "numpy")(nodes.x, nodes.y) * np.ones(nodes.n)
+            for d, op in ops.items():
+                ref = sympy.lambdify((X, Y), op(poly), "numpy")(nodes.x[idx], nodes.y[idx])
+                ref = ref * np.ones(idx.size)
+                got = np.array([np.sum((phi[col[rp[i]:rp[i + 1]]] - phi[i])
+                                       * W["w"][d, rp[i]:rp[i + 1]]) for i in inner])
+                assert np.max(np.abs(got - ref)) <= 1e-8 * (1 + np.max(np.abs(ref))), (deg, a, d)
+
+
+def test_few_neighbours_status():
+    dx = np.array([0.1, 0.0, -0.1])
+    dy = np.array([0.0, 0.1, 0.0])
+    r = O.node_weights(dx, dy, 0.1, 0.1, 4)
+    assert r["status"] in (O.STATUS_FEW_NEIGHBOURS, O.STATUS_SINGULAR)
