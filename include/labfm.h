@@ -1,0 +1,247 @@
+/*
+ * labfm.h - C ABI of the MI355X (gfx950) LABFM hot-path library.
+ *
+ * LABFM (local anisotropic basis function method, King & Lind, arXiv
+ * 2102.02019) builds high-order mesh-free derivative operators
+ *     L^d_i(phi) = sum_j (phi_j - phi_i) w^d_ji            (eq. general_do)
+ * from a per-node linear system over Hermite anisotropic basis functions,
+ * and uses them in an explicit Runge-Kutta solve of the isothermal
+ * compressible Navier-Stokes equations.
+ *
+ * Conventions shared by every call:
+ *  - Arrays are DEVICE pointers (HIP device memory) unless marked "host".
+ *    The caller owns every buffer; no call keeps a pointer after it returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on that stream and the call returns without waiting,
+ *    except where a host output is documented (then the call synchronises
+ *    the stream before returning).
+ *  - Every call returns LABFM_OK (0) or a negative status; none throws across
+ *    the ABI. labfm_last_error() returns a message for the calling thread's
+ *    most recent failure.
+ *  - Node arrays are structure-of-arrays, float64, length n; fields of the
+ *    evolved state are stored one after another: q = [ln rho | u | v], each
+ *    of length n.
+ *  - Stencils are CSR: row_ptr int32[n+1] (row_ptr[0] = 0), col int32[nnz],
+ *    the neighbours of node i in ascending index order, i itself excluded.
+ *  - Operator weights are stored one operator after another:
+ *    w[op * nnz + e] for edge e of the CSR, op in labfm_op order.
+ */
+#ifndef LABFM_H
+#define LABFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  LABFM_OK = 0,
+  LABFM_ERR_ARG = -1,         /* invalid argument (null pointer, size, box) */
+  LABFM_ERR_HIP = -2,         /* a HIP runtime call failed */
+  LABFM_ERR_CAPACITY = -3,    /* output capacity too small (size reported) */
+  LABFM_ERR_NONFINITE = -4,   /* a non-finite value appeared in the state */
+  LABFM_ERR_UNSUPPORTED = -5  /* request outside what the library implements */
+};
+
+/* Operator index (row of the weight array). The first five are the
+ * derivative operators used by the Navier-Stokes right-hand side; the last
+ * is the hyperviscous filter operator nabla^m (nabla^(m-1) for odd m). */
+typedef enum {
+  LABFM_OP_X = 0,   /* d/dx                       C^x: x        */
+  LABFM_OP_Y = 1,   /* d/dy                       C^y: y        */
+  LABFM_OP_L = 2,   /* Laplacian d2/dx2 + d2/dy2  C^L: x^2 + y^2 */
+  LABFM_OP_XX = 3,  /* d2/dx2                                   */
+  LABFM_OP_XY = 4,  /* d2/dxdy                                  */
+  LABFM_OP_HYP = 5, /* nabla^m (filter)                         */
+  LABFM_NUM_OPS = 6
+} labfm_op;
+
+/* Arithmetic of operator application. */
+typedef enum {
+  LABFM_F64 = 0,      /* float64 weights and fields, float64 sums */
+  LABFM_F32_COMP = 2  /* float32 weights; differences phi_j - phi_i formed in
+                         float64 and rounded to float32; products and sums
+                         compensated (error-free TwoProd + TwoSum, "Dot2") */
+} labfm_prec;
+
+/* Per-node status written by labfm_build_weights. */
+enum {
+  LABFM_NODE_OK = 0,
+  LABFM_NODE_SINGULAR = 1,       /* a zero pivot in the LU factorisation */
+  LABFM_NODE_FEW_NEIGHBOURS = 2, /* fewer neighbours than moments (K < n) */
+  LABFM_NODE_BAD_FILTER = 3,     /* filter calibration F_0 zero/non-finite */
+  LABFM_NODE_BAD_ORDER = 4       /* order_m outside 1..10 (weights set to 0) */
+};
+
+/* Rectangular domain [0, Lx) x [0, Ly); each axis periodic (1) or not (0).
+ * Positions must lie inside the box. */
+typedef struct {
+  double Lx, Ly;
+  int32_t periodic_x, periodic_y;
+} labfm_box;
+
+/* Operators of a node set, as built by labfm_build_weights. */
+typedef struct {
+  int32_t n;                /* nodes */
+  int64_t nnz;              /* CSR entries */
+  const int32_t* row_ptr;   /* int32[n+1] */
+  const int32_t* col;       /* int32[nnz] */
+  const double* w;          /* float64[6*nnz], labfm_op order (may be NULL
+                               when only the float32 copy is used) */
+  const float* w32;         /* float32[6*nnz] or NULL */
+  const double* kappa;      /* float64[n] filter coefficients */
+} labfm_operators;
+
+/* Constants of the isothermal flow and of the integration. */
+typedef struct {
+  double c2;        /* speed of sound squared, p = c2 * rho */
+  double mu;        /* dynamic viscosity (uniform) */
+  double gx, gy;    /* body force */
+  double dt;        /* time step, > 0 */
+  int32_t filter;   /* 1: filter ln rho, u, v after every step */
+  int32_t check_finite; /* 1: test the state once at the end of the call
+                           (synchronises) and report LABFM_ERR_NONFINITE */
+} labfm_rk_params;
+
+/* Kernel timings collected by labfm_rk_step when requested. Durations are
+ * measured with HIP events recorded on the call's stream around each launch
+ * (summed over the launches of the call). */
+typedef struct {
+  double stage_ms;        /* all Runge-Kutta stage launches */
+  double filter_ms;       /* all filter launches */
+  int64_t stage_launches;
+  int64_t filter_launches;
+} labfm_timing;
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* labfm_last_error(void);
+
+/* Library version string. */
+const char* labfm_version(void);
+
+/*
+ * Stencil search (stencil definition of the paper's LABFM section): node j
+ * is a neighbour of node i iff j != i and |r_ji| <= 2 h_i, where
+ * r_ji = r_j - r_i is taken to the nearest periodic image on periodic axes
+ * and the test is evaluated as dx*dx + dy*dy <= (2h_i)*(2h_i) with every
+ * product and sum rounded separately (bit-reproducible).
+ *
+ *   x, y, h   float64[n] positions (inside the box) and stencil scales.
+ *   row_ptr   int32[n+1] output.
+ *   col       int32[capacity] output, or NULL to query the size.
+ *   nnz_out   host: receives the number of CSR entries.
+ *
+ * Synchronises the stream. Returns LABFM_ERR_CAPACITY (with *nnz_out set
+ * and row_ptr filled) when col is NULL or capacity < nnz. Returns
+ * LABFM_ERR_ARG when a periodic axis is shorter than 4 max(h) (the nearest
+ * image would not be unique) or n <= 0. Temporary device memory is
+ * allocated and freed inside the call.
+ */
+int labfm_build_neighbours(const double* x, const double* y, const double* h, int32_t n,
+                           labfm_box box, int32_t* row_ptr, int32_t* col, int64_t capacity,
+                           int64_t* nnz_out, void* stream);
+
+/*
+ * Weight construction (sections "LABFM" and "New ABFs"; eqs. disc_form,
+ * lsys, w_abf, hermite; filter calibration of section "Spatial filtering").
+ * For each node i of order m_i (1..10), with n = (m^2+3m)/2 moments:
+ *   X~_ji^q = (x_ji/h)^a (y_ji/h)^b / (a! b!)           scaled monomials
+ *   W_ji^q  = psi(|r_ji|/h) He_a(x_ji/h) He_b(y_ji/h)  Hermite ABFs
+ *             (He = probabilists' Hermite, equal to the paper's
+ *              H_a(z/sqrt2)/sqrt(2^a)); psi = Wendland C2,
+ *             psi(q) = (1-q/2)^4 (1+2q) for q < 2
+ *   M~_i = sum_j X~_ji (outer) W_ji,  M~_i Psi^d = C~^d  (LU, partial pivoting)
+ *   w^d_ji = W_ji . Psi^d
+ * for the six operators of labfm_op, then
+ *   F_0,i = sum_j [1 - cos(k x_ji) cos(k y_ji)] w^hyp_ji, k = 2 pi / (3 s_i),
+ *   kappa_i = 2 / (3 F_0,i).
+ *
+ *   x, y, h, s  float64[n]; s = local node spacing (filter calibration).
+ *   order_m     int8[n], each in 1..10.
+ *   row_ptr, col, nnz  CSR from labfm_build_neighbours.
+ *   w       float64[6*nnz] output.
+ *   w32     float32[6*nnz] output copy, or NULL.
+ *   kappa   float64[n] output.
+ *   rowsum  float64[6*n] output sum_j w^d_ji, or NULL.
+ *   status  int8[n] output, LABFM_NODE_* per node.
+ *
+ * Numerical failures and out-of-range orders are reported per node in
+ * status (the call still returns LABFM_OK); such nodes get zero weights and
+ * kappa = 0 except for LABFM_NODE_FEW_NEIGHBOURS, whose weights are those of
+ * the (rank-deficient) solve when it completes.
+ */
+int labfm_build_weights(const double* x, const double* y, const double* h, const double* s,
+                        const int8_t* order_m, int32_t n, labfm_box box,
+                        const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                        double* w, float* w32, double* kappa, double* rowsum,
+                        int8_t* status, void* stream);
+
+/*
+ * Operator application, eq. general_do: for each selected operator d (bit d
+ * of op_mask, labfm_op order) out_k[i] = sum_j (phi_j - phi_i) w^d_ji, where
+ * k counts the selected operators in increasing d.
+ *
+ *   ops     operators (w for LABFM_F64, w32 for LABFM_F32_COMP).
+ *   phi     float64[n] field.
+ *   out     float64[popcount(op_mask) * n] output.
+ */
+int labfm_apply_operators(const labfm_operators* ops, uint32_t op_mask, const double* phi,
+                          double* out, labfm_prec prec, void* stream);
+
+/*
+ * Time step, eq. dt: dt = min over nodes of min(1.0 s_i/(|u_i| + c),
+ * 0.4 s_i^2 rho_i / mu), rho = exp(ln rho).
+ *
+ *   q       float64[3n] state [ln rho | u | v].
+ *   s       float64[n] node spacing.
+ *   dt_out  host: receives dt. Synchronises the stream.
+ */
+int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
+                    double* dt_out, void* stream);
+
+/*
+ * Right-hand side of the isothermal Navier-Stokes equations (eq. icns) in
+ * (ln rho, u, v), with the derivatives taken by the LABFM operators:
+ *   R_l = -(u l_x + v l_y) - (u_x + v_y)
+ *   R_u = -(u u_x + v u_y) - c2 l_x + (mu/rho)(4/3 u_xx + u_yy + 1/3 v_xy) + gx
+ *   R_v = -(u v_x + v v_y) - c2 l_y + (mu/rho)(4/3 v_yy + v_xx + 1/3 u_xy) + gy
+ * with l = ln rho and u_yy = L(u) - u_xx. This is the stage kernel of
+ * labfm_rk_step run without the update.
+ *
+ *   q    float64[3n] state [ln rho | u | v].
+ *   prm  c2, mu, gx, gy are used.
+ *   out  float64[3n] output [R_l | R_u | R_v]; must not alias q.
+ */
+int labfm_ns_rhs(const double* q, const labfm_operators* ops, const labfm_rk_params* prm,
+                 double* out, labfm_prec prec, void* stream);
+
+/* Bytes of device workspace labfm_rk_step needs for n nodes. */
+size_t labfm_rk_workspace_bytes(int32_t n);
+
+/*
+ * n_steps steps of the four-stage, third-order, low-storage Runge-Kutta
+ * scheme RK3(2)4[2R+]C (Kennedy, Carpenter & Lewis 2000) applied to the
+ * isothermal Navier-Stokes equations in (ln rho, u, v) (eq. icns, with
+ * p = c2 rho so that grad(p)/rho = c2 grad(ln rho)), each step followed by
+ * the filter phi <- phi + kappa_i L^hyp_i(phi) on ln rho, u and v when
+ * prm->filter is set.
+ *
+ *   q          float64[3n] state [ln rho | u | v], updated in place.
+ *   ops        operators (w and kappa for LABFM_F64; w32 and kappa for
+ *              LABFM_F32_COMP; the state stays float64 in both).
+ *   workspace  device buffer of labfm_rk_workspace_bytes(n) bytes.
+ *   use_graph  1: capture one step as a HIP graph and replay it.
+ *   timing     host, optional: per-kernel event timings (synchronises).
+ */
+int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_rk_params* prm,
+                  int32_t n_steps, labfm_prec prec, int32_t use_graph, void* workspace,
+                  size_t workspace_bytes, labfm_timing* timing, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LABFM_H */

@@ -458,3 +458,26 @@ def rk_run(lnrho, u, v, W: dict, prm, dt: float, n_steps: int, filt: bool = True
     rhs = lambda l_, u_, v_: ns_rhs(l_, u_, v_, W, prm)  # noqa: E731
     post = (lambda q: filter_fields(q, W)) if filt else None
     return rk_integrate((lnrho, u, v), rhs, dt, n_steps, post)
+
+
+def ns_rhs_at(lnrho, u, v, x, y, h, s, m, row_ptr, col, box, prm, nodes) -> np.ndarray:
+    """Right-hand side of eq. icns at the listed nodes only, each from its own
+    weights (the derivatives at a node need only that node's stencil).
+    Returns (3, len(nodes))."""
+    m = np.broadcast_to(np.asarray(m), (x.size,))
+    out = np.empty((3, len(nodes)))
+    for k, i in enumerate(nodes):
+        dx, dy = stencil_offsets(x, y, box, row_ptr, col, i)
+        w = node_weights(dx, dy, float(h[i]), float(s[i]), int(m[i]))["w"]
+        c = col[row_ptr[i]:row_ptr[i + 1]]
+        dl, du, dv = lnrho[c] - lnrho[i], u[c] - u[i], v[c] - v[i]
+        lx, ly = np.sum(dl * w[OP_X]), np.sum(dl * w[OP_Y])
+        ux, uy, uL, uxx, uxy = (np.sum(du * w[d]) for d in (OP_X, OP_Y, OP_L, OP_XX, OP_XY))
+        vx, vy, vL, vxx, vxy = (np.sum(dv * w[d]) for d in (OP_X, OP_Y, OP_L, OP_XX, OP_XY))
+        nu = prm.mu / math.exp(lnrho[i])
+        out[0, k] = -(u[i] * lx + v[i] * ly) - (ux + vy)
+        out[1, k] = (-(u[i] * ux + v[i] * uy) - prm.c2 * lx
+                     + nu * (4.0 / 3.0 * uxx + (uL - uxx) + 1.0 / 3.0 * vxy) + prm.gx)
+        out[2, k] = (-(u[i] * vx + v[i] * vy) - prm.c2 * ly
+                     + nu * (4.0 / 3.0 * (vL - vxx) + vxx + 1.0 / 3.0 * uxy) + prm.gy)
+    return out

@@ -1,0 +1,331 @@
+// Stencil search: N_i = { j != i : |r_ji| <= 2 h_i } (stencil definition of
+// the paper's LABFM section), as CSR with ascending j per row.
+//
+// Nodes are binned into a uniform cell grid whose cells are at least
+// 2 max(h) wide (a stable counting sort: count, scan, scatter, per-cell
+// ordering), so every neighbour of a node lies in the 3x3 block of cells
+// around it. A count pass sizes each row, a scan turns counts into row
+// offsets, and a fill pass walks the candidate cells as a k-way merge of
+// their (ascending) node lists so that each row comes out sorted without a
+// separate sort. The distance test rounds every product and sum separately
+// (no fused multiply-add), so the lists are reproducible bit for bit by any
+// IEEE-754 double implementation of the same test.
+#include <climits>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace labfm {
+namespace {
+
+struct Grid {
+  int ncx, ncy;
+  double wx, wy;  // cell widths
+  double Lx, Ly;
+  int px, py;     // periodic flags
+};
+
+__device__ __forceinline__ int cell_coord(double p, double w, int nc) {
+  int c = static_cast<int>(floor(p / w));
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// Candidate cell coordinates along one axis (at most 3, all distinct).
+__device__ __forceinline__ int axis_candidates(int c, int nc, int periodic, int* out) {
+  int k = 0;
+  if (periodic) {
+    if (nc >= 3) {
+      out[k++] = (c + nc - 1) % nc;
+      out[k++] = c;
+      out[k++] = (c + 1) % nc;
+    } else {
+      for (int a = 0; a < nc; ++a) out[k++] = a;
+    }
+  } else {
+    for (int a = c - 1; a <= c + 1; ++a)
+      if (a >= 0 && a < nc) out[k++] = a;
+  }
+  return k;
+}
+
+// |r_ji| <= 2 h_i with separately rounded products and sum.
+__device__ __forceinline__ bool within(double xi, double yi, double xj, double yj, double r2,
+                                       const Grid& g) {
+  const double dx = wrap_axis(xj - xi, g.Lx, g.px);
+  const double dy = wrap_axis(yj - yi, g.Ly, g.py);
+  const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+  return d2 <= r2;
+}
+
+__global__ void max_reduce_kernel(const double* __restrict__ v, int n, double* out) {
+  __shared__ double sh[1024];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void bin_count_kernel(const double* __restrict__ x, const double* __restrict__ y, int n,
+                                 Grid g, int* __restrict__ cell_of, int* __restrict__ cell_count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cx = cell_coord(x[i], g.wx, g.ncx);
+  const int cy = cell_coord(y[i], g.wy, g.ncy);
+  const int c = cy * g.ncx + cx;
+  cell_of[i] = c;
+  atomicAdd(&cell_count[c], 1);
+}
+
+// Exclusive scan of int32 counts into int32 offsets (out has n+1 entries),
+// one block walking the array in tiles; the running total is kept in int64
+// and reported through total (so overflow of int32 can be detected).
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads)
+scan_kernel(const int* __restrict__ in, int* __restrict__ out, int n, long long* total) {
+  __shared__ long long sh[kScanThreads];
+  long long carry = 0;
+  for (int base = 0; base < n; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    const long long v = (i < n) ? static_cast<long long>(in[i]) : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the tile
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      long long t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const long long incl = carry + sh[threadIdx.x];
+    if (i < n) out[i] = static_cast<int>(incl - v);
+    carry += sh[kScanThreads - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[n] = static_cast<int>(carry);
+    *total = carry;
+  }
+}
+
+__global__ void bin_scatter_kernel(const int* __restrict__ cell_of, int n,
+                                   const int* __restrict__ cell_start, int* __restrict__ cursor,
+                                   int* __restrict__ cell_nodes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int slot = atomicAdd(&cursor[c], 1);
+  cell_nodes[cell_start[c] + slot] = i;
+}
+
+// Orders each cell's node list ascending (insertion sort: cells hold a few
+// tens of nodes), which makes the binning a stable sort.
+__global__ void cell_sort_kernel(const int* __restrict__ cell_start, int ncell,
+                                 int* __restrict__ cell_nodes) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = cell_start[c], e = cell_start[c + 1];
+  for (int k = b + 1; k < e; ++k) {
+    const int v = cell_nodes[k];
+    int p = k - 1;
+    while (p >= b && cell_nodes[p] > v) {
+      cell_nodes[p + 1] = cell_nodes[p];
+      --p;
+    }
+    cell_nodes[p + 1] = v;
+  }
+}
+
+struct Candidates {
+  int cells[9];
+  int count;
+};
+
+__device__ __forceinline__ Candidates candidate_cells(int cell, const Grid& g) {
+  int xs[3], ys[3];
+  const int cx = cell % g.ncx, cy = cell / g.ncx;
+  const int nx = axis_candidates(cx, g.ncx, g.px, xs);
+  const int ny = axis_candidates(cy, g.ncy, g.py, ys);
+  Candidates c;
+  c.count = 0;
+  for (int b = 0; b < ny; ++b)
+    for (int a = 0; a < nx; ++a) c.cells[c.count++] = ys[b] * g.ncx + xs[a];
+  return c;
+}
+
+__global__ void count_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ h, int n, Grid g,
+                             const int* __restrict__ cell_of, const int* __restrict__ cell_start,
+                             const int* __restrict__ cell_nodes, int* __restrict__ counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  const double r = 2.0 * h[i];
+  const double r2 = __dmul_rn(r, r);
+  const Candidates cand = candidate_cells(cell_of[i], g);
+  int cnt = 0;
+  for (int c = 0; c < cand.count; ++c) {
+    const int b = cell_start[cand.cells[c]], e = cell_start[cand.cells[c] + 1];
+    for (int k = b; k < e; ++k) {
+      const int j = cell_nodes[k];
+      if (j != i && within(xi, yi, x[j], y[j], r2, g)) ++cnt;
+    }
+  }
+  counts[i] = cnt;
+}
+
+__global__ void fill_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ h, int n, Grid g,
+                            const int* __restrict__ cell_of, const int* __restrict__ cell_start,
+                            const int* __restrict__ cell_nodes, const int* __restrict__ row_ptr,
+                            int* __restrict__ col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  const double r = 2.0 * h[i];
+  const double r2 = __dmul_rn(r, r);
+  const Candidates cand = candidate_cells(cell_of[i], g);
+  int cur[9], end[9], head[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    if (c < cand.count) {
+      cur[c] = cell_start[cand.cells[c]];
+      end[c] = cell_start[cand.cells[c] + 1];
+    } else {
+      cur[c] = 0;
+      end[c] = 0;
+    }
+    head[c] = (cur[c] < end[c]) ? cell_nodes[cur[c]] : INT_MAX;
+  }
+  int out = row_ptr[i];
+  const int stop = row_ptr[i + 1];
+  while (true) {
+    // smallest head among the candidate cells (cells are disjoint)
+    int best = 0;
+#pragma unroll
+    for (int c = 1; c < 9; ++c)
+      if (head[c] < head[best]) best = c;
+    const int j = head[best];
+    if (j == INT_MAX) break;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      if (c == best) {
+        ++cur[c];
+        head[c] = (cur[c] < end[c]) ? cell_nodes[cur[c]] : INT_MAX;
+      }
+    }
+    if (j != i && within(xi, yi, x[j], y[j], r2, g)) {
+      if (out < stop) col[out] = j;
+      ++out;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace labfm
+
+using namespace labfm;
+
+extern "C" int labfm_build_neighbours(const double* x, const double* y, const double* h,
+                                      int32_t n, labfm_box box, int32_t* row_ptr, int32_t* col,
+                                      int64_t capacity, int64_t* nnz_out, void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(n > 0, "build_neighbours: n must be positive (got %d)", n);
+  LABFM_REQUIRE(x && y && h && row_ptr && nnz_out, "build_neighbours: null pointer argument");
+  LABFM_REQUIRE(box.Lx > 0.0 && box.Ly > 0.0, "build_neighbours: box sides must be positive");
+  hipStream_t st = as_stream(stream_);
+
+  // Temporary device memory, released on every exit path below.
+  struct Temp {
+    void* p = nullptr;
+    ~Temp() {
+      if (p) (void)hipFree(p);
+    }
+  };
+  Temp t_small;
+  LABFM_HIP(hipMalloc(&t_small.p, 64));
+  double* d_hmax = static_cast<double*>(t_small.p);
+  long long* d_total = reinterpret_cast<long long*>(static_cast<char*>(t_small.p) + 16);
+
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(1024), 0, st, h, n, d_hmax);
+  LABFM_LAUNCHED();
+  double hmax = 0.0;
+  LABFM_HIP(hipMemcpyAsync(&hmax, d_hmax, sizeof(double), hipMemcpyDeviceToHost, st));
+  LABFM_HIP(hipStreamSynchronize(st));
+  LABFM_REQUIRE(std::isfinite(hmax) && hmax > 0.0, "build_neighbours: max(h) must be positive");
+  if (box.periodic_x)
+    LABFM_REQUIRE(4.0 * hmax < box.Lx, "build_neighbours: periodic Lx must exceed 4 max(h)");
+  if (box.periodic_y)
+    LABFM_REQUIRE(4.0 * hmax < box.Ly, "build_neighbours: periodic Ly must exceed 4 max(h)");
+
+  // Cells strictly wider than the largest stencil diameter.
+  const double reach = 2.0 * hmax * (1.0 + 1e-9);
+  Grid g;
+  g.ncx = static_cast<int>(std::fmax(1.0, std::floor(box.Lx / reach)));
+  g.ncy = static_cast<int>(std::fmax(1.0, std::floor(box.Ly / reach)));
+  // keep the cell table modest for very small stencils
+  while (static_cast<long long>(g.ncx) * g.ncy > 4LL * n + 64) {
+    g.ncx = (g.ncx + 1) / 2;
+    g.ncy = (g.ncy + 1) / 2;
+  }
+  g.wx = box.Lx / g.ncx;
+  g.wy = box.Ly / g.ncy;
+  g.Lx = box.Lx;
+  g.Ly = box.Ly;
+  g.px = box.periodic_x ? 1 : 0;
+  g.py = box.periodic_y ? 1 : 0;
+  const int ncell = g.ncx * g.ncy;
+
+  Temp t_big;
+  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 3 + 2 * (ncell + 1));
+  LABFM_HIP(hipMalloc(&t_big.p, bytes));
+  int* cell_of = static_cast<int*>(t_big.p);
+  int* cell_nodes = cell_of + n;
+  int* counts = cell_nodes + n;
+  int* cell_count = counts + n;            // ncell + 1
+  int* cell_start = cell_count + ncell + 1;  // ncell + 1
+
+  const int T = 256;
+  LABFM_HIP(hipMemsetAsync(cell_count, 0, sizeof(int) * (ncell + 1), st));
+  hipLaunchKernelGGL(bin_count_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, n, g,
+                     cell_of, cell_count);
+  LABFM_LAUNCHED();
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, cell_count, cell_start,
+                     ncell, d_total);
+  LABFM_LAUNCHED();
+  LABFM_HIP(hipMemsetAsync(cell_count, 0, sizeof(int) * (ncell + 1), st));  // now cursors
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, cell_of, n,
+                     cell_start, cell_count, cell_nodes);
+  LABFM_LAUNCHED();
+  hipLaunchKernelGGL(cell_sort_kernel, dim3(blocks_for(ncell, T)), dim3(T), 0, st, cell_start,
+                     ncell, cell_nodes);
+  LABFM_LAUNCHED();
+  hipLaunchKernelGGL(count_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, h, n, g, cell_of,
+                     cell_start, cell_nodes, counts);
+  LABFM_LAUNCHED();
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, counts, row_ptr, n,
+                     d_total);
+  LABFM_LAUNCHED();
+  long long total = 0;
+  LABFM_HIP(hipMemcpyAsync(&total, d_total, sizeof(long long), hipMemcpyDeviceToHost, st));
+  LABFM_HIP(hipStreamSynchronize(st));
+  *nnz_out = total;
+  if (total > INT_MAX) {
+    set_error("build_neighbours: %lld entries exceed the int32 CSR index range", total);
+    return LABFM_ERR_UNSUPPORTED;
+  }
+  if (col == nullptr || capacity < total) {
+    set_error("build_neighbours: col capacity %lld < nnz %lld", (long long)capacity, total);
+    return LABFM_ERR_CAPACITY;
+  }
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, h, n, g, cell_of,
+                     cell_start, cell_nodes, row_ptr, col);
+  LABFM_LAUNCHED();
+  // the temporaries are freed on return; make sure the fill has consumed them
+  LABFM_HIP(hipStreamSynchronize(st));
+  return LABFM_OK;
+}

@@ -1,0 +1,627 @@
+// Operator application (eq. general_do), the fused Runge-Kutta stage of the
+// isothermal Navier-Stokes equations (eq. icns), the filter pass, the time
+// step (eq. dt) and the RK3(2)4[2R+]C time loop.
+//
+// Gather layout: G = 64 / LPN nodes per wavefront, LPN lanes per node. The
+// lanes of a node walk its CSR row with stride LPN, so each weight array is
+// read in contiguous LPN-wide runs and consecutive nodes (Morton order) read
+// consecutive rows; the field values phi_j are gathered through the cache.
+// Partial sums are combined with a butterfly over the LPN lanes. No atomics
+// touch floating-point data, so every result is bitwise reproducible.
+//
+// Precision policies:
+//   F64      float64 weights, differences and sums.
+//   F32Comp  float32 weights; phi_j - phi_i formed in float64 and rounded to
+//            float32; each product split exactly with an FMA (TwoProd) and
+//            summed with TwoSum, the error terms accumulated separately
+//            (Dot2 of Ogita, Rump & Oishi 2005), partial sums combined across
+//            lanes the same way, the final pair added in float64.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace labfm {
+namespace {
+
+// --------------------------------------------------------------------------
+// precision policies
+// --------------------------------------------------------------------------
+
+struct F64 {
+  using W = double;
+  struct Acc {
+    double s;
+    __device__ __forceinline__ void zero() { s = 0.0; }
+    __device__ __forceinline__ void add(double w, double d) { s = fma(w, d, s); }
+    template <int width>
+    __device__ __forceinline__ double reduce() {
+      return group_sum<width>(s);
+    }
+  };
+  using D = double;
+  __device__ __forceinline__ static D diff(double pj, double pi) { return pj - pi; }
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+struct F32Comp {
+  using W = float;
+  struct Acc {
+    float s, c;
+    __device__ __forceinline__ void zero() {
+      s = 0.0f;
+      c = 0.0f;
+    }
+    __device__ __forceinline__ void add(float w, float d) {
+      const float p = w * d;
+      const float ep = fmaf(w, d, -p);  // exact: w*d = p + ep
+      float t, es;
+      two_sum(s, p, t, es);
+      s = t;
+      c += es + ep;
+    }
+    template <int width>
+    __device__ __forceinline__ double reduce() {
+      float hs = s, hc = c;
+#pragma unroll
+      for (int off = width / 2; off > 0; off >>= 1) {
+        const float os = __shfl_xor(hs, off, width);
+        const float oc = __shfl_xor(hc, off, width);
+        float t, e;
+        two_sum(hs, os, t, e);
+        hs = t;
+        hc = hc + oc + e;
+      }
+      return static_cast<double>(hs) + static_cast<double>(hc);
+    }
+  };
+  using D = float;
+  __device__ __forceinline__ static D diff(double pj, double pi) {
+    return static_cast<float>(pj - pi);
+  }
+};
+
+// --------------------------------------------------------------------------
+// operator application
+// --------------------------------------------------------------------------
+
+template <int LPN, class P>
+__global__ void __launch_bounds__(256)
+apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
+             const typename P::W* __restrict__ w, long long nnz, unsigned mask,
+             const double* __restrict__ phi, double* __restrict__ out, int n) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = gid / LPN;
+  const int sub = gid % LPN;
+  if (node >= n) return;  // whole LPN groups exit together
+  const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+  const double pi = phi[node];
+  typename P::Acc acc[LABFM_NUM_OPS];
+#pragma unroll
+  for (int d = 0; d < LABFM_NUM_OPS; ++d) acc[d].zero();
+  for (int e = e0 + sub; e < e1; e += LPN) {
+    const typename P::D dj = P::diff(phi[col[e]], pi);
+#pragma unroll
+    for (int d = 0; d < LABFM_NUM_OPS; ++d)
+      if (mask & (1u << d)) acc[d].add(w[d * nnz + e], dj);
+  }
+  int k = 0;
+#pragma unroll
+  for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+    if (mask & (1u << d)) {
+      const double v = acc[d].template reduce<LPN>();
+      if (sub == 0) out[static_cast<long long>(k) * n + node] = v;
+      ++k;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// fused Runge-Kutta stage
+// --------------------------------------------------------------------------
+
+struct Flow {
+  double c2, mu, gx, gy;
+};
+
+// Stage of the two-register scheme. Y (gathered) holds the stage value, q the
+// solution. With F = R(Y):  Y' = q + dta F  (skipped when Yout is null),
+// q <- q + dtb F. qin and qout may be the same buffer; Y is never written.
+template <int LPN, class P>
+__global__ void __launch_bounds__(256)
+rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
+                const typename P::W* __restrict__ w, long long nnz, const double* Y,
+                const double* qin, double* qout, double* Yout, double dta, double dtb, Flow fl,
+                int n) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = gid / LPN;
+  const int sub = gid % LPN;
+  if (node >= n) return;
+  const double* Yl = Y;
+  const double* Yu = Y + n;
+  const double* Yv = Y + 2 * static_cast<long long>(n);
+  const double li = Yl[node], ui = Yu[node], vi = Yv[node];
+  const typename P::W* wx = w + 0 * nnz;
+  const typename P::W* wy = w + 1 * nnz;
+  const typename P::W* wL = w + 2 * nnz;
+  const typename P::W* wxx = w + 3 * nnz;
+  const typename P::W* wxy = w + 4 * nnz;
+  typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
+  lx.zero(); ly.zero();
+  ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
+  vx.zero(); vy.zero(); vL.zero(); vxx.zero(); vxy.zero();
+  const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+  for (int e = e0 + sub; e < e1; e += LPN) {
+    const int j = col[e];
+    const typename P::D dl = P::diff(Yl[j], li);
+    const typename P::D du = P::diff(Yu[j], ui);
+    const typename P::D dv = P::diff(Yv[j], vi);
+    const typename P::W a = wx[e], b = wy[e], c = wL[e], d = wxx[e], f = wxy[e];
+    lx.add(a, dl);
+    ly.add(b, dl);
+    ux.add(a, du);
+    uy.add(b, du);
+    uL.add(c, du);
+    uxx.add(d, du);
+    uxy.add(f, du);
+    vx.add(a, dv);
+    vy.add(b, dv);
+    vL.add(c, dv);
+    vxx.add(d, dv);
+    vxy.add(f, dv);
+  }
+  const double Lx = lx.template reduce<LPN>(), Ly = ly.template reduce<LPN>();
+  const double Ux = ux.template reduce<LPN>(), Uy = uy.template reduce<LPN>();
+  const double UL = uL.template reduce<LPN>(), Uxx = uxx.template reduce<LPN>();
+  const double Uxy = uxy.template reduce<LPN>();
+  const double Vx = vx.template reduce<LPN>(), Vy = vy.template reduce<LPN>();
+  const double VL = vL.template reduce<LPN>(), Vxx = vxx.template reduce<LPN>();
+  const double Vxy = vxy.template reduce<LPN>();
+  if (sub != 0) return;
+  // right-hand side of eq. icns in (ln rho, u, v); 4/3 u_xx + u_yy = L u + u_xx/3
+  // and 4/3 v_yy + v_xx = L v + v_yy/3 with v_yy = L v - v_xx
+  const double nu = fl.mu / exp(li);
+  const double third = 1.0 / 3.0;
+  const double rl = -(ui * Lx + vi * Ly) - (Ux + Vy);
+  const double ru = -(ui * Ux + vi * Uy) - fl.c2 * Lx + nu * (UL + third * (Uxx + Vxy)) + fl.gx;
+  const double rv =
+      -(ui * Vx + vi * Vy) - fl.c2 * Ly + nu * (VL + third * ((VL - Vxx) + Uxy)) + fl.gy;
+  const long long n2 = 2 * static_cast<long long>(n);
+  // qin == nullptr evaluates the right-hand side alone (q taken as zero)
+  const double ql = qin ? qin[node] : 0.0;
+  const double qu = qin ? qin[n + node] : 0.0;
+  const double qv = qin ? qin[n2 + node] : 0.0;
+  if (Yout) {
+    Yout[node] = ql + dta * rl;
+    Yout[n + node] = qu + dta * ru;
+    Yout[n2 + node] = qv + dta * rv;
+  }
+  qout[node] = ql + dtb * rl;
+  qout[n + node] = qu + dtb * ru;
+  qout[n2 + node] = qv + dtb * rv;
+}
+
+// --------------------------------------------------------------------------
+// filter: phi <- phi + kappa_i L^hyp_i(phi) for the three fields
+// --------------------------------------------------------------------------
+
+template <int LPN, class P>
+__global__ void __launch_bounds__(256)
+filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
+              const typename P::W* __restrict__ whyp, const double* __restrict__ kappa,
+              const double* __restrict__ in, double* __restrict__ out, int n) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = gid / LPN;
+  const int sub = gid % LPN;
+  if (node >= n) return;
+  const long long n2 = 2 * static_cast<long long>(n);
+  const double li = in[node], ui = in[n + node], vi = in[n2 + node];
+  typename P::Acc al, au, av;
+  al.zero();
+  au.zero();
+  av.zero();
+  const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+  for (int e = e0 + sub; e < e1; e += LPN) {
+    const int j = col[e];
+    const typename P::W a = whyp[e];
+    al.add(a, P::diff(in[j], li));
+    au.add(a, P::diff(in[n + j], ui));
+    av.add(a, P::diff(in[n2 + j], vi));
+  }
+  const double sl = al.template reduce<LPN>();
+  const double su = au.template reduce<LPN>();
+  const double sv = av.template reduce<LPN>();
+  if (sub != 0) return;
+  const double k = kappa[node];
+  out[node] = li + k * sl;
+  out[n + node] = ui + k * su;
+  out[n2 + node] = vi + k * sv;
+}
+
+// --------------------------------------------------------------------------
+// time step and finiteness check
+// --------------------------------------------------------------------------
+
+constexpr int kRedThreads = 256;
+
+__global__ void __launch_bounds__(kRedThreads)
+dt_partial_kernel(const double* __restrict__ q, const double* __restrict__ s, int n, double c,
+                  double mu, double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  double m = INFINITY;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double u = q[n + i], v = q[2 * static_cast<long long>(n) + i];
+    const double speed = sqrt(u * u + v * v);
+    const double conv = 1.0 * s[i] / (speed + c);
+    const double visc = 0.4 * s[i] * s[i] * exp(q[i]) / mu;
+    m = fmin(m, fmin(conv, visc));
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+min_final_kernel(const double* __restrict__ partial, int m, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double v = INFINITY;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) v = fmin(v, partial[i]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ q, long long len, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < len;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    bad |= !isfinite(q[i]);
+  if (__any(bad) && (threadIdx.x % 64) == 0) atomicOr(flag, 1);
+}
+
+// --------------------------------------------------------------------------
+// launch helpers
+// --------------------------------------------------------------------------
+
+constexpr int kThreads = 256;
+
+// Lanes per node used by the gather kernels, chosen from the mean row length.
+int lanes_per_node(int n, long long nnz) {
+  const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
+  if (k > 48.0) return 16;
+  if (k > 12.0) return 8;
+  return 4;
+}
+
+template <class P>
+hipError_t launch_apply(int lpn, const labfm_operators* o, const typename P::W* w, unsigned mask,
+                        const double* phi, double* out, hipStream_t st) {
+  const int n = o->n;
+  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
+#define LABFM_APPLY_CASE(L)                                                                    \
+  case L:                                                                                      \
+    hipLaunchKernelGGL((apply_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st, o->row_ptr, \
+                       o->col, w, static_cast<long long>(o->nnz), mask, phi, out, n);          \
+    break;
+  switch (lpn) {
+    LABFM_APPLY_CASE(4)
+    LABFM_APPLY_CASE(8)
+    LABFM_APPLY_CASE(16)
+    LABFM_APPLY_CASE(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LABFM_APPLY_CASE
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_stage(int lpn, const labfm_operators* o, const typename P::W* w,
+                        const double* Y, const double* qin, double* qout, double* Yout, double dta,
+                        double dtb, const Flow& fl, hipStream_t st) {
+  const int n = o->n;
+  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
+#define LABFM_STAGE_CASE(L)                                                                   \
+  case L:                                                                                     \
+    hipLaunchKernelGGL((rk_stage_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st,          \
+                       o->row_ptr, o->col, w, static_cast<long long>(o->nnz), Y, qin, qout, \
+                       Yout, dta, dtb, fl, n);                                                \
+    break;
+  switch (lpn) {
+    LABFM_STAGE_CASE(4)
+    LABFM_STAGE_CASE(8)
+    LABFM_STAGE_CASE(16)
+    LABFM_STAGE_CASE(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LABFM_STAGE_CASE
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_filter(int lpn, const labfm_operators* o, const typename P::W* w,
+                         const double* in, double* out, hipStream_t st) {
+  const int n = o->n;
+  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
+  const typename P::W* whyp = w + LABFM_OP_HYP * o->nnz;
+#define LABFM_FILTER_CASE(L)                                                                  \
+  case L:                                                                                     \
+    hipLaunchKernelGGL((filter_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st, o->row_ptr, \
+                       o->col, whyp, o->kappa, in, out, n);                                   \
+    break;
+  switch (lpn) {
+    LABFM_FILTER_CASE(4)
+    LABFM_FILTER_CASE(8)
+    LABFM_FILTER_CASE(16)
+    LABFM_FILTER_CASE(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef LABFM_FILTER_CASE
+  return hipGetLastError();
+}
+
+// RK3(2)4[2R+]C (Kennedy, Carpenter & Lewis 2000): sub-diagonal a_{i+1,i}
+// and weights b_i of the two-register form.
+constexpr double kA[3] = {11847461282814.0 / 36547543011857.0,
+                          3943225443063.0 / 7078155732230.0,
+                          -346793006927.0 / 4029903576067.0};
+constexpr double kB[4] = {1017324711453.0 / 9774461848756.0,
+                          8237718856693.0 / 13685301971492.0,
+                          57731312506979.0 / 19404895981398.0,
+                          -101169746363290.0 / 37734290219643.0};
+
+// Kernel sequence of one full step. Registers rotate between the caller's
+// state Q and workspace buffers Ya, Yb so that no launch writes a buffer it
+// gathers from and no copy is needed:
+//   stage 1: gather Q,  q in Q  -> q to Ya, Y to Yb
+//   stage 2: gather Yb, q in Ya -> q to Ya, Y to Q
+//   stage 3: gather Q,  q in Ya -> q to Ya, Y to Yb
+//   stage 4: gather Yb, q in Ya -> q to Ya
+//   filter:  gather Ya          -> Q        (or a copy Ya -> Q without filter)
+struct StepPlan {
+  const labfm_operators* ops;
+  const void* w;
+  labfm_prec prec;
+  int lpn;
+  Flow fl;
+  double dt;
+  int filter;
+  double* Q;
+  double* Ya;
+  double* Yb;
+};
+
+template <class P>
+hipError_t enqueue_step(const StepPlan& p, hipStream_t st, hipEvent_t* ev, int* nev) {
+  const auto* w = static_cast<const typename P::W*>(p.w);
+  const long long bytes = 3LL * p.ops->n * sizeof(double);
+  double* const Ys[4] = {p.Yb, p.Q, p.Yb, nullptr};
+  const double* const G[4] = {p.Q, p.Yb, p.Q, p.Yb};
+  const double* const Qin[4] = {p.Q, p.Ya, p.Ya, p.Ya};
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+    const double dta = (s < 3) ? p.dt * kA[s] : 0.0;
+    if (ev) e = hipEventRecord(ev[(*nev)++], st);
+    if (e == hipSuccess)
+      e = launch_stage<P>(p.lpn, p.ops, w, G[s], Qin[s], p.Ya, Ys[s], dta, p.dt * kB[s], p.fl,
+                          st);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[(*nev)++], st);
+  }
+  if (e != hipSuccess) return e;
+  if (p.filter) {
+    if (ev) e = hipEventRecord(ev[(*nev)++], st);
+    if (e == hipSuccess) e = launch_filter<P>(p.lpn, p.ops, w, p.Ya, p.Q, st);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[(*nev)++], st);
+  } else {
+    e = hipMemcpyAsync(p.Q, p.Ya, bytes, hipMemcpyDeviceToDevice, st);
+  }
+  return e;
+}
+
+hipError_t enqueue_step_any(const StepPlan& p, hipStream_t st, hipEvent_t* ev, int* nev) {
+  return p.prec == LABFM_F64 ? enqueue_step<F64>(p, st, ev, nev)
+                             : enqueue_step<F32Comp>(p, st, ev, nev);
+}
+
+int check_ops(const labfm_operators* o, labfm_prec prec, const char* who) {
+  LABFM_REQUIRE(o, "%s: null operators", who);
+  LABFM_REQUIRE(o->n > 0 && o->nnz >= 0 && o->row_ptr && (o->col || o->nnz == 0),
+                "%s: incomplete operator description", who);
+  LABFM_REQUIRE(prec == LABFM_F64 || prec == LABFM_F32_COMP, "%s: unknown precision %d", who,
+                (int)prec);
+  if (prec == LABFM_F64) LABFM_REQUIRE(o->w, "%s: float64 weights required", who);
+  if (prec == LABFM_F32_COMP) LABFM_REQUIRE(o->w32, "%s: float32 weights required", who);
+  return LABFM_OK;
+}
+
+}  // namespace
+}  // namespace labfm
+
+using namespace labfm;
+
+extern "C" int labfm_apply_operators(const labfm_operators* ops, uint32_t op_mask,
+                                     const double* phi, double* out, labfm_prec prec,
+                                     void* stream_) {
+  clear_error();
+  if (int r = check_ops(ops, prec, "apply_operators")) return r;
+  LABFM_REQUIRE(phi && out, "apply_operators: null field pointer");
+  LABFM_REQUIRE(op_mask != 0 && op_mask < (1u << LABFM_NUM_OPS),
+                "apply_operators: op_mask must select operators 0..5");
+  hipStream_t st = as_stream(stream_);
+  const int lpn = lanes_per_node(ops->n, ops->nnz);
+  hipError_t e = (prec == LABFM_F64)
+                     ? launch_apply<F64>(lpn, ops, ops->w, op_mask, phi, out, st)
+                     : launch_apply<F32Comp>(lpn, ops, ops->w32, op_mask, phi, out, st);
+  LABFM_HIP(e);
+  return LABFM_OK;
+}
+
+extern "C" int labfm_ns_rhs(const double* q, const labfm_operators* ops,
+                            const labfm_rk_params* prm, double* out, labfm_prec prec,
+                            void* stream_) {
+  clear_error();
+  if (int r = check_ops(ops, prec, "ns_rhs")) return r;
+  LABFM_REQUIRE(q && prm && out, "ns_rhs: null argument");
+  LABFM_REQUIRE(out != q, "ns_rhs: out must not alias q");
+  hipStream_t st = as_stream(stream_);
+  const int lpn = lanes_per_node(ops->n, ops->nnz);
+  const Flow fl{prm->c2, prm->mu, prm->gx, prm->gy};
+  hipError_t e = (prec == LABFM_F64)
+                     ? launch_stage<F64>(lpn, ops, ops->w, q, nullptr, out, nullptr, 0.0, 1.0, fl, st)
+                     : launch_stage<F32Comp>(lpn, ops, ops->w32, q, nullptr, out, nullptr, 0.0,
+                                             1.0, fl, st);
+  LABFM_HIP(e);
+  return LABFM_OK;
+}
+
+extern "C" int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
+                               double* dt_out, void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(n > 0 && q && s && dt_out, "time_step: bad arguments");
+  LABFM_REQUIRE(c2 > 0.0 && mu > 0.0, "time_step: c2 and mu must be positive");
+  hipStream_t st = as_stream(stream_);
+  const int nb = static_cast<int>(std::min<long long>(1024, blocks_for(n, kRedThreads)));
+  double* d = nullptr;
+  LABFM_HIP(hipMalloc(&d, sizeof(double) * (nb + 1)));
+  hipLaunchKernelGGL(dt_partial_kernel, dim3(nb), dim3(kRedThreads), 0, st, q, s, n, sqrt(c2),
+                     mu, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(min_final_kernel, dim3(1), dim3(kRedThreads), 0, st, d, nb, d + nb);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(dt_out, d + nb, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  LABFM_HIP(e);
+  return LABFM_OK;
+}
+
+extern "C" size_t labfm_rk_workspace_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  // two stage registers of 3n doubles, then an int flag (256-byte aligned)
+  return 2 * 3 * static_cast<size_t>(n) * sizeof(double) + 256;
+}
+
+extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_rk_params* prm,
+                             int32_t n_steps, labfm_prec prec, int32_t use_graph,
+                             void* workspace, size_t workspace_bytes, labfm_timing* timing,
+                             void* stream_) {
+  clear_error();
+  if (int r = check_ops(ops, prec, "rk_step")) return r;
+  LABFM_REQUIRE(q && prm, "rk_step: null state or parameters");
+  LABFM_REQUIRE(n_steps >= 0, "rk_step: n_steps must be >= 0");
+  LABFM_REQUIRE(prm->dt > 0.0 && std::isfinite(prm->dt), "rk_step: dt must be positive");
+  LABFM_REQUIRE(!prm->filter || ops->kappa, "rk_step: filter requires kappa");
+  const int n = ops->n;
+  LABFM_REQUIRE(workspace && workspace_bytes >= labfm_rk_workspace_bytes(n),
+                "rk_step: workspace of %zu bytes required", labfm_rk_workspace_bytes(n));
+  hipStream_t st = as_stream(stream_);
+  double* Ya = static_cast<double*>(workspace);
+  double* Yb = Ya + 3 * static_cast<size_t>(n);
+  int* flag = reinterpret_cast<int*>(Yb + 3 * static_cast<size_t>(n));
+
+  StepPlan plan;
+  plan.ops = ops;
+  plan.w = (prec == LABFM_F64) ? static_cast<const void*>(ops->w)
+                               : static_cast<const void*>(ops->w32);
+  plan.prec = prec;
+  plan.lpn = lanes_per_node(n, ops->nnz);
+  plan.fl = Flow{prm->c2, prm->mu, prm->gx, prm->gy};
+  plan.dt = prm->dt;
+  plan.filter = prm->filter;
+  plan.Q = q;
+  plan.Ya = Ya;
+  plan.Yb = Yb;
+
+  if (timing) {
+    // event-timed launches (no graph): 2 events per kernel launch
+    const int per_step = 2 * (4 + (prm->filter ? 1 : 0));
+    std::vector<hipEvent_t> ev(static_cast<size_t>(per_step) * n_steps);
+    for (auto& e : ev) LABFM_HIP(hipEventCreate(&e));
+    int nev = 0;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = enqueue_step_any(plan, st, ev.data(), &nev);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    double stage = 0.0, filt = 0.0;
+    long long ns = 0, nf = 0;
+    for (int k = 0; k < nev && e == hipSuccess; k += 2) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      const int pos = (k / 2) % (per_step / 2);
+      if (pos < 4) {
+        stage += ms;
+        ++ns;
+      } else {
+        filt += ms;
+        ++nf;
+      }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    LABFM_HIP(e);
+    timing->stage_ms = stage;
+    timing->filter_ms = filt;
+    timing->stage_launches = ns;
+    timing->filter_launches = nf;
+  } else if (use_graph && n_steps > 0) {
+    // capture one step on a private stream, replay it n_steps times
+    hipStream_t cs = nullptr;
+    LABFM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipEvent_t join = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(join, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, join, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t ce = enqueue_step_any(plan, cs, nullptr, nullptr);
+      e = hipStreamEndCapture(cs, &graph);
+      if (ce != hipSuccess) e = ce;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = hipGraphLaunch(exec, cs);
+    if (e == hipSuccess) e = hipEventRecord(join, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    // the graph and stream may only be released once the replays are done
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (join) (void)hipEventDestroy(join);
+    (void)hipStreamDestroy(cs);
+    LABFM_HIP(e);
+  } else {
+    for (int k = 0; k < n_steps; ++k) LABFM_HIP(enqueue_step_any(plan, st, nullptr, nullptr));
+  }
+
+  if (prm->check_finite) {
+    LABFM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const long long len = 3LL * n;
+    const unsigned nb = static_cast<unsigned>(std::min<long long>(2048, blocks_for(len, 256)));
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(nb), dim3(256), 0, st, q, len, flag);
+    LABFM_LAUNCHED();
+    int h_flag = 0;
+    LABFM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LABFM_HIP(hipStreamSynchronize(st));
+    if (h_flag) {
+      set_error("rk_step: non-finite value in the state after %d steps", n_steps);
+      return LABFM_ERR_NONFINITE;
+    }
+  }
+  return LABFM_OK;
+}

@@ -1,0 +1,456 @@
+// Weight construction (sections "LABFM" and "New ABFs" of the paper, eqs.
+// disc_form, lsys, w_abf and hermite; filter calibration of section "Spatial
+// filtering").
+//
+// One 64-lane wavefront builds one node:
+//   1. basis tables: for 16 neighbours at a time, four lanes per neighbour
+//      evaluate x^a/a!, y^b/b!, psi He_a(x), He_b(y) (scaled offsets, a,b <= m)
+//      into LDS;
+//   2. moment matrix M~ = sum_j X~_j (outer) W_j, n x n with n = (m^2+3m)/2,
+//      accumulated with FP64 MFMA (v_mfma_f64_16x16x4f64): the moment index
+//      is tiled by 16, the neighbour index is the MFMA's K dimension;
+//   3. LU factorisation with partial pivoting (largest magnitude, first index
+//      on ties) of [M~ | C~] in LDS, applied to the six right-hand sides;
+//   4. back substitution for Psi^d;
+//   5. per neighbour (one lane each), w^d_j = W_j . Psi^d for the six
+//      operators, the filter sum F_0 and the row sums, reduced across the
+//      wave.
+// Hermite ABFs use the probabilists' polynomials He_a(x/h), which equal the
+// paper's H_a(x/(h sqrt 2)) / sqrt(2^a).
+#include <cmath>
+
+#include "common.hpp"
+
+namespace labfm {
+namespace {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 16;  // neighbours per basis-table chunk
+
+// (a, b) exponents of moment index p (degree-major, decreasing power of x).
+__device__ __forceinline__ void exponents_of(int p, int& a, int& b) {
+  int d = 1;
+  while ((d + 1) * (d + 2) / 2 - 1 <= p) ++d;
+  b = p - (d * (d + 1) / 2 - 1);
+  a = d - b;
+}
+
+__device__ __forceinline__ int index_of(int a, int b) {
+  const int d = a + b;
+  return d * (d + 1) / 2 - 1 + b;
+}
+
+__device__ __forceinline__ double wendland_c2(double q) {
+  if (q >= 2.0) return 0.0;
+  const double t = 1.0 - 0.5 * q;
+  const double t2 = t * t;
+  return t2 * t2 * (1.0 + 2.0 * q);
+}
+
+template <int MMAX>
+struct Shape {
+  static constexpr int NMAX = moments_of(MMAX);
+  static constexpr int NB = (NMAX + 15) / 16;   // 16-wide MFMA tiles per side
+  static constexpr int LDA = NMAX + 6 + 1;       // row stride of [M | C] (odd)
+  static constexpr int TW = MMAX + 1;            // one basis table's length
+  static constexpr int TABLE = 4 * TW;           // four tables per neighbour
+  static constexpr int HW = 2 * TW + 1;          // per-lane Hermite row (odd)
+};
+
+template <int MMAX>
+__global__ void __launch_bounds__(64)
+build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                     const double* __restrict__ hh, const double* __restrict__ ss,
+                     const int8_t* __restrict__ order, int nnodes, labfm_box box,
+                     const int* __restrict__ row_ptr, const int* __restrict__ col, long long nnz,
+                     double* __restrict__ w, float* __restrict__ w32,
+                     double* __restrict__ kappa, double* __restrict__ rowsum,
+                     int8_t* __restrict__ status) {
+  using S = Shape<MMAX>;
+  __shared__ double A[S::NMAX * S::LDA];
+  __shared__ double T[kChunk * S::TABLE];
+  __shared__ double H[64 * S::HW];
+  __shared__ int s_flag;
+
+  const int i = blockIdx.x;
+  if (i >= nnodes) return;
+  const int lane = threadIdx.x;
+  const int m = order[i];
+  const int e0 = row_ptr[i];
+  const int K = row_ptr[i + 1] - e0;
+
+  if (m < 1 || m > MMAX) {
+    for (int k = lane; k < K; k += 64)
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        w[d * nnz + e0 + k] = 0.0;
+        if (w32) w32[d * nnz + e0 + k] = 0.0f;
+      }
+    if (lane == 0) {
+      kappa[i] = 0.0;
+      status[i] = LABFM_NODE_BAD_ORDER;
+      if (rowsum)
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+    }
+    return;
+  }
+  const int n = moments_of(m);
+  const double xi = x[i], yi = y[i], h = hh[i], s = ss[i];
+  const int px = box.periodic_x, py = box.periodic_y;
+
+  // ---- 1+2: basis tables and MFMA assembly of M~ -------------------------
+  int pa[S::NB], pb[S::NB];  // exponents of this lane's row/column in each tile
+#pragma unroll
+  for (int P = 0; P < S::NB; ++P) {
+    const int p = P * 16 + (lane & 15);
+    if (p < n) {
+      exponents_of(p, pa[P], pb[P]);
+    } else {
+      pa[P] = -1;
+      pb[P] = -1;
+    }
+  }
+  double4_t acc[S::NB][S::NB];
+#pragma unroll
+  for (int P = 0; P < S::NB; ++P)
+#pragma unroll
+    for (int Q = 0; Q < S::NB; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += kChunk) {
+    {
+      const int kk = lane >> 2, t = lane & 3;
+      const int k = k0 + kk;
+      double* tab = &T[kk * S::TABLE + t * S::TW];
+      if (k < K) {
+        const int j = col[e0 + k];
+        const double dx = wrap_axis(x[j] - xi, box.Lx, px);
+        const double dy = wrap_axis(y[j] - yi, box.Ly, py);
+        const double xs = dx / h, ys = dy / h;
+        const double z = (t == 0 || t == 2) ? xs : ys;
+        if (t < 2) {
+          // z^a / a!
+          double v = 1.0;
+          tab[0] = 1.0;
+#pragma unroll
+          for (int a = 1; a <= MMAX; ++a) {
+            v = v * z / static_cast<double>(a);
+            tab[a] = v;
+          }
+        } else {
+          // probabilists' Hermite He_a(z); the x table carries psi
+          const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+          double h0 = 1.0, h1 = z;
+          tab[0] = psi;
+          tab[1] = psi * z;
+#pragma unroll
+          for (int a = 1; a < MMAX; ++a) {
+            const double h2 = z * h1 - static_cast<double>(a) * h0;
+            h0 = h1;
+            h1 = h2;
+            tab[a + 1] = psi * h2;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a <= MMAX; ++a) tab[a] = 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kChunk / 4; ++ks) {
+      const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
+      double av[S::NB], bv[S::NB];
+#pragma unroll
+      for (int P = 0; P < S::NB; ++P) {
+        if (pa[P] >= 0) {
+          av[P] = tk[pa[P]] * tk[S::TW + pb[P]];
+          bv[P] = tk[2 * S::TW + pa[P]] * tk[3 * S::TW + pb[P]];
+        } else {
+          av[P] = 0.0;
+          bv[P] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int P = 0; P < S::NB; ++P)
+#pragma unroll
+        for (int Q = 0; Q < S::NB; ++Q)
+          acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
+#pragma unroll
+  for (int P = 0; P < S::NB; ++P)
+#pragma unroll
+    for (int Q = 0; Q < S::NB; ++Q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = P * 16 + (lane >> 4) + 4 * v;
+        const int c = Q * 16 + (lane & 15);
+        if (r < n && c < n) A[r * S::LDA + c] = acc[P][Q][v];
+      }
+  // right-hand sides C~^d = C^d h^-(a+b)
+  for (int r = lane; r < n; r += 64)
+#pragma unroll
+    for (int d = 0; d < LABFM_NUM_OPS; ++d) A[r * S::LDA + S::NMAX + d] = 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    const double h1 = 1.0 / h, h2 = 1.0 / (h * h);
+    const int C0 = S::NMAX;
+    A[0 * S::LDA + C0 + LABFM_OP_X] = h1;
+    A[1 * S::LDA + C0 + LABFM_OP_Y] = h1;
+    if (m >= 2) {
+      A[index_of(2, 0) * S::LDA + C0 + LABFM_OP_L] = h2;
+      A[index_of(0, 2) * S::LDA + C0 + LABFM_OP_L] = h2;
+      A[index_of(2, 0) * S::LDA + C0 + LABFM_OP_XX] = h2;
+      A[index_of(1, 1) * S::LDA + C0 + LABFM_OP_XY] = h2;
+    }
+    const int mp = (m % 2 == 0) ? m : m - 1;
+    if (mp >= 2) {
+      double hp = 1.0;
+      for (int k = 0; k < mp; ++k) hp *= h;
+      const int half = mp / 2;
+      double binom = 1.0;
+      for (int p = 0; p <= half; ++p) {
+        A[index_of(2 * p, mp - 2 * p) * S::LDA + C0 + LABFM_OP_HYP] = binom / hp;
+        binom = binom * static_cast<double>(half - p) / static_cast<double>(p + 1);
+      }
+    }
+    s_flag = 0;
+  }
+  __syncthreads();
+
+  // ---- 3: LU with partial pivoting on [M~ | C~] -----------------------------
+  // columns of the augmented matrix: 0..n-1 (M~) and NMAX..NMAX+5 (C~)
+  int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
+  bool singular = false;
+  for (int c = 0; c < n; ++c) {
+    // pivot: largest |A[r][c]|, r >= c, smallest r on ties
+    double best = -1.0;
+    int bi = n;
+    for (int r = c + lane; r < n; r += 64) {
+      const double v = fabs(A[r * S::LDA + c]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (!(best > 0.0)) {  // zero pivot (or a non-finite column)
+      singular = true;
+      break;
+    }
+    // swap rows c and bi over the columns still in play
+    if (bi != c) {
+      for (int jj = c + lane; jj < n; jj += 64) {
+        const double t0 = A[c * S::LDA + jj];
+        A[c * S::LDA + jj] = A[bi * S::LDA + jj];
+        A[bi * S::LDA + jj] = t0;
+      }
+      if (lane < LABFM_NUM_OPS) {
+        const int jj = S::NMAX + lane;
+        const double t0 = A[c * S::LDA + jj];
+        A[c * S::LDA + jj] = A[bi * S::LDA + jj];
+        A[bi * S::LDA + jj] = t0;
+      }
+    }
+    __syncthreads();
+    const double piv = A[c * S::LDA + c];
+    // multipliers l_r = A[r][c] / pivot, kept in column c
+    for (int r = c + 1 + lane; r < n; r += 64) A[r * S::LDA + c] = A[r * S::LDA + c] / piv;
+    __syncthreads();
+    // trailing update, one lane per column (M~ columns c+1..n-1 and the RHS)
+    const int width = (n - c - 1) + LABFM_NUM_OPS;
+    for (int t = lane; t < width; t += 64) {
+      const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
+      const double ucj = A[c * S::LDA + jj];
+      int r = c + 1;
+      for (; r + 3 < n; r += 4) {
+        const double l0 = A[r * S::LDA + c], l1 = A[(r + 1) * S::LDA + c];
+        const double l2 = A[(r + 2) * S::LDA + c], l3 = A[(r + 3) * S::LDA + c];
+        A[r * S::LDA + jj] -= l0 * ucj;
+        A[(r + 1) * S::LDA + jj] -= l1 * ucj;
+        A[(r + 2) * S::LDA + jj] -= l2 * ucj;
+        A[(r + 3) * S::LDA + jj] -= l3 * ucj;
+      }
+      for (; r < n; ++r) A[r * S::LDA + jj] -= A[r * S::LDA + c] * ucj;
+    }
+    __syncthreads();
+  }
+
+  if (singular) {
+    for (int k = lane; k < K; k += 64)
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        w[d * nnz + e0 + k] = 0.0;
+        if (w32) w32[d * nnz + e0 + k] = 0.0f;
+      }
+    if (lane == 0) {
+      kappa[i] = 0.0;
+      status[i] = LABFM_NODE_SINGULAR;
+      if (rowsum)
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+    }
+    return;
+  }
+
+  // ---- 4: back substitution U Psi = C' (in place in the RHS columns) ------
+  for (int c = n - 1; c >= 0; --c) {
+    if (lane < LABFM_NUM_OPS) {
+      const int jj = S::NMAX + lane;
+      A[c * S::LDA + jj] = A[c * S::LDA + jj] / A[c * S::LDA + c];
+    }
+    __syncthreads();
+    for (int t = lane; t < c * LABFM_NUM_OPS; t += 64) {
+      const int r = t / LABFM_NUM_OPS, d = t - r * LABFM_NUM_OPS;
+      const int jj = S::NMAX + d;
+      A[r * S::LDA + jj] -= A[r * S::LDA + c] * A[c * S::LDA + jj];
+    }
+    __syncthreads();
+  }
+
+  // ---- 5: weights, filter calibration, row sums ----------------------------
+  // one lane per neighbour; its Hermite values go to its own LDS row so the
+  // loop over moments can index them at run time
+  double* hx = &H[lane * S::HW];
+  double* hy = hx + (MMAX + 1);
+  const double kf = 2.0 * M_PI / (3.0 * s);
+  double f0 = 0.0;
+  double rs[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    if (k < K) {
+      const int j = col[e0 + k];
+      const double dx = wrap_axis(x[j] - xi, box.Lx, px);
+      const double dy = wrap_axis(y[j] - yi, box.Ly, py);
+      const double xs = dx / h, ys = dy / h;
+      const double psi = wendland_c2(sqrt(xs * xs + ys * ys));
+      {
+        double a0 = 1.0, a1 = xs, b0 = 1.0, b1 = ys;
+        hx[0] = 1.0;
+        hy[0] = 1.0;
+        hx[1] = xs;
+        hy[1] = ys;
+        for (int a = 1; a < m; ++a) {
+          const double a2 = xs * a1 - static_cast<double>(a) * a0;
+          const double b2 = ys * b1 - static_cast<double>(a) * b0;
+          a0 = a1;
+          a1 = a2;
+          b0 = b1;
+          b1 = b2;
+          hx[a + 1] = a2;
+          hy[a + 1] = b2;
+        }
+      }
+      double wd[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int p = 0;
+      for (int deg = 1; deg <= m; ++deg) {
+        for (int b = 0; b <= deg; ++b, ++p) {
+          const double Wq = hx[deg - b] * hy[b];
+          const double* psi_row = &A[p * S::LDA + S::NMAX];
+#pragma unroll
+          for (int d = 0; d < LABFM_NUM_OPS; ++d) wd[d] += Wq * psi_row[d];
+        }
+      }
+      const long long e = e0 + k;
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        const double v = psi * wd[d];
+        w[d * nnz + e] = v;
+        if (w32) w32[d * nnz + e] = static_cast<float>(v);
+        rs[d] += v;
+      }
+      const double phi = 1.0 - cos(kf * dx) * cos(kf * dy);
+      f0 += phi * (psi * wd[LABFM_OP_HYP]);
+    }
+  }
+  f0 = group_sum<64>(f0);
+#pragma unroll
+  for (int d = 0; d < LABFM_NUM_OPS; ++d) rs[d] = group_sum<64>(rs[d]);
+  if (lane == 0) {
+    const bool bad = !isfinite(f0) || f0 == 0.0;
+    kappa[i] = bad ? 0.0 : 2.0 / (3.0 * f0);
+    if (st == LABFM_NODE_OK && bad) st = LABFM_NODE_BAD_FILTER;
+    status[i] = static_cast<int8_t>(st);
+    if (rowsum)
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = rs[d];
+  }
+}
+
+__global__ void max_order_kernel(const int8_t* __restrict__ m, int n, int* out) {
+  __shared__ int sh[256];
+  int v = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int o = m[i];
+    v = o > v ? o : v;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+template <int MMAX>
+hipError_t launch_build(const double* x, const double* y, const double* h, const double* s,
+                        const int8_t* m, int n, labfm_box box, const int* row_ptr,
+                        const int* col, long long nnz, double* w, float* w32, double* kappa,
+                        double* rowsum, int8_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(build_weights_kernel<MMAX>, dim3(n), dim3(64), 0, st, x, y, h, s, m, n, box,
+                     row_ptr, col, nnz, w, w32, kappa, rowsum, status);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace labfm
+
+using namespace labfm;
+
+extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
+                                   const double* s, const int8_t* order_m, int32_t n,
+                                   labfm_box box, const int32_t* row_ptr, const int32_t* col,
+                                   int64_t nnz, double* w, float* w32, double* kappa,
+                                   double* rowsum, int8_t* status, void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(n > 0, "build_weights: n must be positive (got %d)", n);
+  LABFM_REQUIRE(x && y && h && s && order_m && row_ptr && w && kappa && status,
+                "build_weights: null pointer argument");
+  LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "build_weights: bad CSR arguments");
+  hipStream_t st = as_stream(stream_);
+  int* d_max = nullptr;
+  LABFM_HIP(hipMalloc(&d_max, sizeof(int)));
+  hipLaunchKernelGGL(max_order_kernel, dim3(1), dim3(256), 0, st, order_m, n, d_max);
+  hipError_t le = hipGetLastError();
+  int mmax = 0;
+  if (le == hipSuccess) le = hipMemcpyAsync(&mmax, d_max, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (le == hipSuccess) le = hipStreamSynchronize(st);
+  (void)hipFree(d_max);
+  LABFM_HIP(le);
+  hipError_t e;
+  if (mmax <= 4) {
+    e = launch_build<4>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
+                        status, st);
+  } else if (mmax <= 6) {
+    e = launch_build<6>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
+                        status, st);
+  } else if (mmax <= 8) {
+    e = launch_build<8>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
+                        status, st);
+  } else {
+    // orders above 10 are reported per node as LABFM_NODE_BAD_ORDER
+    e = launch_build<10>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
+                         status, st);
+  }
+  LABFM_HIP(e);
+  return LABFM_OK;
+}

@@ -1,0 +1,248 @@
+"""Python binding of liblabfm.so (the gfx950 LABFM library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/labfm.h. Tensors must be
+contiguous HIP device tensors; work is enqueued on torch's current stream.
+There is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblabfm.so")
+
+OPS = ("x", "y", "L", "xx", "xy", "hyp")
+OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
+F64, F32_COMP = 0, 2
+
+OK, ERR_ARG, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+NODE_OK, NODE_SINGULAR, NODE_FEW_NEIGHBOURS, NODE_BAD_FILTER, NODE_BAD_ORDER = range(5)
+
+
+class LabfmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"labfm error {code}: {msg}")
+        self.code = code
+
+
+class _Box(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32)]
+
+
+class _Operators(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("w32", ctypes.c_void_p),
+                ("kappa", ctypes.c_void_p)]
+
+
+class _RKParams(ctypes.Structure):
+    _fields_ = [("c2", ctypes.c_double), ("mu", ctypes.c_double),
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("dt", ctypes.c_double), ("filter", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32)]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_double), ("filter_ms", ctypes.c_double),
+                ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "labfm_last_error": (ctypes.c_char_p, []),
+    "labfm_version": (ctypes.c_char_p, []),
+    "labfm_build_neighbours": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _Box, _P, _P,
+                                              ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
+    "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
+                                           ctypes.c_int64, _P, _P, _P, _P, _P, _P]),
+    "labfm_apply_operators": (ctypes.c_int, [ctypes.POINTER(_Operators), ctypes.c_uint32, _P, _P,
+                                             ctypes.c_int, _P]),
+    "labfm_time_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double), _P]),
+    "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
+                                    ctypes.c_int, _P]),
+    "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "labfm_rk_step": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams),
+                                     ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _P,
+                                     ctypes.c_size_t, ctypes.POINTER(_Timing), _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblabfm.so (built in-tree by ``__graft_entry__.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list:
+    return list(_SIGNATURES)
+
+
+def _check(code: int) -> None:
+    if code != OK:
+        raise LabfmError(code, lib().labfm_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("labfm expects HIP device tensors")
+    if not t.is_contiguous():
+        raise ValueError("labfm expects contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _box(box) -> _Box:
+    return _Box(float(box.Lx), float(box.Ly), int(bool(box.periodic_x)), int(bool(box.periodic_y)))
+
+
+def version() -> str:
+    return lib().labfm_version().decode()
+
+
+# ---------------------------------------------------------------------------
+
+def build_neighbours(x: torch.Tensor, y: torch.Tensor, h: torch.Tensor, box):
+    """CSR stencils (row_ptr int32[n+1], col int32[nnz]) on the device."""
+    n = x.numel()
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=x.device)
+    nnz = ctypes.c_int64(0)
+    code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(row_ptr),
+                                        None, 0, ctypes.byref(nnz), _stream())
+    if code != ERR_CAPACITY:
+        _check(code)
+    col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=x.device)
+    code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(row_ptr),
+                                        _ptr(col), col.numel(), ctypes.byref(nnz), _stream())
+    _check(code)
+    return row_ptr, col[: nnz.value]
+
+
+@dataclass
+class Operators:
+    """Device-resident operators of one node set."""
+
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    w: Optional[torch.Tensor]       # float64 (6, nnz)
+    w32: Optional[torch.Tensor]     # float32 (6, nnz)
+    kappa: torch.Tensor             # float64 (n,)
+    rowsum: Optional[torch.Tensor] = None
+    status: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def _c(self) -> _Operators:
+        return _Operators(self.n, self.nnz, _ptr(self.row_ptr).value, _ptr(self.col).value,
+                          None if self.w is None else _ptr(self.w).value,
+                          None if self.w32 is None else _ptr(self.w32).value,
+                          _ptr(self.kappa).value)
+
+
+def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
+                  rowsum: bool = False) -> Operators:
+    """Weights of the six operators, filter coefficients and node status."""
+    n = x.numel()
+    nnz = col.numel()
+    dev = x.device
+    if not torch.is_tensor(m):
+        m = torch.full((n,), int(m), dtype=torch.int8, device=dev)
+    # one extra element keeps the data pointer valid when nnz == 0
+    w = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)[: 6 * nnz].view(6, nnz)
+    w32 = (torch.empty(6 * nnz + 1, dtype=torch.float32, device=dev)[: 6 * nnz].view(6, nnz)
+           if f32 else None)
+    kappa = torch.empty(n, dtype=torch.float64, device=dev)
+    rs = torch.empty((6, n), dtype=torch.float64, device=dev) if rowsum else None
+    status = torch.empty(n, dtype=torch.int8, device=dev)
+    code = lib().labfm_build_weights(_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box),
+                                     _ptr(row_ptr), _ptr(col), nnz, _ptr(w), _ptr(w32),
+                                     _ptr(kappa), _ptr(rs), _ptr(status), _stream())
+    _check(code)
+    return Operators(row_ptr, col, w, w32, kappa, rs, status)
+
+
+def apply_operators(ops: Operators, phi: torch.Tensor, op_mask: int = 0x3F,
+                    prec: int = F64) -> torch.Tensor:
+    """L^d(phi) for the operators in op_mask; shape (popcount(mask), n)."""
+    k = bin(op_mask).count("1")
+    out = torch.empty((k, ops.n), dtype=torch.float64, device=phi.device)
+    c = ops._c()
+    _check(lib().labfm_apply_operators(ctypes.byref(c), op_mask, _ptr(phi), _ptr(out), prec,
+                                       _stream()))
+    return out
+
+
+def time_step(q: torch.Tensor, s: torch.Tensor, c2: float, mu: float) -> float:
+    dt = ctypes.c_double(0.0)
+    n = s.numel()
+    _check(lib().labfm_time_step(_ptr(q), _ptr(s), n, float(c2), float(mu), ctypes.byref(dt),
+                                 _stream()))
+    return dt.value
+
+
+def ns_rhs(q: torch.Tensor, ops: Operators, flow, prec: int = F64) -> torch.Tensor:
+    """Right-hand side [R_l | R_u | R_v] of the state q = [ln rho | u | v]."""
+    out = torch.empty_like(q)
+    prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
+                    float(getattr(flow, "gy", 0.0)), 1.0, 0, 0)
+    c = ops._c()
+    _check(lib().labfm_ns_rhs(_ptr(q), ctypes.byref(c), ctypes.byref(prm), _ptr(out), prec,
+                              _stream()))
+    return out
+
+
+def rk_workspace(n: int, device) -> torch.Tensor:
+    nbytes = lib().labfm_rk_workspace_bytes(n)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def rk_step(q: torch.Tensor, ops: Operators, flow, dt: float, n_steps: int, prec: int = F64,
+            use_graph: bool = False, filter: bool = True, check_finite: bool = False,
+            workspace: Optional[torch.Tensor] = None, timing: bool = False):
+    """Advance q = [ln rho | u | v] (float64, 3n) in place by n_steps RK steps.
+    Returns the per-kernel timing dict when ``timing`` is set."""
+    if workspace is None:
+        workspace = rk_workspace(ops.n, q.device)
+    prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
+                    float(getattr(flow, "gy", 0.0)), float(dt), int(filter), int(check_finite))
+    c = ops._c()
+    tm = _Timing()
+    code = lib().labfm_rk_step(_ptr(q), ctypes.byref(c), ctypes.byref(prm), int(n_steps), prec,
+                               int(use_graph), _ptr(workspace), workspace.numel(),
+                               ctypes.byref(tm) if timing else None, _stream())
+    _check(code)
+    if timing:
+        return {"stage_ms": tm.stage_ms, "filter_ms": tm.filter_ms,
+                "stage_launches": tm.stage_launches, "filter_launches": tm.filter_launches}
+    return None
