@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""Throughput of the LABFM hot path on one MI355X.
+
+One benchmark step is the whole periodic Taylor-Green job of the workload:
+stencil search, weight construction (six operators, filter coefficients),
+time step, then the RK steps of the run (four fused RK stages and one filter
+pass each). All inputs (node positions, spacings, orders, initial state) are
+resident in device memory before the timed region starts.
+
+value  = node-updates per second per RK stage for the whole job
+         (nodes x 4 stages x RK steps / job time), float64 path;
+roofline: the fused RK stage kernel, algorithmic bytes per launch
+         (44 K + 104 bytes per node, K = mean neighbours) over its mean
+         duration from HIP events recorded on its stream during the timed
+         region;
+f32_comp: the same job with float32 weights and compensated sums, its
+         speedup and its per-field error against the float64 run;
+cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+import os
+
+# the oracle's BLAS runs single-threaded so the core count is known
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import math  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-updates/s per RK stage + HBM roofline frac, FP32-comp vs FP64 at stated err"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed benchmark steps (whole jobs)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tg512_m8")
+    ap.add_argument("--rk-steps", type=int, default=None,
+                    help="RK steps per job (default: the workload's run length)")
+    ap.add_argument("--no-f32", action="store_true", help="skip the float32 compensated job")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for rocprofv3: a 1 GiB copy, then warmup jobs only")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2102_02019_amd import inputs, labfm, profiling
+
+    dev = torch.device("cuda:0")
+    wl = inputs.WORKLOADS[args.workload]
+    rk_steps = wl.steps if args.rk_steps is None else args.rk_steps
+    nodes = wl.nodes()
+    N = nodes.n
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    q0_h = np.concatenate([np.log(rho), u, v])
+
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    x, y, h, s, m = T(nodes.x), T(nodes.y), T(nodes.h), T(nodes.s), T(nodes.m)
+    q0 = T(q0_h)
+    q = torch.empty_like(q0)
+    ws = labfm.rk_workspace(N, dev)
+    torch.cuda.synchronize()
+
+    if args.profile_run:
+        # a plain copy of known size calibrates the HBM byte counters
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    def job(prec):
+        rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+        ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=(prec == labfm.F32_COMP))
+        q.copy_(q0)
+        dt = labfm.time_step(q, s, prm.c2, prm.mu)
+        tm = labfm.rk_step(q, ops, prm, dt, rk_steps, prec=prec, workspace=ws, timing=True)
+        return ops, tm
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            job(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tms = []
+        ops = None
+        for _ in range(steps):
+            ops, tm = job(prec)
+            tms.append(tm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return ops, tms, (t1 - t0) / max(1, steps)
+
+    if args.profile_run:
+        job(labfm.F64)
+        if not args.no_f32:
+            job(labfm.F32_COMP)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": "done", "workload": wl.name, "nodes": N}))
+        return
+
+    ops, tms, sec = timed(labfm.F64, args.steps, args.warmup)
+    q64 = q.clone()
+    nnz = ops.nnz
+    kbar = nnz / N
+    stage_ms = sum(t["stage_ms"] for t in tms) / sum(t["stage_launches"] for t in tms)
+    filter_ms = sum(t["filter_ms"] for t in tms) / max(1, sum(t["filter_launches"] for t in tms))
+    value = N * 4 * rk_steps / sec
+    bytes_stage = (44.0 * kbar + 104.0) * N
+    achieved = bytes_stage / (stage_ms * 1e-3) / 1e9
+    traffic = profiling.load_traffic("rk_stage_f64", wl.name,
+                                     profiling.kernel_source("operators.hip"))
+    status_hist = np.bincount(ops.status.cpu().numpy().astype(np.int64), minlength=5).tolist()
+    finite = bool(torch.isfinite(q64).all().item())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nodes": N, "order_m": wl.m,
+                   "mean_neighbours": round(kbar, 2), "rk_steps_per_job": rk_steps,
+                   "filter": "every step", "domain": "[0,2pi)^2 periodic, +/-0.3s jitter",
+                   "flow": "Taylor-Green, Re=100, Ma=0.1"},
+        "roofline": {"bound": "hbm", "kernel": "rk_stage_kernel<f64>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "bytes_per_node_stage": 44.0 * kbar + 104.0,
+                     "mean_launch_ms": stage_ms, "launches": sum(t["stage_launches"] for t in tms)},
+        "stage_kernel_node_updates_per_s": N / (stage_ms * 1e-3),
+        "filter_kernel_ms": filter_ms,
+        "setup_ms_per_job": sec * 1e3 - sum(t["stage_ms"] + t["filter_ms"] for t in tms) / len(tms),
+        "final_state_finite": finite,
+        "node_status_histogram": status_hist,
+    }
+
+    if not args.no_f32:
+        ops32, tms32, sec32 = timed(labfm.F32_COMP, args.steps, args.warmup)
+        q32 = q.clone()
+        st32 = sum(t["stage_ms"] for t in tms32) / sum(t["stage_launches"] for t in tms32)
+        a64 = q64.cpu().numpy().reshape(3, -1)
+        a32 = q32.cpu().numpy().reshape(3, -1)
+        err = {
+            "rho": float(np.linalg.norm(np.exp(a32[0]) - np.exp(a64[0])) / np.linalg.norm(np.exp(a64[0]))),
+            "u": float(np.linalg.norm(a32[1] - a64[1]) / np.linalg.norm(a64[1])),
+            "v": float(np.linalg.norm(a32[2] - a64[2]) / np.linalg.norm(a64[2])),
+        }
+        # per-operator error of one application on the initial velocity
+        uu = q0[N:2 * N].contiguous()
+        d64 = labfm.apply_operators(ops32, uu, 0x1F, labfm.F64).cpu().numpy()
+        d32 = labfm.apply_operators(ops32, uu, 0x1F, labfm.F32_COMP).cpu().numpy()
+        op_err = {labfm.OPS[d]: float(np.linalg.norm(d32[d] - d64[d]) / np.linalg.norm(d64[d]))
+                  for d in range(5)}
+        b32 = (24.0 * kbar + 104.0) * N
+        out["f32_comp"] = {
+            "value": N * 4 * rk_steps / sec32,
+            "ms_per_step": sec32 * 1e3,
+            "speedup_job": sec / sec32,
+            "speedup_stage_kernel": stage_ms / st32,
+            "stage_mean_launch_ms": st32,
+            "stage_achieved_GBs": b32 / (st32 * 1e-3) / 1e9,
+            "stage_frac": b32 / (st32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_node_stage": 24.0 * kbar + 104.0,
+            "final_state_rel_err_vs_f64": err,
+            "operator_rel_err_vs_f64": op_err,
+        }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, rk_steps, N)
+
+    print(json.dumps(out))
+
+
+def cpu_baseline(wl, rk_steps, N_full):
+    """The oracle on a 64 x 64 node sample of the workload (same order m,
+    h/s and so the same stencils per node): stencil search, weight build and
+    40 RK steps, timed, then scaled per node to the full job."""
+    import numpy as np
+
+    from oracle import labfm_oracle as O
+    from paper_2102_02019_amd import inputs
+
+    nodes = inputs.jittered_lattice(64, L=wl.L, seed=wl.seed, m=wl.m)
+    n = nodes.n
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    t0 = time.perf_counter()
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, wl.m, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm)
+    t1 = time.perf_counter()
+    k = 40
+    O.rk_run(np.log(rho), u, v, W, prm, dt, k)
+    t2 = time.perf_counter()
+    setup_per_node = (t1 - t0) / n
+    step_per_node = (t2 - t1) / (n * k)
+    job_s = N_full * (setup_per_node + rk_steps * step_per_node)
+    return {
+        "value": N_full * 4 * rk_steps / job_s,
+        "unit": "node-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{n} nodes (64x64, m={wl.m}): stencils + weights {t1 - t0:.1f} s, "
+                   f"{k} RK steps {t2 - t1:.1f} s; scaled per node to {N_full} nodes "
+                   f"and {rk_steps} steps"),
+        "rk_stage_only_node_updates_per_s": 4 * n * k / (t2 - t1),
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -17,6 +17,7 @@
 //            (Dot2 of Ogita, Rump & Oishi 2005), partial sums combined across
 //            lanes the same way, the final pair added in float64.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -406,8 +407,16 @@ struct StepPlan {
   double* Yb;
 };
 
+// Event marks around the launches of a step when timing is requested: one
+// mark before every launch and one after the last, so the time of launch k
+// is mark[k+1] - mark[k] (launches on one stream run back to back).
+struct Marks {
+  hipEvent_t* ev;
+  int count;
+};
+
 template <class P>
-hipError_t enqueue_step(const StepPlan& p, hipStream_t st, hipEvent_t* ev, int* nev) {
+hipError_t enqueue_step(const StepPlan& p, hipStream_t st, Marks* mk) {
   const auto* w = static_cast<const typename P::W*>(p.w);
   const long long bytes = 3LL * p.ops->n * sizeof(double);
   double* const Ys[4] = {p.Yb, p.Q, p.Yb, nullptr};
@@ -416,26 +425,39 @@ hipError_t enqueue_step(const StepPlan& p, hipStream_t st, hipEvent_t* ev, int* 
   hipError_t e = hipSuccess;
   for (int s = 0; s < 4 && e == hipSuccess; ++s) {
     const double dta = (s < 3) ? p.dt * kA[s] : 0.0;
-    if (ev) e = hipEventRecord(ev[(*nev)++], st);
+    if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
     if (e == hipSuccess)
       e = launch_stage<P>(p.lpn, p.ops, w, G[s], Qin[s], p.Ya, Ys[s], dta, p.dt * kB[s], p.fl,
                           st);
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[(*nev)++], st);
   }
   if (e != hipSuccess) return e;
   if (p.filter) {
-    if (ev) e = hipEventRecord(ev[(*nev)++], st);
+    if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
     if (e == hipSuccess) e = launch_filter<P>(p.lpn, p.ops, w, p.Ya, p.Q, st);
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[(*nev)++], st);
   } else {
-    e = hipMemcpyAsync(p.Q, p.Ya, bytes, hipMemcpyDeviceToDevice, st);
+    if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p.Q, p.Ya, bytes, hipMemcpyDeviceToDevice, st);
   }
+  if (mk && e == hipSuccess) e = hipEventRecord(mk->ev[mk->count++], st);
   return e;
 }
 
-hipError_t enqueue_step_any(const StepPlan& p, hipStream_t st, hipEvent_t* ev, int* nev) {
-  return p.prec == LABFM_F64 ? enqueue_step<F64>(p, st, ev, nev)
-                             : enqueue_step<F32Comp>(p, st, ev, nev);
+hipError_t enqueue_step_any(const StepPlan& p, hipStream_t st, Marks* mk) {
+  return p.prec == LABFM_F64 ? enqueue_step<F64>(p, st, mk) : enqueue_step<F32Comp>(p, st, mk);
+}
+
+// Timing events are created once and reused by later calls.
+std::mutex g_event_mutex;
+std::vector<hipEvent_t> g_events;
+
+hipError_t reserve_events(size_t count) {
+  while (g_events.size() < count) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    g_events.push_back(e);
+  }
+  return hipSuccess;
 }
 
 int check_ops(const labfm_operators* o, labfm_prec prec, const char* who) {
@@ -550,29 +572,29 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
   plan.Yb = Yb;
 
   if (timing) {
-    // event-timed launches (no graph): 2 events per kernel launch
-    const int per_step = 2 * (4 + (prm->filter ? 1 : 0));
-    std::vector<hipEvent_t> ev(static_cast<size_t>(per_step) * n_steps);
-    for (auto& e : ev) LABFM_HIP(hipEventCreate(&e));
-    int nev = 0;
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = enqueue_step_any(plan, st, ev.data(), &nev);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    // event-timed launches (no graph); 6 marks per step
+    std::lock_guard<std::mutex> lock(g_event_mutex);
+    const int per_step = 6;
+    LABFM_HIP(reserve_events(static_cast<size_t>(per_step) * n_steps));
     double stage = 0.0, filt = 0.0;
     long long ns = 0, nf = 0;
-    for (int k = 0; k < nev && e == hipSuccess; k += 2) {
-      float ms = 0.0f;
-      e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      const int pos = (k / 2) % (per_step / 2);
-      if (pos < 4) {
-        stage += ms;
-        ++ns;
-      } else {
-        filt += ms;
-        ++nf;
+    Marks mk{g_events.data(), 0};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = enqueue_step_any(plan, st, &mk);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+      for (int l = 0; l < 5 && e == hipSuccess; ++l) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, g_events[k * per_step + l], g_events[k * per_step + l + 1]);
+        if (l < 4) {
+          stage += ms;
+          ++ns;
+        } else if (prm->filter) {
+          filt += ms;
+          ++nf;
+        }
       }
     }
-    for (auto& x : ev) (void)hipEventDestroy(x);
     LABFM_HIP(e);
     timing->stage_ms = stage;
     timing->filter_ms = filt;
@@ -590,7 +612,7 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
     if (e == hipSuccess) e = hipStreamWaitEvent(cs, join, 0);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t ce = enqueue_step_any(plan, cs, nullptr, nullptr);
+      hipError_t ce = enqueue_step_any(plan, cs, nullptr);
       e = hipStreamEndCapture(cs, &graph);
       if (ce != hipSuccess) e = ce;
     }
@@ -606,7 +628,7 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
     (void)hipStreamDestroy(cs);
     LABFM_HIP(e);
   } else {
-    for (int k = 0; k < n_steps; ++k) LABFM_HIP(enqueue_step_any(plan, st, nullptr, nullptr));
+    for (int k = 0; k < n_steps; ++k) LABFM_HIP(enqueue_step_any(plan, st, nullptr));
   }
 
   if (prm->check_finite) {
