@@ -62,6 +62,7 @@ typedef enum {
 /* Arithmetic of operator application. */
 typedef enum {
   LABFM_F64 = 0,      /* float64 weights and fields, float64 sums */
+  LABFM_F32W = 1,     /* float32 weights, float64 differences and sums */
   LABFM_F32_COMP = 2  /* float32 weights; differences phi_j - phi_i formed in
                          float64 and rounded to float32; products and sums
                          compensated (error-free TwoProd + TwoSum, "Dot2") */
@@ -115,6 +116,25 @@ typedef struct {
   int64_t stage_launches;
   int64_t filter_launches;
 } labfm_timing;
+
+/* Gather kernels whose launch shape can be chosen (labfm_set_launch_config,
+ * labfm_tune). */
+typedef enum {
+  LABFM_KERNEL_STAGE = 0,   /* fused RK stage (and labfm_ns_rhs) */
+  LABFM_KERNEL_FILTER = 1,  /* filter pass of labfm_rk_step */
+  LABFM_KERNEL_APPLY = 2    /* labfm_apply_operators */
+} labfm_kernel;
+
+/* Launch-shape flags. */
+#define LABFM_LAUNCH_XCD_ORDER 1 /* workgroups of each XCD take one contiguous node range */
+#define LABFM_LAUNCH_STREAMING 2 /* weights and indices loaded non-temporally */
+
+/* Launch shape of a gather kernel: lanes_per_node lanes of a 64-lane
+ * wavefront share one node's row (4, 8, 16 or 32), plus flags. */
+typedef struct {
+  int32_t lanes_per_node;
+  int32_t flags;
+} labfm_launch_config;
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* labfm_last_error(void);
@@ -184,7 +204,7 @@ int labfm_build_weights(const double* x, const double* y, const double* h, const
  * of op_mask, labfm_op order) out_k[i] = sum_j (phi_j - phi_i) w^d_ji, where
  * k counts the selected operators in increasing d.
  *
- *   ops     operators (w for LABFM_F64, w32 for LABFM_F32_COMP).
+ *   ops     operators (w for LABFM_F64, w32 for the float32 precisions).
  *   phi     float64[n] field.
  *   out     float64[popcount(op_mask) * n] output.
  */
@@ -218,6 +238,35 @@ int labfm_time_step(const double* q, const double* s, int32_t n, double c2, doub
 int labfm_ns_rhs(const double* q, const labfm_operators* ops, const labfm_rk_params* prm,
                  double* out, labfm_prec prec, void* stream);
 
+/*
+ * Launch shape used for `kernel` at precision `prec` on a node set of n
+ * nodes and nnz entries (the process-wide setting, or the built-in choice
+ * from the mean row length nnz/n when none is set).
+ */
+int labfm_get_launch_config(int32_t kernel, labfm_prec prec, int32_t n, int64_t nnz,
+                            labfm_launch_config* cfg);
+
+/* Sets the process-wide launch shape of `kernel` at `prec`; a NULL cfg or
+ * lanes_per_node == 0 restores the built-in choice. LABFM_ERR_ARG for an
+ * unsupported shape. */
+int labfm_set_launch_config(int32_t kernel, labfm_prec prec, const labfm_launch_config* cfg);
+
+/*
+ * Autotuner: times every supported launch shape of the stage, filter and
+ * apply kernels on the given operators and state (reps launches each, HIP
+ * events on `stream`), installs the fastest as the process-wide setting for
+ * `prec` and reports it.
+ *
+ *   q          float64[3n] state the stage kernel reads (not modified).
+ *   workspace  labfm_rk_workspace_bytes(n) bytes (overwritten).
+ *   best       host, labfm_launch_config[3] in labfm_kernel order.
+ *   best_ms    host, double[3]: mean launch time of each chosen shape.
+ * Synchronises the stream.
+ */
+int labfm_tune(const labfm_operators* ops, const double* q, labfm_prec prec, int32_t reps,
+               void* workspace, size_t workspace_bytes, labfm_launch_config* best,
+               double* best_ms, void* stream);
+
 /* Bytes of device workspace labfm_rk_step needs for n nodes. */
 size_t labfm_rk_workspace_bytes(int32_t n);
 
@@ -231,7 +280,7 @@ size_t labfm_rk_workspace_bytes(int32_t n);
  *
  *   q          float64[3n] state [ln rho | u | v], updated in place.
  *   ops        operators (w and kappa for LABFM_F64; w32 and kappa for
- *              LABFM_F32_COMP; the state stays float64 in both).
+ *              LABFM_F32W and LABFM_F32_COMP; the state stays float64).
  *   workspace  device buffer of labfm_rk_workspace_bytes(n) bytes.
  *   use_graph  1: capture one step as a HIP graph and replay it.
  *   timing     host, optional: per-kernel event timings (synchronises).

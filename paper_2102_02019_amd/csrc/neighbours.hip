@@ -48,12 +48,14 @@ __device__ __forceinline__ int axis_candidates(int c, int nc, int periodic, int*
   return k;
 }
 
-// |r_ji| <= 2 h_i with separately rounded products and sum.
+// |r_ji| <= 2 h_i with separately rounded products and sum (contraction into
+// an FMA is switched off here).
 __device__ __forceinline__ bool within(double xi, double yi, double xj, double yj, double r2,
                                        const Grid& g) {
+#pragma clang fp contract(off)
   const double dx = wrap_axis(xj - xi, g.Lx, g.px);
   const double dy = wrap_axis(yj - yi, g.Ly, g.py);
-  const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+  const double d2 = dx * dx + dy * dy;
   return d2 <= r2;
 }
 
@@ -165,7 +167,7 @@ __global__ void count_kernel(const double* __restrict__ x, const double* __restr
   if (i >= n) return;
   const double xi = x[i], yi = y[i];
   const double r = 2.0 * h[i];
-  const double r2 = __dmul_rn(r, r);
+  const double r2 = r * r;  // a lone product: rounded once
   const Candidates cand = candidate_cells(cell_of[i], g);
   int cnt = 0;
   for (int c = 0; c < cand.count; ++c) {
@@ -187,7 +189,7 @@ __global__ void fill_kernel(const double* __restrict__ x, const double* __restri
   if (i >= n) return;
   const double xi = x[i], yi = y[i];
   const double r = 2.0 * h[i];
-  const double r2 = __dmul_rn(r, r);
+  const double r2 = r * r;  // a lone product: rounded once
   const Candidates cand = candidate_cells(cell_of[i], g);
   int cur[9], end[9], head[9];
 #pragma unroll

@@ -18,6 +18,7 @@
 //            lanes the same way, the final pair added in float64.
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -44,7 +45,10 @@ struct F64 {
   __device__ __forceinline__ static D diff(double pj, double pi) { return pj - pi; }
 };
 
+// Error-free transformations need every operation rounded on its own, so
+// floating-point contraction into FMAs is switched off inside them.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   const float bb = s - a;
   e = (a - (s - bb)) + (b - bb);
@@ -59,12 +63,13 @@ struct F32Comp {
       c = 0.0f;
     }
     __device__ __forceinline__ void add(float w, float d) {
+#pragma clang fp contract(off)
       const float p = w * d;
       const float ep = fmaf(w, d, -p);  // exact: w*d = p + ep
       float t, es;
       two_sum(s, p, t, es);
       s = t;
-      c += es + ep;
+      c = c + (es + ep);
     }
     template <int width>
     __device__ __forceinline__ double reduce() {
@@ -76,7 +81,7 @@ struct F32Comp {
         float t, e;
         two_sum(hs, os, t, e);
         hs = t;
-        hc = hc + oc + e;
+        hc = (hc + oc) + e;
       }
       return static_cast<double>(hs) + static_cast<double>(hc);
     }
@@ -87,16 +92,63 @@ struct F32Comp {
   }
 };
 
+// float32 weights, float64 differences and sums: the product of a float32
+// weight and a float64 difference is rounded once, as in F64.
+struct F32W {
+  using W = float;
+  using Acc = F64::Acc;
+  using D = double;
+  __device__ __forceinline__ static D diff(double pj, double pi) { return pj - pi; }
+};
+
+// --------------------------------------------------------------------------
+// launch variants
+// --------------------------------------------------------------------------
+
+// Bit flags of a gather kernel's variant (labfm_launch_config.flags).
+constexpr int kXcdOrder = LABFM_LAUNCH_XCD_ORDER;   // contiguous node ranges per XCD
+constexpr int kStreaming = LABFM_LAUNCH_STREAMING;  // non-temporal weight/index loads
+
+// The dispatcher hands workgroups to the 8 XCDs round-robin. With the XCD
+// order flag, workgroup b works on logical tile xcd_tile(b) so that each XCD
+// gets one contiguous run of tiles (a compact, Morton-ordered region whose
+// gathered field values then stay in that XCD's L2).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+  const unsigned q = nb / kXcds, r = nb % kXcds;
+  const unsigned x = b % kXcds, k = b / kXcds;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <int FL>
+__device__ __forceinline__ int first_thread() {
+  const unsigned b = (FL & kXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  return static_cast<int>(b * blockDim.x + threadIdx.x);
+}
+
+// Loads of data that is read once per launch (weights, column indices).
+template <int FL, class T>
+__device__ __forceinline__ T stream_load(const T* p) {
+  if constexpr ((FL & kStreaming) != 0) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+// Edges per lane whose loads are issued together in the gather loops.
+__host__ __device__ constexpr int unroll_of(int lpn) { return lpn >= 32 ? 3 : (lpn >= 16 ? 3 : 4); }
+
 // --------------------------------------------------------------------------
 // operator application
 // --------------------------------------------------------------------------
 
-template <int LPN, class P>
+template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
              const typename P::W* __restrict__ w, long long nnz, unsigned mask,
              const double* __restrict__ phi, double* __restrict__ out, int n) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
   if (node >= n) return;  // whole LPN groups exit together
@@ -105,11 +157,31 @@ apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   typename P::Acc acc[LABFM_NUM_OPS];
 #pragma unroll
   for (int d = 0; d < LABFM_NUM_OPS; ++d) acc[d].zero();
-  for (int e = e0 + sub; e < e1; e += LPN) {
-    const typename P::D dj = P::diff(phi[col[e]], pi);
+  constexpr int U = unroll_of(LPN);
+  if (e1 > e0) {
+    for (int base = e0 + sub; base < e1; base += U * LPN) {
+      int ee[U];
+      bool ok[U];
+      typename P::D dj[U];
 #pragma unroll
-    for (int d = 0; d < LABFM_NUM_OPS; ++d)
-      if (mask & (1u << d)) acc[d].add(w[d * nnz + e], dj);
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * LPN;
+        ok[u] = e < e1;
+        ee[u] = ok[u] ? e : e1 - 1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) dj[u] = P::diff(phi[stream_load<FL>(col + ee[u])], pi);
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        if (mask & (1u << d)) {
+          typename P::W wv[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) wv[u] = stream_load<FL>(w + d * nnz + ee[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc[d].add(ok[u] ? wv[u] : typename P::W(0), dj[u]);
+        }
+      }
+    }
   }
   int k = 0;
 #pragma unroll
@@ -133,13 +205,13 @@ struct Flow {
 // Stage of the two-register scheme. Y (gathered) holds the stage value, q the
 // solution. With F = R(Y):  Y' = q + dta F  (skipped when Yout is null),
 // q <- q + dtb F. qin and qout may be the same buffer; Y is never written.
-template <int LPN, class P>
+template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
                 const typename P::W* __restrict__ w, long long nnz, const double* Y,
                 const double* qin, double* qout, double* Yout, double dta, double dtb, Flow fl,
                 int n) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
   if (node >= n) return;
@@ -156,25 +228,64 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   lx.zero(); ly.zero();
   ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
   vx.zero(); vy.zero(); vL.zero(); vxx.zero(); vxy.zero();
+  // Edges are taken U per lane at a time: all index, weight and field loads
+  // of the U edges are issued before any is used. Lanes past the row's end
+  // re-read its last entry (a valid address) with zero weights.
+  constexpr int U = unroll_of(LPN);
+  using W = typename P::W;
+  using D = typename P::D;
   const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
-  for (int e = e0 + sub; e < e1; e += LPN) {
-    const int j = col[e];
-    const typename P::D dl = P::diff(Yl[j], li);
-    const typename P::D du = P::diff(Yu[j], ui);
-    const typename P::D dv = P::diff(Yv[j], vi);
-    const typename P::W a = wx[e], b = wy[e], c = wL[e], d = wxx[e], f = wxy[e];
-    lx.add(a, dl);
-    ly.add(b, dl);
-    ux.add(a, du);
-    uy.add(b, du);
-    uL.add(c, du);
-    uxx.add(d, du);
-    uxy.add(f, du);
-    vx.add(a, dv);
-    vy.add(b, dv);
-    vL.add(c, dv);
-    vxx.add(d, dv);
-    vxy.add(f, dv);
+  if (e1 > e0) {
+    for (int base = e0 + sub; base < e1; base += U * LPN) {
+      int ee[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * LPN;
+        ok[u] = e < e1;
+        ee[u] = ok[u] ? e : e1 - 1;
+      }
+      int jj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) jj[u] = stream_load<FL>(col + ee[u]);
+      W a[U], b[U], c[U], d[U], f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = stream_load<FL>(wx + ee[u]);
+        b[u] = stream_load<FL>(wy + ee[u]);
+        c[u] = stream_load<FL>(wL + ee[u]);
+        d[u] = stream_load<FL>(wxx + ee[u]);
+        f[u] = stream_load<FL>(wxy + ee[u]);
+      }
+      double gl[U], gu[U], gv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        gl[u] = Yl[jj[u]];
+        gu[u] = Yu[jj[u]];
+        gv[u] = Yv[jj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const W z = W(0);
+        const W au = ok[u] ? a[u] : z, bu = ok[u] ? b[u] : z, cu = ok[u] ? c[u] : z;
+        const W du_ = ok[u] ? d[u] : z, fu = ok[u] ? f[u] : z;
+        const D dl = P::diff(gl[u], li);
+        const D du = P::diff(gu[u], ui);
+        const D dv = P::diff(gv[u], vi);
+        lx.add(au, dl);
+        ly.add(bu, dl);
+        ux.add(au, du);
+        uy.add(bu, du);
+        uL.add(cu, du);
+        uxx.add(du_, du);
+        uxy.add(fu, du);
+        vx.add(au, dv);
+        vy.add(bu, dv);
+        vL.add(cu, dv);
+        vxx.add(du_, dv);
+        vxy.add(fu, dv);
+      }
+    }
   }
   const double Lx = lx.template reduce<LPN>(), Ly = ly.template reduce<LPN>();
   const double Ux = ux.template reduce<LPN>(), Uy = uy.template reduce<LPN>();
@@ -211,12 +322,12 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
 // filter: phi <- phi + kappa_i L^hyp_i(phi) for the three fields
 // --------------------------------------------------------------------------
 
-template <int LPN, class P>
+template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
               const typename P::W* __restrict__ whyp, const double* __restrict__ kappa,
               const double* __restrict__ in, double* __restrict__ out, int n) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
   if (node >= n) return;
@@ -227,12 +338,38 @@ filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   au.zero();
   av.zero();
   const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
-  for (int e = e0 + sub; e < e1; e += LPN) {
-    const int j = col[e];
-    const typename P::W a = whyp[e];
-    al.add(a, P::diff(in[j], li));
-    au.add(a, P::diff(in[n + j], ui));
-    av.add(a, P::diff(in[n2 + j], vi));
+  constexpr int U = unroll_of(LPN);
+  if (e1 > e0) {
+    for (int base = e0 + sub; base < e1; base += U * LPN) {
+      int ee[U], jj[U];
+      bool ok[U];
+      typename P::W a[U];
+      double gl[U], gu[U], gv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * LPN;
+        ok[u] = e < e1;
+        ee[u] = ok[u] ? e : e1 - 1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jj[u] = stream_load<FL>(col + ee[u]);
+        a[u] = stream_load<FL>(whyp + ee[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        gl[u] = in[jj[u]];
+        gu[u] = in[n + jj[u]];
+        gv[u] = in[n2 + jj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const typename P::W wu = ok[u] ? a[u] : typename P::W(0);
+        al.add(wu, P::diff(gl[u], li));
+        au.add(wu, P::diff(gu[u], ui));
+        av.add(wu, P::diff(gv[u], vi));
+      }
+    }
   }
   const double sl = al.template reduce<LPN>();
   const double su = au.template reduce<LPN>();
@@ -299,81 +436,117 @@ __global__ void nonfinite_kernel(const double* __restrict__ q, long long len, in
 
 constexpr int kThreads = 256;
 
-// Lanes per node used by the gather kernels, chosen from the mean row length.
-int lanes_per_node(int n, long long nnz) {
-  const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
-  if (k > 48.0) return 16;
-  if (k > 12.0) return 8;
-  return 4;
-}
+struct LaunchCfg {
+  int lpn;    // lanes per node: 4, 8, 16 or 32
+  int flags;  // kXcdOrder | kStreaming
+};
 
-template <class P>
-hipError_t launch_apply(int lpn, const labfm_operators* o, const typename P::W* w, unsigned mask,
-                        const double* phi, double* out, hipStream_t st) {
-  const int n = o->n;
-  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
-#define LABFM_APPLY_CASE(L)                                                                    \
-  case L:                                                                                      \
-    hipLaunchKernelGGL((apply_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st, o->row_ptr, \
-                       o->col, w, static_cast<long long>(o->nnz), mask, phi, out, n);          \
+// Calls fn(integral_constant<LPN>, integral_constant<FLAGS>) for a config.
+template <class Fn>
+hipError_t with_cfg(LaunchCfg c, Fn&& fn) {
+  using std::integral_constant;
+#define LABFM_CFG_CASE(L, F)                                  \
+  case (L) * 8 + (F):                                          \
+    fn(integral_constant<int, L>{}, integral_constant<int, F>{}); \
     break;
-  switch (lpn) {
-    LABFM_APPLY_CASE(4)
-    LABFM_APPLY_CASE(8)
-    LABFM_APPLY_CASE(16)
-    LABFM_APPLY_CASE(32)
+#define LABFM_CFG_LPN(L) \
+  LABFM_CFG_CASE(L, 0) LABFM_CFG_CASE(L, 1) LABFM_CFG_CASE(L, 2) LABFM_CFG_CASE(L, 3)
+  switch (c.lpn * 8 + c.flags) {
+    LABFM_CFG_LPN(4)
+    LABFM_CFG_LPN(8)
+    LABFM_CFG_LPN(16)
+    LABFM_CFG_LPN(32)
     default:
       return hipErrorInvalidValue;
   }
-#undef LABFM_APPLY_CASE
+#undef LABFM_CFG_LPN
+#undef LABFM_CFG_CASE
   return hipGetLastError();
 }
 
+bool valid_cfg(const labfm_launch_config& c) {
+  return (c.lanes_per_node == 4 || c.lanes_per_node == 8 || c.lanes_per_node == 16 ||
+          c.lanes_per_node == 32) &&
+         c.flags >= 0 && c.flags <= 3;
+}
+
+// Default variant from the mean row length K (measured on MI355X at K ~ 90:
+// the float64 stage runs best with 32 lanes per node, the float32 stages and
+// every filter pass with fewer); overridden per kernel and precision by
+// labfm_set_launch_config or labfm_tune.
+LaunchCfg default_cfg(int kernel, labfm_prec prec, int n, long long nnz) {
+  const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
+  int lpn = k > 48.0 ? 16 : (k > 12.0 ? 8 : 4);
+  if (kernel == LABFM_KERNEL_STAGE && prec == LABFM_F64 && k > 48.0) lpn = 32;
+  if (kernel == LABFM_KERNEL_FILTER && k > 48.0) lpn = 8;
+  return LaunchCfg{lpn, 0};
+}
+
+std::mutex g_cfg_mutex;
+labfm_launch_config g_cfg[3][3] = {};  // [kernel][precision]; lanes_per_node 0 = default
+
+int prec_slot(labfm_prec p) { return p == LABFM_F64 ? 0 : (p == LABFM_F32_COMP ? 1 : 2); }
+
+LaunchCfg cfg_for(int kernel, labfm_prec prec, int n, long long nnz) {
+  std::lock_guard<std::mutex> lock(g_cfg_mutex);
+  const labfm_launch_config& c = g_cfg[kernel][prec_slot(prec)];
+  if (c.lanes_per_node == 0) return default_cfg(kernel, prec, n, nnz);
+  return LaunchCfg{c.lanes_per_node, c.flags};
+}
+
 template <class P>
-hipError_t launch_stage(int lpn, const labfm_operators* o, const typename P::W* w,
+hipError_t launch_apply(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
+                        unsigned mask, const double* phi, double* out, hipStream_t st) {
+  const int n = o->n;
+  const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
+  return with_cfg(cfg, [&](auto L, auto F) {
+    hipLaunchKernelGGL((apply_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, w,
+                       static_cast<long long>(o->nnz), mask, phi, out, n);
+  });
+}
+
+template <class P>
+hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                         const double* Y, const double* qin, double* qout, double* Yout, double dta,
                         double dtb, const Flow& fl, hipStream_t st) {
   const int n = o->n;
-  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
-#define LABFM_STAGE_CASE(L)                                                                   \
-  case L:                                                                                     \
-    hipLaunchKernelGGL((rk_stage_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st,          \
-                       o->row_ptr, o->col, w, static_cast<long long>(o->nnz), Y, qin, qout, \
-                       Yout, dta, dtb, fl, n);                                                \
-    break;
-  switch (lpn) {
-    LABFM_STAGE_CASE(4)
-    LABFM_STAGE_CASE(8)
-    LABFM_STAGE_CASE(16)
-    LABFM_STAGE_CASE(32)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef LABFM_STAGE_CASE
-  return hipGetLastError();
+  const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
+  return with_cfg(cfg, [&](auto L, auto F) {
+    hipLaunchKernelGGL((rk_stage_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, w,
+                       static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n);
+  });
 }
 
 template <class P>
-hipError_t launch_filter(int lpn, const labfm_operators* o, const typename P::W* w,
+hipError_t launch_filter(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                          const double* in, double* out, hipStream_t st) {
   const int n = o->n;
-  const unsigned grid = blocks_for(static_cast<long long>(n) * lpn, kThreads);
+  const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   const typename P::W* whyp = w + LABFM_OP_HYP * o->nnz;
-#define LABFM_FILTER_CASE(L)                                                                  \
-  case L:                                                                                     \
-    hipLaunchKernelGGL((filter_kernel<L, P>), dim3(grid), dim3(kThreads), 0, st, o->row_ptr, \
-                       o->col, whyp, o->kappa, in, out, n);                                   \
-    break;
-  switch (lpn) {
-    LABFM_FILTER_CASE(4)
-    LABFM_FILTER_CASE(8)
-    LABFM_FILTER_CASE(16)
-    LABFM_FILTER_CASE(32)
-    default:
-      return hipErrorInvalidValue;
+  return with_cfg(cfg, [&](auto L, auto F) {
+    hipLaunchKernelGGL((filter_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, whyp, o->kappa, in, out, n);
+  });
+}
+
+// Calls fn(policy{}, weights) with the arithmetic policy of a precision.
+template <class Fn>
+hipError_t with_prec(labfm_prec prec, const labfm_operators* o, Fn&& fn) {
+  switch (prec) {
+    case LABFM_F64:
+      return fn(F64{}, o->w);
+    case LABFM_F32_COMP:
+      return fn(F32Comp{}, o->w32);
+    case LABFM_F32W:
+      return fn(F32W{}, o->w32);
   }
-#undef LABFM_FILTER_CASE
-  return hipGetLastError();
+  return hipErrorInvalidValue;
+}
+
+bool known_prec(labfm_prec p) {
+  return p == LABFM_F64 || p == LABFM_F32_COMP || p == LABFM_F32W;
 }
 
 // RK3(2)4[2R+]C (Kennedy, Carpenter & Lewis 2000): sub-diagonal a_{i+1,i}
@@ -398,7 +571,7 @@ struct StepPlan {
   const labfm_operators* ops;
   const void* w;
   labfm_prec prec;
-  int lpn;
+  LaunchCfg stage_cfg, filter_cfg;
   Flow fl;
   double dt;
   int filter;
@@ -427,13 +600,13 @@ hipError_t enqueue_step(const StepPlan& p, hipStream_t st, Marks* mk) {
     const double dta = (s < 3) ? p.dt * kA[s] : 0.0;
     if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
     if (e == hipSuccess)
-      e = launch_stage<P>(p.lpn, p.ops, w, G[s], Qin[s], p.Ya, Ys[s], dta, p.dt * kB[s], p.fl,
-                          st);
+      e = launch_stage<P>(p.stage_cfg, p.ops, w, G[s], Qin[s], p.Ya, Ys[s], dta, p.dt * kB[s],
+                          p.fl, st);
   }
   if (e != hipSuccess) return e;
   if (p.filter) {
     if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
-    if (e == hipSuccess) e = launch_filter<P>(p.lpn, p.ops, w, p.Ya, p.Q, st);
+    if (e == hipSuccess) e = launch_filter<P>(p.filter_cfg, p.ops, w, p.Ya, p.Q, st);
   } else {
     if (mk) e = hipEventRecord(mk->ev[mk->count++], st);
     if (e == hipSuccess) e = hipMemcpyAsync(p.Q, p.Ya, bytes, hipMemcpyDeviceToDevice, st);
@@ -443,7 +616,9 @@ hipError_t enqueue_step(const StepPlan& p, hipStream_t st, Marks* mk) {
 }
 
 hipError_t enqueue_step_any(const StepPlan& p, hipStream_t st, Marks* mk) {
-  return p.prec == LABFM_F64 ? enqueue_step<F64>(p, st, mk) : enqueue_step<F32Comp>(p, st, mk);
+  return with_prec(p.prec, p.ops, [&](auto pol, const auto*) {
+    return enqueue_step<decltype(pol)>(p, st, mk);
+  });
 }
 
 // Timing events are created once and reused by later calls.
@@ -464,10 +639,9 @@ int check_ops(const labfm_operators* o, labfm_prec prec, const char* who) {
   LABFM_REQUIRE(o, "%s: null operators", who);
   LABFM_REQUIRE(o->n > 0 && o->nnz >= 0 && o->row_ptr && (o->col || o->nnz == 0),
                 "%s: incomplete operator description", who);
-  LABFM_REQUIRE(prec == LABFM_F64 || prec == LABFM_F32_COMP, "%s: unknown precision %d", who,
-                (int)prec);
+  LABFM_REQUIRE(known_prec(prec), "%s: unknown precision %d", who, (int)prec);
   if (prec == LABFM_F64) LABFM_REQUIRE(o->w, "%s: float64 weights required", who);
-  if (prec == LABFM_F32_COMP) LABFM_REQUIRE(o->w32, "%s: float32 weights required", who);
+  if (prec != LABFM_F64) LABFM_REQUIRE(o->w32, "%s: float32 weights required", who);
   return LABFM_OK;
 }
 
@@ -485,10 +659,10 @@ extern "C" int labfm_apply_operators(const labfm_operators* ops, uint32_t op_mas
   LABFM_REQUIRE(op_mask != 0 && op_mask < (1u << LABFM_NUM_OPS),
                 "apply_operators: op_mask must select operators 0..5");
   hipStream_t st = as_stream(stream_);
-  const int lpn = lanes_per_node(ops->n, ops->nnz);
-  hipError_t e = (prec == LABFM_F64)
-                     ? launch_apply<F64>(lpn, ops, ops->w, op_mask, phi, out, st)
-                     : launch_apply<F32Comp>(lpn, ops, ops->w32, op_mask, phi, out, st);
+  const LaunchCfg cfg = cfg_for(LABFM_KERNEL_APPLY, prec, ops->n, ops->nnz);
+  hipError_t e = with_prec(prec, ops, [&](auto pol, const auto* w) {
+    return launch_apply<decltype(pol)>(cfg, ops, w, op_mask, phi, out, st);
+  });
   LABFM_HIP(e);
   return LABFM_OK;
 }
@@ -501,12 +675,11 @@ extern "C" int labfm_ns_rhs(const double* q, const labfm_operators* ops,
   LABFM_REQUIRE(q && prm && out, "ns_rhs: null argument");
   LABFM_REQUIRE(out != q, "ns_rhs: out must not alias q");
   hipStream_t st = as_stream(stream_);
-  const int lpn = lanes_per_node(ops->n, ops->nnz);
+  const LaunchCfg cfg = cfg_for(LABFM_KERNEL_STAGE, prec, ops->n, ops->nnz);
   const Flow fl{prm->c2, prm->mu, prm->gx, prm->gy};
-  hipError_t e = (prec == LABFM_F64)
-                     ? launch_stage<F64>(lpn, ops, ops->w, q, nullptr, out, nullptr, 0.0, 1.0, fl, st)
-                     : launch_stage<F32Comp>(lpn, ops, ops->w32, q, nullptr, out, nullptr, 0.0,
-                                             1.0, fl, st);
+  hipError_t e = with_prec(prec, ops, [&](auto pol, const auto* w) {
+    return launch_stage<decltype(pol)>(cfg, ops, w, q, nullptr, out, nullptr, 0.0, 1.0, fl, st);
+  });
   LABFM_HIP(e);
   return LABFM_OK;
 }
@@ -561,9 +734,10 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
   StepPlan plan;
   plan.ops = ops;
   plan.w = (prec == LABFM_F64) ? static_cast<const void*>(ops->w)
-                               : static_cast<const void*>(ops->w32);
+                               : static_cast<const void*>(ops->w32);  // F32 policies
   plan.prec = prec;
-  plan.lpn = lanes_per_node(n, ops->nnz);
+  plan.stage_cfg = cfg_for(LABFM_KERNEL_STAGE, prec, n, ops->nnz);
+  plan.filter_cfg = cfg_for(LABFM_KERNEL_FILTER, prec, n, ops->nnz);
   plan.fl = Flow{prm->c2, prm->mu, prm->gx, prm->gy};
   plan.dt = prm->dt;
   plan.filter = prm->filter;
@@ -645,5 +819,94 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
       return LABFM_ERR_NONFINITE;
     }
   }
+  return LABFM_OK;
+}
+
+extern "C" int labfm_get_launch_config(int32_t kernel, labfm_prec prec, int32_t n, int64_t nnz,
+                                       labfm_launch_config* cfg) {
+  clear_error();
+  LABFM_REQUIRE(kernel >= 0 && kernel <= 2 && cfg, "get_launch_config: bad arguments");
+  LABFM_REQUIRE(known_prec(prec), "get_launch_config: bad precision");
+  const LaunchCfg c = cfg_for(kernel, prec, n, nnz);
+  cfg->lanes_per_node = c.lpn;
+  cfg->flags = c.flags;
+  return LABFM_OK;
+}
+
+extern "C" int labfm_set_launch_config(int32_t kernel, labfm_prec prec,
+                                       const labfm_launch_config* cfg) {
+  clear_error();
+  LABFM_REQUIRE(kernel >= 0 && kernel <= 2, "set_launch_config: unknown kernel %d", kernel);
+  LABFM_REQUIRE(known_prec(prec), "set_launch_config: bad precision");
+  labfm_launch_config c{0, 0};
+  if (cfg && cfg->lanes_per_node != 0) {
+    LABFM_REQUIRE(valid_cfg(*cfg), "set_launch_config: unsupported shape (%d lanes, flags %d)",
+                  cfg->lanes_per_node, cfg->flags);
+    c = *cfg;
+  }
+  std::lock_guard<std::mutex> lock(g_cfg_mutex);
+  g_cfg[kernel][prec_slot(prec)] = c;
+  return LABFM_OK;
+}
+
+extern "C" int labfm_tune(const labfm_operators* ops, const double* q, labfm_prec prec,
+                          int32_t reps, void* workspace, size_t workspace_bytes,
+                          labfm_launch_config* best, double* best_ms, void* stream_) {
+  clear_error();
+  if (int r = check_ops(ops, prec, "tune")) return r;
+  LABFM_REQUIRE(q && best && best_ms && reps > 0, "tune: bad arguments");
+  const int n = ops->n;
+  LABFM_REQUIRE(workspace && workspace_bytes >= labfm_rk_workspace_bytes(n),
+                "tune: workspace of %zu bytes required", labfm_rk_workspace_bytes(n));
+  LABFM_REQUIRE(ops->kappa, "tune: kappa required");
+  hipStream_t st = as_stream(stream_);
+  double* out = static_cast<double*>(workspace);
+  const Flow fl{1.0, 1.0, 0.0, 0.0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LABFM_HIP(hipEventCreate(&e0));
+  LABFM_HIP(hipEventCreate(&e1));
+  hipError_t err = hipSuccess;
+  const int lpns[4] = {4, 8, 16, 32};
+  for (int kernel = 0; kernel < 3 && err == hipSuccess; ++kernel) {
+    double bms = 1e300;
+    LaunchCfg bc{0, 0};
+    for (int li = 0; li < 4 && err == hipSuccess; ++li) {
+      for (int fl_bits = 0; fl_bits < 4 && err == hipSuccess; ++fl_bits) {
+        const LaunchCfg c{lpns[li], fl_bits};
+        auto launch = [&]() -> hipError_t {
+          return with_prec(prec, ops, [&](auto pol, const auto* w) {
+            using P = decltype(pol);
+            if (kernel == LABFM_KERNEL_STAGE)
+              return launch_stage<P>(c, ops, w, q, nullptr, out, nullptr, 0.0, 1.0, fl, st);
+            if (kernel == LABFM_KERNEL_FILTER) return launch_filter<P>(c, ops, w, q, out, st);
+            // apply: the five derivative operators of u
+            return launch_apply<P>(c, ops, w, 0x1F, q + n, out, st);
+          });
+        };
+        err = launch();  // warm-up
+        if (err == hipSuccess) err = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        const double mean = static_cast<double>(ms) / reps;
+        if (err == hipSuccess && mean < bms) {
+          bms = mean;
+          bc = c;
+        }
+      }
+    }
+    if (err == hipSuccess) {
+      best[kernel].lanes_per_node = bc.lpn;
+      best[kernel].flags = bc.flags;
+      best_ms[kernel] = bms;
+      std::lock_guard<std::mutex> lock(g_cfg_mutex);
+      g_cfg[kernel][prec_slot(prec)] = best[kernel];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LABFM_HIP(err);
   return LABFM_OK;
 }

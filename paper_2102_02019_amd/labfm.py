@@ -15,12 +15,15 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblabfm.so")
+# the in-tree build; LABFM_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("LABFM_LIBRARY") or os.path.join(_HERE, "liblabfm.so")
 
 OPS = ("x", "y", "L", "xx", "xy", "hyp")
 OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
-F64, F32_COMP = 0, 2
+F64, F32W, F32_COMP = 0, 1, 2
 
+KERNEL_STAGE, KERNEL_FILTER, KERNEL_APPLY = 0, 1, 2
+XCD_ORDER, STREAMING = 1, 2
 OK, ERR_ARG, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 NODE_OK, NODE_SINGULAR, NODE_FEW_NEIGHBOURS, NODE_BAD_FILTER, NODE_BAD_ORDER = range(5)
 
@@ -50,6 +53,10 @@ class _RKParams(ctypes.Structure):
                 ("check_finite", ctypes.c_int32)]
 
 
+class _LaunchConfig(ctypes.Structure):
+    _fields_ = [("lanes_per_node", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
 class _Timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("filter_ms", ctypes.c_double),
                 ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64)]
@@ -70,6 +77,13 @@ _SIGNATURES = {
     "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
                                     ctypes.c_int, _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "labfm_get_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                               ctypes.c_int64, ctypes.POINTER(_LaunchConfig)]),
+    "labfm_set_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int,
+                                               ctypes.POINTER(_LaunchConfig)]),
+    "labfm_tune": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, ctypes.c_int, ctypes.c_int32, _P,
+                                  ctypes.c_size_t, ctypes.POINTER(_LaunchConfig),
+                                  ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_rk_step": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams),
                                      ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _P,
                                      ctypes.c_size_t, ctypes.POINTER(_Timing), _P]),
@@ -246,3 +260,30 @@ def rk_step(q: torch.Tensor, ops: Operators, flow, dt: float, n_steps: int, prec
         return {"stage_ms": tm.stage_ms, "filter_ms": tm.filter_ms,
                 "stage_launches": tm.stage_launches, "filter_launches": tm.filter_launches}
     return None
+
+
+def get_launch_config(kernel: int, prec: int, n: int, nnz: int) -> tuple:
+    c = _LaunchConfig()
+    _check(lib().labfm_get_launch_config(kernel, prec, n, nnz, ctypes.byref(c)))
+    return c.lanes_per_node, c.flags
+
+
+def set_launch_config(kernel: int, prec: int, lanes_per_node: int = 0, flags: int = 0) -> None:
+    """Pin a launch shape (lanes_per_node = 0 restores the built-in choice)."""
+    c = _LaunchConfig(lanes_per_node, flags)
+    _check(lib().labfm_set_launch_config(kernel, prec, ctypes.byref(c)))
+
+
+def tune(ops: Operators, q: torch.Tensor, prec: int = F64, reps: int = 10,
+         workspace: Optional[torch.Tensor] = None) -> dict:
+    """Time every launch shape of the stage, filter and apply kernels and
+    install the fastest; returns {kernel: (lanes_per_node, flags, ms)}."""
+    if workspace is None:
+        workspace = rk_workspace(ops.n, q.device)
+    best = (_LaunchConfig * 3)()
+    ms = (ctypes.c_double * 3)()
+    c = ops._c()
+    _check(lib().labfm_tune(ctypes.byref(c), _ptr(q), prec, reps, _ptr(workspace),
+                            workspace.numel(), best, ms, _stream()))
+    names = ("stage", "filter", "apply")
+    return {names[k]: (best[k].lanes_per_node, best[k].flags, ms[k]) for k in range(3)}

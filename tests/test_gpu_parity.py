@@ -433,3 +433,93 @@ def test_full_size_rk_stable_and_decays(dev, tg512):
     decay = math.exp(-2 * prm.mu * dt * 100)
     assert np.max(np.abs(g[1])) == pytest.approx(np.max(np.abs(u)) * decay, rel=2e-3)
     assert np.max(np.abs(g[0])) < 0.02
+
+
+# ------------------------------------------------------- float32 weight paths
+
+def test_f32_paths_operator_error(dev, tg64):
+    """float32 weights: operator outputs within 1e-5 relative of the FP64
+    oracle. As properties of the kernels' arithmetic on their own float32
+    inputs (the stored float32 weights, read back): the float32-weight /
+    float64-sum path equals the float64 sum of those weights times the float64
+    differences, and the compensated float32 path (Dot2) equals the float64
+    sum of those weights times the float32-rounded differences to a few
+    float32 units."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, W = tg64
+    rp, col = W["row_ptr"], W["col"]
+    rows = np.repeat(np.arange(nodes.n), np.diff(rp))
+    w32_gpu = ops.w32.cpu().numpy().astype(np.float64)
+    for name, phi in _fields(nodes).items():
+        f32w = labfm.apply_operators(ops, T(phi, dev), 0x3F, labfm.F32W).cpu().numpy()
+        f32c = labfm.apply_operators(ops, T(phi, dev), 0x3F, labfm.F32_COMP).cpu().numpy()
+        dphi64 = phi[col] - phi[rows]
+        dphi32 = dphi64.astype(np.float32).astype(np.float64)
+        for d in range(5):
+            ref = O.apply_op(rp, col, W["w"][d], phi)
+            assert rel(f32w[d], ref) <= 1e-5, (name, d)
+            assert rel(f32c[d], ref) <= 1e-5, (name, d)
+            sum_w = np.bincount(rows, weights=w32_gpu[d] * dphi64, minlength=nodes.n)
+            assert rel(f32w[d], sum_w) <= 1e-12, (name, d)
+            sum_c = np.bincount(rows, weights=w32_gpu[d] * dphi32, minlength=nodes.n)
+            assert rel(f32c[d], sum_c) <= 3e-8, (name, d)
+
+
+@pytest.mark.parametrize("prec_name", ["F32W", "F32_COMP"])
+def test_f32_rk_close_to_f64(dev, tg64, prec_name):
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, W = tg64
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    q0 = np.concatenate([l, u, v])
+    q64, q32 = T(q0, dev), T(q0, dev)
+    labfm.rk_step(q64, ops, prm, dt, 20)
+    labfm.rk_step(q32, ops, prm, dt, 20, prec=getattr(labfm, prec_name))
+    errs = _compare_state(q32.cpu().numpy(), q64.cpu().numpy().reshape(3, -1))
+    assert max(errs) <= 1e-6, errs
+
+
+@pytest.mark.parametrize("lpn", [4, 8, 16, 32])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_every_launch_shape_agrees(dev, tg64, lpn, flags):
+    """Each launch shape computes the same right-hand side (summation order
+    differs, so to rounding) as the default."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    q = T(np.concatenate([l, u, v]), dev)
+    ref = labfm.ns_rhs(q, ops, prm).cpu().numpy()
+    try:
+        labfm.set_launch_config(labfm.KERNEL_STAGE, labfm.F64, lpn, flags)
+        got = labfm.ns_rhs(q, ops, prm).cpu().numpy()
+        labfm.set_launch_config(labfm.KERNEL_APPLY, labfm.F64, lpn, flags)
+        phi = T(_fields(nodes)["mixed"], dev)
+        a = labfm.apply_operators(ops, phi, 0x3F).cpu().numpy()
+    finally:
+        labfm.set_launch_config(labfm.KERNEL_STAGE, labfm.F64, 0, 0)
+        labfm.set_launch_config(labfm.KERNEL_APPLY, labfm.F64, 0, 0)
+    b = labfm.apply_operators(ops, phi, 0x3F).cpu().numpy()
+    assert rel(got, ref) <= 1e-13
+    assert rel(a, b) <= 1e-13
+
+
+def test_tuner_installs_a_valid_shape(dev, tg64):
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    l, u, v = _tg_state(nodes)
+    q = T(np.concatenate([l, u, v]), dev)
+    try:
+        best = labfm.tune(ops, q, labfm.F64, reps=3)
+        for k, (lpn, fl, ms) in best.items():
+            assert lpn in (4, 8, 16, 32) and 0 <= fl <= 3 and ms > 0
+        cfg = labfm.get_launch_config(labfm.KERNEL_STAGE, labfm.F64, ops.n, ops.nnz)
+        assert cfg == best["stage"][:2]
+    finally:
+        for k in range(3):
+            labfm.set_launch_config(k, labfm.F64, 0, 0)
