@@ -84,6 +84,19 @@ typedef struct {
   int32_t periodic_x, periodic_y;
 } labfm_box;
 
+/* Node tiles for the LDS-staged gather kernels (labfm_build_tiles): tile t
+ * holds nodes [t*LABFM_TILE_NODES, (t+1)*LABFM_TILE_NODES); its halo is the
+ * ascending list of distinct neighbour indices of its rows. */
+#define LABFM_TILE_NODES 64
+#define LABFM_TILE_HALO_MAX 1024
+typedef struct {
+  int32_t ntiles;             /* labfm_tile_count(n) */
+  int32_t max_halo;           /* largest halo of any tile */
+  const int32_t* halo_count;  /* int32[ntiles] */
+  const int32_t* halo_idx;    /* int32[ntiles * LABFM_TILE_HALO_MAX] */
+  const uint16_t* lcol;       /* uint16[nnz]: position of col[e] in its tile's halo */
+} labfm_tiles;
+
 /* Operators of a node set, as built by labfm_build_weights. */
 typedef struct {
   int32_t n;                /* nodes */
@@ -94,6 +107,9 @@ typedef struct {
                                when only the float32 copy is used) */
   const float* w32;         /* float32[6*nnz] or NULL */
   const double* kappa;      /* float64[n] filter coefficients */
+  const labfm_tiles* tiles; /* host pointer to tiles, or NULL: when set, the
+                               stage and filter kernels of labfm_rk_step and
+                               labfm_ns_rhs stage each tile's halo in LDS */
 } labfm_operators;
 
 /* Constants of the isothermal flow and of the integration. */
@@ -266,6 +282,24 @@ int labfm_set_launch_config(int32_t kernel, labfm_prec prec, const labfm_launch_
 int labfm_tune(const labfm_operators* ops, const double* q, labfm_prec prec, int32_t reps,
                void* workspace, size_t workspace_bytes, labfm_launch_config* best,
                double* best_ms, void* stream);
+
+/* Number of node tiles of a node set of n nodes. */
+int32_t labfm_tile_count(int32_t n);
+
+/*
+ * Builds the node tiles of a CSR stencil set (a data layout for the gather
+ * kernels; it changes no result beyond summation order).
+ *
+ *   halo_count   int32[labfm_tile_count(n)] output.
+ *   halo_idx     int32[labfm_tile_count(n) * LABFM_TILE_HALO_MAX] output.
+ *   lcol         uint16[nnz] output.
+ *   max_halo_out host: largest halo.
+ * Synchronises. Returns LABFM_ERR_CAPACITY if a tile's halo exceeds
+ * LABFM_TILE_HALO_MAX nodes (then use the operators without tiles).
+ */
+int labfm_build_tiles(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz,
+                      int32_t* halo_count, int32_t* halo_idx, uint16_t* lcol,
+                      int32_t* max_halo_out, void* stream);
 
 /* Bytes of device workspace labfm_rk_step needs for n nodes. */
 size_t labfm_rk_workspace_bytes(int32_t n);

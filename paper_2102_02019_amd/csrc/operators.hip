@@ -202,6 +202,37 @@ struct Flow {
   double c2, mu, gx, gy;
 };
 
+// Right-hand side of eq. icns at one node from its operator sums
+// D = (l_x, l_y, u_x, u_y, Lu, u_xx, u_xy, v_x, v_y, Lv, v_xx, v_xy), and the
+// two-register update: Y' = q + dta F (when Yout is set), q <- q + dtb F.
+// 4/3 u_xx + u_yy = L u + u_xx/3 and 4/3 v_yy + v_xx = L v + v_yy/3 with
+// v_yy = L v - v_xx. qin == nullptr evaluates the right-hand side alone.
+__device__ __forceinline__ void stage_update(int node, int n, double li, double ui, double vi,
+                                             const double* D, const double* qin, double* qout,
+                                             double* Yout, double dta, double dtb,
+                                             const Flow& fl) {
+  const double Lx = D[0], Ly = D[1], Ux = D[2], Uy = D[3], UL = D[4], Uxx = D[5], Uxy = D[6];
+  const double Vx = D[7], Vy = D[8], VL = D[9], Vxx = D[10], Vxy = D[11];
+  const double nu = fl.mu / exp(li);
+  const double third = 1.0 / 3.0;
+  const double rl = -(ui * Lx + vi * Ly) - (Ux + Vy);
+  const double ru = -(ui * Ux + vi * Uy) - fl.c2 * Lx + nu * (UL + third * (Uxx + Vxy)) + fl.gx;
+  const double rv =
+      -(ui * Vx + vi * Vy) - fl.c2 * Ly + nu * (VL + third * ((VL - Vxx) + Uxy)) + fl.gy;
+  const long long n2 = 2 * static_cast<long long>(n);
+  const double ql = qin ? qin[node] : 0.0;
+  const double qu = qin ? qin[n + node] : 0.0;
+  const double qv = qin ? qin[n2 + node] : 0.0;
+  if (Yout) {
+    Yout[node] = ql + dta * rl;
+    Yout[n + node] = qu + dta * ru;
+    Yout[n2 + node] = qv + dta * rv;
+  }
+  qout[node] = ql + dtb * rl;
+  qout[n + node] = qu + dtb * ru;
+  qout[n2 + node] = qv + dtb * rv;
+}
+
 // Stage of the two-register scheme. Y (gathered) holds the stage value, q the
 // solution. With F = R(Y):  Y' = q + dta F  (skipped when Yout is null),
 // q <- q + dtb F. qin and qout may be the same buffer; Y is never written.
@@ -295,27 +326,8 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   const double VL = vL.template reduce<LPN>(), Vxx = vxx.template reduce<LPN>();
   const double Vxy = vxy.template reduce<LPN>();
   if (sub != 0) return;
-  // right-hand side of eq. icns in (ln rho, u, v); 4/3 u_xx + u_yy = L u + u_xx/3
-  // and 4/3 v_yy + v_xx = L v + v_yy/3 with v_yy = L v - v_xx
-  const double nu = fl.mu / exp(li);
-  const double third = 1.0 / 3.0;
-  const double rl = -(ui * Lx + vi * Ly) - (Ux + Vy);
-  const double ru = -(ui * Ux + vi * Uy) - fl.c2 * Lx + nu * (UL + third * (Uxx + Vxy)) + fl.gx;
-  const double rv =
-      -(ui * Vx + vi * Vy) - fl.c2 * Ly + nu * (VL + third * ((VL - Vxx) + Uxy)) + fl.gy;
-  const long long n2 = 2 * static_cast<long long>(n);
-  // qin == nullptr evaluates the right-hand side alone (q taken as zero)
-  const double ql = qin ? qin[node] : 0.0;
-  const double qu = qin ? qin[n + node] : 0.0;
-  const double qv = qin ? qin[n2 + node] : 0.0;
-  if (Yout) {
-    Yout[node] = ql + dta * rl;
-    Yout[n + node] = qu + dta * ru;
-    Yout[n2 + node] = qv + dta * rv;
-  }
-  qout[node] = ql + dtb * rl;
-  qout[n + node] = qu + dtb * ru;
-  qout[n2 + node] = qv + dtb * rv;
+  const double sums[12] = {Lx, Ly, Ux, Uy, UL, Uxx, Uxy, Vx, Vy, VL, Vxx, Vxy};
+  stage_update(node, n, li, ui, vi, sums, qin, qout, Yout, dta, dtb, fl);
 }
 
 // --------------------------------------------------------------------------
@@ -379,6 +391,189 @@ filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   out[node] = li + k * sl;
   out[n + node] = ui + k * su;
   out[n2 + node] = vi + k * sv;
+}
+
+// --------------------------------------------------------------------------
+// LDS-staged (tiled) stage and filter kernels
+// --------------------------------------------------------------------------
+
+// One workgroup per tile of LABFM_TILE_NODES nodes. The gathered register's
+// values at the tile's halo are first copied into LDS (three arrays of hmax
+// doubles, dynamic shared memory); the tile's nodes are then processed
+// 256/LPN at a time, every neighbour value read from LDS through its 16-bit
+// halo position.
+struct Tiles {
+  const int* count;
+  const int* idx;
+  const unsigned short* lcol;
+  int hmax;
+};
+
+template <int FL>
+__device__ __forceinline__ int tile_of_block() {
+  return static_cast<int>((FL & kXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+}
+
+__device__ __forceinline__ void load_halo(const Tiles& tl, int t, const double* Y, int n,
+                                          double* sl, double* su, double* sv) {
+  const int hc = tl.count[t];
+  const int* idx = tl.idx + static_cast<long long>(t) * LABFM_TILE_HALO_MAX;
+  const long long n2 = 2 * static_cast<long long>(n);
+  for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+    const int g = idx[k];
+    sl[k] = Y[g];
+    su[k] = Y[n + g];
+    sv[k] = Y[n2 + g];
+  }
+  __syncthreads();
+}
+
+template <int LPN, int FL, class P>
+__global__ void __launch_bounds__(256)
+rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                      const typename P::W* __restrict__ w, long long nnz, const double* Y,
+                      const double* qin, double* qout, double* Yout, double dta, double dtb,
+                      Flow fl, int n) {
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, Y, n, sl, su, sv);
+  const typename P::W* wx = w + 0 * nnz;
+  const typename P::W* wy = w + 1 * nnz;
+  const typename P::W* wL = w + 2 * nnz;
+  const typename P::W* wxx = w + 3 * nnz;
+  const typename P::W* wxy = w + 4 * nnz;
+  constexpr int NPR = 256 / LPN;  // nodes per round
+  constexpr int U = unroll_of(LPN);
+  using W = typename P::W;
+  using D = typename P::D;
+  const int sub = threadIdx.x % LPN;
+#pragma unroll 1
+  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
+    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+    if (node >= n) break;  // whole LPN groups stop together
+    const double li = Y[node], ui = Y[n + node], vi = Y[2 * static_cast<long long>(n) + node];
+    typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
+    lx.zero(); ly.zero();
+    ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
+    vx.zero(); vy.zero(); vL.zero(); vxx.zero(); vxy.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    if (e1 > e0) {
+      for (int base = e0 + sub; base < e1; base += U * LPN) {
+        int ee[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * LPN;
+          ok[u] = e < e1;
+          ee[u] = ok[u] ? e : e1 - 1;
+        }
+        int jj[U];
+        W a[U], b[U], c[U], d[U], f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          jj[u] = stream_load<FL>(tl.lcol + ee[u]);
+          a[u] = stream_load<FL>(wx + ee[u]);
+          b[u] = stream_load<FL>(wy + ee[u]);
+          c[u] = stream_load<FL>(wL + ee[u]);
+          d[u] = stream_load<FL>(wxx + ee[u]);
+          f[u] = stream_load<FL>(wxy + ee[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const W z = W(0);
+          const W au = ok[u] ? a[u] : z, bu = ok[u] ? b[u] : z, cu = ok[u] ? c[u] : z;
+          const W du_ = ok[u] ? d[u] : z, fu = ok[u] ? f[u] : z;
+          const D dl = P::diff(sl[jj[u]], li);
+          const D du = P::diff(su[jj[u]], ui);
+          const D dv = P::diff(sv[jj[u]], vi);
+          lx.add(au, dl);
+          ly.add(bu, dl);
+          ux.add(au, du);
+          uy.add(bu, du);
+          uL.add(cu, du);
+          uxx.add(du_, du);
+          uxy.add(fu, du);
+          vx.add(au, dv);
+          vy.add(bu, dv);
+          vL.add(cu, dv);
+          vxx.add(du_, dv);
+          vxy.add(fu, dv);
+        }
+      }
+    }
+    const double Dv[12] = {lx.template reduce<LPN>(),  ly.template reduce<LPN>(),
+                           ux.template reduce<LPN>(),  uy.template reduce<LPN>(),
+                           uL.template reduce<LPN>(),  uxx.template reduce<LPN>(),
+                           uxy.template reduce<LPN>(), vx.template reduce<LPN>(),
+                           vy.template reduce<LPN>(),  vL.template reduce<LPN>(),
+                           vxx.template reduce<LPN>(), vxy.template reduce<LPN>()};
+    if (sub == 0) stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl);
+  }
+}
+
+template <int LPN, int FL, class P>
+__global__ void __launch_bounds__(256)
+filter_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                    const typename P::W* __restrict__ whyp, const double* __restrict__ kappa,
+                    const double* __restrict__ in, double* __restrict__ out, int n) {
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, in, n, sl, su, sv);
+  constexpr int NPR = 256 / LPN;
+  constexpr int U = unroll_of(LPN);
+  const int sub = threadIdx.x % LPN;
+  const long long n2 = 2 * static_cast<long long>(n);
+#pragma unroll 1
+  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
+    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+    if (node >= n) break;
+    const double li = in[node], ui = in[n + node], vi = in[n2 + node];
+    typename P::Acc al, au, av;
+    al.zero();
+    au.zero();
+    av.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    if (e1 > e0) {
+      for (int base = e0 + sub; base < e1; base += U * LPN) {
+        int ee[U], jj[U];
+        bool ok[U];
+        typename P::W a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * LPN;
+          ok[u] = e < e1;
+          ee[u] = ok[u] ? e : e1 - 1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          jj[u] = stream_load<FL>(tl.lcol + ee[u]);
+          a[u] = stream_load<FL>(whyp + ee[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const typename P::W wu = ok[u] ? a[u] : typename P::W(0);
+          al.add(wu, P::diff(sl[jj[u]], li));
+          au.add(wu, P::diff(su[jj[u]], ui));
+          av.add(wu, P::diff(sv[jj[u]], vi));
+        }
+      }
+    }
+    const double rl = al.template reduce<LPN>();
+    const double ru = au.template reduce<LPN>();
+    const double rv = av.template reduce<LPN>();
+    if (sub == 0) {
+      const double k = kappa[node];
+      out[node] = li + k * rl;
+      out[n + node] = ui + k * ru;
+      out[n2 + node] = vi + k * rv;
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -470,14 +665,14 @@ bool valid_cfg(const labfm_launch_config& c) {
          c.flags >= 0 && c.flags <= 3;
 }
 
-// Default variant from the mean row length K (measured on MI355X at K ~ 90:
-// the float64 stage runs best with 32 lanes per node, the float32 stages and
-// every filter pass with fewer); overridden per kernel and precision by
-// labfm_set_launch_config or labfm_tune.
+// Default variant from the mean row length K (measured on MI355X at K ~ 90,
+// tiled kernels: 16 lanes per node for the stage, 8 for the filter pass);
+// overridden per kernel and precision by labfm_set_launch_config or
+// labfm_tune.
 LaunchCfg default_cfg(int kernel, labfm_prec prec, int n, long long nnz) {
+  (void)prec;
   const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
   int lpn = k > 48.0 ? 16 : (k > 12.0 ? 8 : 4);
-  if (kernel == LABFM_KERNEL_STAGE && prec == LABFM_F64 && k > 48.0) lpn = 32;
   if (kernel == LABFM_KERNEL_FILTER && k > 48.0) lpn = 8;
   return LaunchCfg{lpn, 0};
 }
@@ -506,11 +701,25 @@ hipError_t launch_apply(LaunchCfg cfg, const labfm_operators* o, const typename 
   });
 }
 
+Tiles tiles_of(const labfm_operators* o) {
+  const labfm_tiles* t = o->tiles;
+  return Tiles{t->halo_count, t->halo_idx, t->lcol, t->max_halo > 0 ? t->max_halo : 1};
+}
+
 template <class P>
 hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                         const double* Y, const double* qin, double* qout, double* Yout, double dta,
                         double dtb, const Flow& fl, hipStream_t st) {
   const int n = o->n;
+  if (o->tiles) {
+    const Tiles tl = tiles_of(o);
+    const size_t shmem = 3 * sizeof(double) * tl.hmax;
+    return with_cfg(cfg, [&](auto L, auto F) {
+      hipLaunchKernelGGL((rk_stage_tiled_kernel<decltype(L)::value, decltype(F)::value, P>),
+                         dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w,
+                         static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n);
+    });
+  }
   const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((rk_stage_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
@@ -523,8 +732,17 @@ template <class P>
 hipError_t launch_filter(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                          const double* in, double* out, hipStream_t st) {
   const int n = o->n;
-  const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   const typename P::W* whyp = w + LABFM_OP_HYP * o->nnz;
+  if (o->tiles) {
+    const Tiles tl = tiles_of(o);
+    const size_t shmem = 3 * sizeof(double) * tl.hmax;
+    return with_cfg(cfg, [&](auto L, auto F) {
+      hipLaunchKernelGGL((filter_tiled_kernel<decltype(L)::value, decltype(F)::value, P>),
+                         dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, whyp,
+                         o->kappa, in, out, n);
+    });
+  }
+  const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((filter_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
                        dim3(kThreads), 0, st, o->row_ptr, o->col, whyp, o->kappa, in, out, n);
@@ -642,6 +860,13 @@ int check_ops(const labfm_operators* o, labfm_prec prec, const char* who) {
   LABFM_REQUIRE(known_prec(prec), "%s: unknown precision %d", who, (int)prec);
   if (prec == LABFM_F64) LABFM_REQUIRE(o->w, "%s: float64 weights required", who);
   if (prec != LABFM_F64) LABFM_REQUIRE(o->w32, "%s: float32 weights required", who);
+  if (o->tiles) {
+    const labfm_tiles* t = o->tiles;
+    LABFM_REQUIRE(t->ntiles == labfm_tile_count(o->n) && t->halo_count && t->halo_idx &&
+                      (t->lcol || o->nnz == 0) && t->max_halo >= 0 &&
+                      t->max_halo <= LABFM_TILE_HALO_MAX,
+                  "%s: inconsistent tiles", who);
+  }
   return LABFM_OK;
 }
 

@@ -39,11 +39,17 @@ class _Box(ctypes.Structure):
                 ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32)]
 
 
+class _Tiles(ctypes.Structure):
+    _fields_ = [("ntiles", ctypes.c_int32), ("max_halo", ctypes.c_int32),
+                ("halo_count", ctypes.c_void_p), ("halo_idx", ctypes.c_void_p),
+                ("lcol", ctypes.c_void_p)]
+
+
 class _Operators(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("w32", ctypes.c_void_p),
-                ("kappa", ctypes.c_void_p)]
+                ("kappa", ctypes.c_void_p), ("tiles", ctypes.POINTER(_Tiles))]
 
 
 class _RKParams(ctypes.Structure):
@@ -76,6 +82,9 @@ _SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
                                     ctypes.c_int, _P]),
+    "labfm_tile_count": (ctypes.c_int32, [ctypes.c_int32]),
+    "labfm_build_tiles": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
+                                         ctypes.POINTER(ctypes.c_int32), _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_get_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                                ctypes.c_int64, ctypes.POINTER(_LaunchConfig)]),
@@ -168,6 +177,9 @@ class Operators:
     kappa: torch.Tensor             # float64 (n,)
     rowsum: Optional[torch.Tensor] = None
     status: Optional[torch.Tensor] = None
+    # node tiles (labfm_build_tiles): halo_count, halo_idx, lcol, max_halo
+    tiles: Optional[tuple] = None
+    use_tiles: bool = True
 
     @property
     def n(self) -> int:
@@ -178,15 +190,22 @@ class Operators:
         return int(self.col.numel())
 
     def _c(self) -> _Operators:
+        tp = None
+        if self.tiles is not None and self.use_tiles:
+            hc, hi, lc, hmax = self.tiles
+            self._ctiles = _Tiles(hc.numel(), hmax, _ptr(hc).value, _ptr(hi).value,
+                                  _ptr(lc).value)
+            tp = ctypes.pointer(self._ctiles)
         return _Operators(self.n, self.nnz, _ptr(self.row_ptr).value, _ptr(self.col).value,
                           None if self.w is None else _ptr(self.w).value,
                           None if self.w32 is None else _ptr(self.w32).value,
-                          _ptr(self.kappa).value)
+                          _ptr(self.kappa).value, tp)
 
 
 def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
-                  rowsum: bool = False) -> Operators:
-    """Weights of the six operators, filter coefficients and node status."""
+                  rowsum: bool = False, tiles: bool = True) -> Operators:
+    """Weights of the six operators, filter coefficients and node status;
+    with ``tiles`` also the node tiles used by the LDS-staged kernels."""
     n = x.numel()
     nnz = col.numel()
     dev = x.device
@@ -203,7 +222,34 @@ def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
                                      _ptr(row_ptr), _ptr(col), nnz, _ptr(w), _ptr(w32),
                                      _ptr(kappa), _ptr(rs), _ptr(status), _stream())
     _check(code)
-    return Operators(row_ptr, col, w, w32, kappa, rs, status)
+    ops = Operators(row_ptr, col, w, w32, kappa, rs, status)
+    if tiles:
+        build_tiles(ops)
+    return ops
+
+
+TILE_NODES = 64
+TILE_HALO_MAX = 1024
+
+
+def build_tiles(ops: Operators) -> bool:
+    """Build the node tiles of ops' stencils (LDS-staged gathers in the RK
+    stage and filter). Returns False, leaving ops untiled, when a tile's halo
+    exceeds TILE_HALO_MAX."""
+    n, nnz, dev = ops.n, ops.nnz, ops.row_ptr.device
+    nt = lib().labfm_tile_count(n)
+    hc = torch.empty(nt, dtype=torch.int32, device=dev)
+    hi = torch.empty(nt * TILE_HALO_MAX, dtype=torch.int32, device=dev)
+    lc = torch.empty(max(1, nnz), dtype=torch.int16, device=dev)
+    hmax = ctypes.c_int32(0)
+    code = lib().labfm_build_tiles(_ptr(ops.row_ptr), _ptr(ops.col), n, nnz, _ptr(hc), _ptr(hi),
+                                   _ptr(lc), ctypes.byref(hmax), _stream())
+    if code == ERR_CAPACITY:
+        ops.tiles = None
+        return False
+    _check(code)
+    ops.tiles = (hc, hi, lc, hmax.value)
+    return True
 
 
 def apply_operators(ops: Operators, phi: torch.Tensor, op_mask: int = 0x3F,

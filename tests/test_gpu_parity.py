@@ -523,3 +523,47 @@ def test_tuner_installs_a_valid_shape(dev, tg64):
     finally:
         for k in range(3):
             labfm.set_launch_config(k, labfm.F64, 0, 0)
+
+
+# ------------------------------------------------------------- node tiles
+
+def test_tiles_map_back_to_the_stencils(dev, tg64):
+    """Each tile's halo is the sorted set of its rows' neighbours, and every
+    16-bit position points back at the original neighbour index."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    assert ops.tiles is not None
+    hc, hi, lc, hmax = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in ops.tiles)
+    rp = ops.row_ptr.cpu().numpy()
+    col = ops.col.cpu().numpy()
+    lc = lc.astype(np.int64) & 0xFFFF
+    T_ = labfm.TILE_NODES
+    assert hc.max() == hmax
+    for t in range(hc.size):
+        a, b = rp[t * T_], rp[min(nodes.n, (t + 1) * T_)]
+        halo = hi[t * labfm.TILE_HALO_MAX: t * labfm.TILE_HALO_MAX + hc[t]]
+        assert np.array_equal(halo, np.unique(col[a:b]))
+        assert np.array_equal(halo[lc[a:b]], col[a:b])
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "F32W", "F32_COMP"])
+def test_tiled_kernels_bitwise_equal_untiled(dev, tg64, prec_name):
+    """Staging the halo in LDS changes where values are read from, not the
+    order of any sum: results are bitwise identical."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    prec = getattr(labfm, prec_name)
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    q0 = np.concatenate([l, u, v])
+    outs = []
+    for use in (True, False):
+        ops.use_tiles = use
+        q = T(q0, dev)
+        labfm.rk_step(q, ops, prm, 0.008, 4, prec=prec)
+        r = labfm.ns_rhs(q, ops, prm, prec)
+        outs.append((q.cpu().numpy(), r.cpu().numpy()))
+    ops.use_tiles = True
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
