@@ -301,6 +301,46 @@ int labfm_build_tiles(const int32_t* row_ptr, const int32_t* col, int32_t n, int
                       int32_t* halo_count, int32_t* halo_idx, uint16_t* lcol,
                       int32_t* max_halo_out, void* stream);
 
+/* Transposed stencils for the adjoint: for each node j the forward edges
+ * i -> j (j in N_i), grouped by j in ascending i, with a copy of their
+ * weights, plus the operators' row sums S^d_i = sum_j w^d_ij. */
+typedef struct {
+  const int32_t* tptr;   /* int32[n+1] */
+  const int32_t* tsrc;   /* int32[nnz]: source node i of each entry */
+  const double* tw;      /* float64[6*nnz]: w^d_ij of each entry, labfm_op order */
+  const double* rowsum;  /* float64[6*n] (labfm_build_weights' rowsum output) */
+} labfm_transpose;
+
+/*
+ * Builds tptr, tsrc and tw from the operators' CSR and float64 weights
+ * (a reordering of data, no arithmetic). Synchronises; allocates and frees
+ * temporaries.
+ */
+int labfm_build_transpose(const labfm_operators* ops, int32_t* tptr, int32_t* tsrc, double* tw,
+                          void* stream);
+
+/* Bytes of workspace labfm_rk_adjoint needs. */
+size_t labfm_adjoint_workspace_bytes(int32_t n, int32_t n_steps, int32_t ckpt_every);
+
+/*
+ * Adjoint (vector-Jacobian product) of n_steps steps of labfm_rk_step in
+ * float64, with the filter when prm->filter is set: given qbar_end, the
+ * gradient of a scalar J with respect to the state after n_steps, writes
+ * qbar_0 = (d q_end / d q_0)^T qbar_end, the gradient with respect to q0.
+ * Operators enter through their transposes A_d^T (gathers over the
+ * transposed stencils, no atomics); the state is checkpointed every
+ * ckpt_every steps and each segment recomputed once.
+ *
+ *   q0, qbar_end, qbar_0  float64[3n] ([ln rho | u | v]); qbar_0 may alias
+ *                         qbar_end.
+ *   workspace             labfm_adjoint_workspace_bytes(n, n_steps,
+ *                         ckpt_every) bytes.
+ */
+int labfm_rk_adjoint(const double* q0, const double* qbar_end, double* qbar_0,
+                     const labfm_operators* ops, const labfm_transpose* tr,
+                     const labfm_rk_params* prm, int32_t n_steps, int32_t ckpt_every,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
 /* Bytes of device workspace labfm_rk_step needs for n nodes. */
 size_t labfm_rk_workspace_bytes(int32_t n);
 

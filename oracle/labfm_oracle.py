@@ -481,3 +481,101 @@ def ns_rhs_at(lnrho, u, v, x, y, h, s, m, row_ptr, col, box, prm, nodes) -> np.n
         out[2, k] = (-(u[i] * vx + v[i] * vy) - prm.c2 * ly
                      + nu * (4.0 / 3.0 * (vL - vxx) + vxx + 1.0 / 3.0 * uxy) + prm.gy)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Adjoint (reverse mode) of the filtered RK time loop
+# ---------------------------------------------------------------------------
+
+def operator_matrices(W: dict) -> list:
+    """A_d = [w^d_ij] - diag(sum_j w^d_ij): L^d(phi) = A_d phi, as scipy CSR."""
+    from scipy import sparse
+
+    rp, col, w = W["row_ptr"], W["col"], W["w"]
+    N = rp.size - 1
+    mats = []
+    for d in range(6):
+        Wd = sparse.csr_matrix((w[d], col, rp), shape=(N, N))
+        S = np.asarray(Wd.sum(axis=1)).ravel()
+        mats.append((Wd - sparse.diags(S)).tocsr())
+    return mats
+
+
+def ns_rhs_vjp(lnrho, u, v, W: dict, prm, rbar: tuple, mats=None) -> tuple:
+    """Vector-Jacobian product of ns_rhs: given adjoints (Rl, Ru, Rv) of the
+    right-hand side, the adjoints of (ln rho, u, v). Derived by hand from the
+    expressions of ns_rhs; operator adjoints are the transposes A_d^T."""
+    if mats is None:
+        mats = operator_matrices(W)
+    A = mats
+    Rl, Ru, Rv = rbar
+    lx, ly = A[OP_X] @ lnrho, A[OP_Y] @ lnrho
+    ux, uy, uL, uxx, uxy = (A[d] @ u for d in (OP_X, OP_Y, OP_L, OP_XX, OP_XY))
+    vx, vy, vL, vxx, vxy = (A[d] @ v for d in (OP_X, OP_Y, OP_L, OP_XX, OP_XY))
+    uyy = uL - uxx
+    vyy = vL - vxx
+    nu = prm.mu / np.exp(lnrho)
+    visc_u = 4.0 / 3.0 * uxx + uyy + 1.0 / 3.0 * vxy
+    visc_v = 4.0 / 3.0 * vyy + vxx + 1.0 / 3.0 * uxy
+    # adjoints of the derivative fields
+    b_lx = -u * Rl - prm.c2 * Ru
+    b_ly = -v * Rl - prm.c2 * Rv
+    b_ux = -Rl - u * Ru
+    b_uy = -v * Ru
+    b_uxx = nu * Ru * (4.0 / 3.0)
+    b_uyy = nu * Ru
+    b_vxy = nu * Ru / 3.0
+    b_vx = -u * Rv
+    b_vy = -Rl - v * Rv
+    b_vyy = nu * Rv * (4.0 / 3.0)
+    b_vxx = nu * Rv
+    b_uxy = nu * Rv / 3.0
+    # uyy = uL - uxx, vyy = vL - vxx
+    b_uL = b_uyy
+    b_uxx = b_uxx - b_uyy
+    b_vL = b_vyy
+    b_vxx = b_vxx - b_vyy
+    T = lambda d, g: A[d].T @ g  # noqa: E731
+    lbar = T(OP_X, b_lx) + T(OP_Y, b_ly) - nu * (Ru * visc_u + Rv * visc_v)
+    ubar = (T(OP_X, b_ux) + T(OP_Y, b_uy) + T(OP_L, b_uL) + T(OP_XX, b_uxx) + T(OP_XY, b_uxy)
+            - Rl * lx - Ru * ux - Rv * vx)
+    vbar = (T(OP_X, b_vx) + T(OP_Y, b_vy) + T(OP_L, b_vL) + T(OP_XX, b_vxx) + T(OP_XY, b_vxy)
+            - Rl * ly - Ru * uy - Rv * vy)
+    return lbar, ubar, vbar
+
+
+def rk_adjoint(lnrho, u, v, W: dict, prm, dt: float, n_steps: int, qbar: tuple,
+               filt: bool = True) -> tuple:
+    """Adjoint of rk_run: given the adjoint of the state after n_steps, the
+    adjoint of the initial state. Written on the full Butcher tableau
+    Y_i = q + dt sum_{j<i} a_ij F_j, q' = q + dt sum_i b_i F_i, q+ = filter(q'):
+        qbar' = (I + diag(kappa) A_hyp)^T qbar+,
+        Fbar_i = dt (b_i qbar' + sum_{k>i} a_ki Ybar_k),  Ybar_i = J_R(Y_i)^T Fbar_i,
+        qbar = qbar' + sum_i Ybar_i,
+    with every forward state stored."""
+    mats = operator_matrices(W)
+    A, b, _ = butcher_tableau()
+    Af = [[float(a) for a in row] for row in A]
+    bf = [float(x) for x in b]
+    kappa = W["kappa"]
+    rhs = lambda l_, u_, v_: ns_rhs(l_, u_, v_, W, prm)  # noqa: E731
+    states = [tuple(np.array(f, dtype=float) for f in (lnrho, u, v))]
+    for _ in range(n_steps):
+        states.append(rk_run(*states[-1], W, prm, dt, 1, filt=filt))
+    qb = tuple(np.array(f, dtype=float) for f in qbar)
+    for k in range(n_steps - 1, -1, -1):
+        q = states[k]
+        Y, F = [], []
+        for i in range(4):
+            Yi = tuple(q[f] + dt * sum(Af[i][j] * F[j][f] for j in range(i)) for f in range(3))
+            Y.append(Yi)
+            F.append(rhs(*Yi))
+        if filt:
+            qb = tuple(g + mats[OP_HYP].T @ (kappa * g) for g in qb)
+        Ybar = [None] * 4
+        for i in range(3, -1, -1):
+            Fb = tuple(dt * (bf[i] * qb[f] + sum(Af[k2][i] * Ybar[k2][f] for k2 in range(i + 1, 4)))
+                       for f in range(3))
+            Ybar[i] = ns_rhs_vjp(*Y[i], W, prm, Fb, mats)
+        qb = tuple(qb[f] + sum(Ybar[i][f] for i in range(4)) for f in range(3))
+    return qb

@@ -21,7 +21,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
-SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip"]
+SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip"]
 
 
 def _compile(src: str) -> str:

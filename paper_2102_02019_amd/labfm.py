@@ -63,6 +63,11 @@ class _LaunchConfig(ctypes.Structure):
     _fields_ = [("lanes_per_node", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
+class _Transpose(ctypes.Structure):
+    _fields_ = [("tptr", ctypes.c_void_p), ("tsrc", ctypes.c_void_p), ("tw", ctypes.c_void_p),
+                ("rowsum", ctypes.c_void_p)]
+
+
 class _Timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("filter_ms", ctypes.c_double),
                 ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64)]
@@ -85,6 +90,12 @@ _SIGNATURES = {
     "labfm_tile_count": (ctypes.c_int32, [ctypes.c_int32]),
     "labfm_build_tiles": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
                                          ctypes.POINTER(ctypes.c_int32), _P]),
+    "labfm_build_transpose": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, _P, _P, _P]),
+    "labfm_adjoint_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32,
+                                                        ctypes.c_int32]),
+    "labfm_rk_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_Operators),
+                                        ctypes.POINTER(_Transpose), ctypes.POINTER(_RKParams),
+                                        ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_get_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                                ctypes.c_int64, ctypes.POINTER(_LaunchConfig)]),
@@ -180,6 +191,8 @@ class Operators:
     # node tiles (labfm_build_tiles): halo_count, halo_idx, lcol, max_halo
     tiles: Optional[tuple] = None
     use_tiles: bool = True
+    # transposed stencils for the adjoint (labfm_build_transpose): tptr, tsrc, tw
+    transpose: Optional[tuple] = None
 
     @property
     def n(self) -> int:
@@ -333,3 +346,72 @@ def tune(ops: Operators, q: torch.Tensor, prec: int = F64, reps: int = 10,
                             workspace.numel(), best, ms, _stream()))
     names = ("stage", "filter", "apply")
     return {names[k]: (best[k].lanes_per_node, best[k].flags, ms[k]) for k in range(3)}
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+def build_transpose(ops: Operators) -> None:
+    """Transposed stencils and weights for the adjoint (needs ops.rowsum,
+    i.e. build_weights(..., rowsum=True))."""
+    if ops.rowsum is None:
+        raise ValueError("build_transpose needs the operators' row sums (rowsum=True)")
+    n, nnz, dev = ops.n, ops.nnz, ops.row_ptr.device
+    tptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    tsrc = torch.empty(max(1, nnz), dtype=torch.int32, device=dev)
+    tw = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)
+    c = ops._c()
+    _check(lib().labfm_build_transpose(ctypes.byref(c), _ptr(tptr), _ptr(tsrc), _ptr(tw),
+                                       _stream()))
+    ops.transpose = (tptr, tsrc, tw)
+
+
+def rk_adjoint(q0: torch.Tensor, qbar_end: torch.Tensor, ops: Operators, flow, dt: float,
+               n_steps: int, ckpt_every: int = 20, filter: bool = True) -> torch.Tensor:
+    """qbar_0 = (d q_end / d q0)^T qbar_end for n_steps filtered RK steps."""
+    if ops.transpose is None:
+        build_transpose(ops)
+    tptr, tsrc, tw = ops.transpose
+    tr = _Transpose(_ptr(tptr).value, _ptr(tsrc).value, _ptr(tw).value, _ptr(ops.rowsum).value)
+    nbytes = lib().labfm_adjoint_workspace_bytes(ops.n, n_steps, ckpt_every)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=q0.device)
+    prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
+                    float(getattr(flow, "gy", 0.0)), float(dt), int(filter), 0)
+    out = torch.empty_like(q0)
+    c = ops._c()
+    _check(lib().labfm_rk_adjoint(_ptr(q0), _ptr(qbar_end), _ptr(out), ctypes.byref(c),
+                                  ctypes.byref(tr), ctypes.byref(prm), int(n_steps),
+                                  int(ckpt_every), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+class RKSolve(torch.autograd.Function):
+    """(rho0, u0, v0) -> (rho, u, v) after n_steps filtered RK steps, with a
+    backward pass through labfm_rk_adjoint (checkpointed recomputation).
+
+    The library evolves ln rho; this wrapper converts rho <-> ln rho (and the
+    matching gradients) at the two ends of the solve."""
+
+    @staticmethod
+    def forward(ctx, rho0, u0, v0, ops, flow, dt, n_steps, ckpt_every=20, filter=True):
+        q0 = torch.cat([torch.log(rho0), u0, v0]).contiguous()
+        q = q0.clone()
+        rk_step(q, ops, flow, dt, n_steps, filter=filter)
+        n = ops.n
+        rho = torch.exp(q[:n])
+        ctx.save_for_backward(q0, rho)
+        ctx.cfg = (ops, flow, dt, n_steps, ckpt_every, filter)
+        return rho, q[n:2 * n].clone(), q[2 * n:].clone()
+
+    @staticmethod
+    def backward(ctx, grho, gu, gv):
+        q0, rho = ctx.saved_tensors
+        ops, flow, dt, n_steps, ckpt_every, filter = ctx.cfg
+        n = ops.n
+        z = torch.zeros(n, dtype=q0.dtype, device=q0.device)
+        qbar = torch.cat([(grho if grho is not None else z) * rho,
+                          gu if gu is not None else z, gv if gv is not None else z]).contiguous()
+        g0 = rk_adjoint(q0, qbar, ops, flow, dt, n_steps, ckpt_every, filter)
+        rho0 = torch.exp(q0[:n])
+        return (g0[:n] / rho0, g0[n:2 * n], g0[2 * n:], None, None, None, None, None, None)

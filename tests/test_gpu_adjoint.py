@@ -1,0 +1,173 @@
+"""The hand-written adjoint through the C ABI: against the oracle's adjoint
+(itself pinned by complex-step derivatives), independence from the checkpoint
+interval, and central finite differences on the adjoint workload
+(65,536 nodes, m = 6, 200 RK steps, checkpoints every 20)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import labfm_oracle as O
+from paper_2102_02019_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def setup(nodes, dev):
+    from paper_2102_02019_amd import labfm
+
+    x, y, h, s, m = (T(a, dev) for a in (nodes.x, nodes.y, nodes.h, nodes.s, nodes.m))
+    rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+    ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, rowsum=True)
+    labfm.build_transpose(ops)
+    return ops
+
+
+@pytest.fixture(scope="module")
+def small(dev):
+    nodes = inputs.jittered_lattice(24, seed=5, m=4)
+    ops = setup(nodes, dev)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, 4, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    prm = inputs.taylor_green_params()
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    l = np.log(rho) + 0.03 * np.sin(nodes.x - nodes.y)
+    return nodes, ops, W, prm, (l, u, v)
+
+
+@pytest.mark.parametrize("filt", [True, False])
+def test_adjoint_matches_oracle(dev, small, filt):
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, W, prm, q = small
+    dt = 0.5 * O.time_step(nodes.s, *q, prm)
+    n_steps = 5
+    rng = np.random.default_rng(3)
+    qbar = tuple(rng.standard_normal(nodes.n) for _ in range(3))
+    ref = O.rk_adjoint(*q, W, prm, dt, n_steps, qbar, filt=filt)
+    got = labfm.rk_adjoint(T(np.concatenate(q), dev), T(np.concatenate(qbar), dev), ops, prm, dt,
+                           n_steps, ckpt_every=2, filter=filt).cpu().numpy().reshape(3, -1)
+    for k in range(3):
+        assert rel(got[k], ref[k]) <= 1e-11, k
+
+
+def test_transpose_is_the_reordered_stencil(dev, small):
+    nodes, ops, _, _, _ = small
+    tptr, tsrc, tw = (t.cpu().numpy() for t in ops.transpose)
+    rp, col = ops.row_ptr.cpu().numpy(), ops.col.cpu().numpy()
+    w = ops.w.cpu().numpy()
+    nnz = col.size
+    fwd = {(i, col[e]): e for i in range(nodes.n) for e in range(rp[i], rp[i + 1])}
+    assert tptr[-1] == nnz
+    for j in range(nodes.n):
+        src = tsrc[tptr[j]:tptr[j + 1]]
+        assert np.all(np.diff(src) > 0)
+        for k, i in enumerate(src):
+            e = fwd[(i, j)]
+            for d in range(6):
+                assert tw[d * nnz + tptr[j] + k] == w[d, e]
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(dev, small):
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _, prm, q = small
+    rng = np.random.default_rng(4)
+    qbar = T(rng.standard_normal(3 * nodes.n), dev)
+    q0 = T(np.concatenate(q), dev)
+    outs = [labfm.rk_adjoint(q0, qbar, ops, prm, 0.01, 7, ckpt_every=c).cpu().numpy()
+            for c in (1, 3, 7, 20)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_autograd_function(dev, small):
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _, prm, q = small
+    rho0 = T(np.exp(q[0]), dev).requires_grad_(True)
+    u0 = T(q[1], dev).requires_grad_(True)
+    v0 = T(q[2], dev).requires_grad_(True)
+    rho, u, v = labfm.RKSolve.apply(rho0, u0, v0, ops, prm, 0.01, 4, 2)
+    J = (u * u).sum() + 0.5 * (v * rho).sum()
+    J.backward()
+    # directional derivative by central differences in float64
+    rng = np.random.default_rng(5)
+    d = [T(rng.standard_normal(nodes.n) * s, dev) for s in (1e-2, 1.0, 1.0)]
+    eps = 1e-6
+
+    def Jof(sign):
+        with torch.no_grad():
+            r, uu, vv = labfm.RKSolve.apply(rho0 + sign * eps * d[0], u0 + sign * eps * d[1],
+                                            v0 + sign * eps * d[2], ops, prm, 0.01, 4, 2)
+            return float((uu * uu).sum() + 0.5 * (vv * r).sum())
+
+    fd = (Jof(1) - Jof(-1)) / (2 * eps)
+    ad = float(sum((g.grad * dd).sum() for g, dd in zip((rho0, u0, v0), d)))
+    assert ad == pytest.approx(fd, rel=1e-6)
+
+
+def test_adjoint_workload_finite_differences(dev):
+    """65,536 nodes, m = 6, 200 steps, checkpoints every 20: the gradient of
+    J = (1/2N) sum (u - u*)^2 + (v - v*)^2 agrees with central differences
+    on 16 seeded directions."""
+    from paper_2102_02019_amd import labfm
+
+    wl = inputs.TG256_M6
+    nodes = wl.nodes()
+    ops = setup(nodes, dev)
+    prm = inputs.taylor_green_params()
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    dl, du, dv = inputs.fourier_perturbation(nodes.x, nodes.y, seed=wl.seed)
+    q_tg = np.concatenate([np.log(rho), u, v])
+    q_pert = np.concatenate([np.log(rho) + dl, u + du, v + dv])
+    s = T(nodes.s, dev)
+    dt = labfm.time_step(T(q_tg, dev), s, prm.c2, prm.mu)
+    steps = wl.steps
+    target = T(q_pert, dev)
+    labfm.rk_step(target, ops, prm, dt, steps)
+    N = nodes.n
+
+    def J(q0):
+        q = q0.clone()
+        labfm.rk_step(q, ops, prm, dt, steps)
+        e = q - target
+        return float(0.5 / N * ((e[N:] * e[N:]).sum()).item())
+
+    q0 = T(q_tg, dev)
+    q = q0.clone()
+    labfm.rk_step(q, ops, prm, dt, steps)
+    qbar = (q - target) / N
+    qbar[:N] = 0.0
+    g = labfm.rk_adjoint(q0, qbar.contiguous(), ops, prm, dt, steps, ckpt_every=20)
+    rng = np.random.default_rng(wl.seed)
+    # unit directions over 3N = 196,608 components: a step of 1e-3 moves each
+    # component by ~2e-6, so truncation is negligible and the difference of J
+    # stays far above its rounding noise
+    eps = 1e-3
+    worst = 0.0
+    for k in range(16):
+        d = rng.standard_normal(3 * N)
+        d /= np.linalg.norm(d)
+        dT = T(d, dev)
+        fd = (J(q0 + eps * dT) - J(q0 - eps * dT)) / (2 * eps)
+        ad = float((g * dT).sum().item())
+        worst = max(worst, abs(ad - fd) / max(abs(fd), 1e-300))
+    assert worst < 1e-5, worst
