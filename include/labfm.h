@@ -207,13 +207,46 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  * Numerical failures and out-of-range orders are reported per node in
  * status (the call still returns LABFM_OK); such nodes get zero weights and
  * kappa = 0 except for LABFM_NODE_FEW_NEIGHBOURS, whose weights are those of
- * the (rank-deficient) solve when it completes.
+ * the (rank-deficient) solve when it completes. Nodes of different orders and
+ * stencil sizes are built in one call; labfm_set_build_config selects how
+ * they are spread over the GPU (default: one workgroup per node, in a work
+ * list ordered by decreasing order; labfm_tune_build picks). Synchronises
+ * (it sizes its work list on the host) and allocates a small work list.
  */
 int labfm_build_weights(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* order_m, int32_t n, labfm_box box,
                         const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                         double* w, float* w32, double* kappa, double* rowsum,
                         int8_t* status, void* stream);
+
+/* How labfm_build_weights distributes nodes over the GPU. */
+enum {
+  LABFM_BUILD_WAVE = 1,        /* one 64-lane wavefront per node */
+  LABFM_BUILD_BLOCK = 2,       /* one 256-thread workgroup (4 wavefronts) per node
+                                  (the default) */
+  LABFM_BUILD_PERSISTENT = 3,  /* one launch of persistent 256-thread workgroups taking
+                                  nodes (highest order first) from a work counter */
+  LABFM_BUILD_BUCKETED = 4     /* one 256-thread-per-node launch per order class */
+};
+typedef struct {
+  int32_t mode;               /* LABFM_BUILD_*; default LABFM_BUILD_BLOCK */
+  int32_t workgroups_per_cu;  /* persistent mode: 0 = as many as fit */
+} labfm_build_config;
+
+/* Process-wide build distribution (NULL restores the default). */
+int labfm_set_build_config(const labfm_build_config* cfg);
+int labfm_get_build_config(labfm_build_config* cfg);
+
+/* Autotuner of the build: runs labfm_build_weights with every distribution
+ * on the given node set (same arguments and outputs), installs the fastest
+ * as the process-wide setting and reports it (best_ms: its duration,
+ * measured with HIP events on `stream`). The outputs hold the weights built
+ * with the chosen distribution. Synchronises. */
+int labfm_tune_build(const double* x, const double* y, const double* h, const double* s,
+                     const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
+                     const int32_t* col, int64_t nnz, double* w, float* w32, double* kappa,
+                     double* rowsum, int8_t* status, labfm_build_config* best, double* best_ms,
+                     void* stream);
 
 /*
  * Operator application, eq. general_do: for each selected operator d (bit d

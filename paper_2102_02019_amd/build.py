@@ -35,9 +35,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+NODEGEN_SRC = os.path.join(HERE, "hostsrc", "place_nodes.c")
+NODEGEN_LIB = os.path.join(HERE, "libnodegen.so")
+
+
+def build_nodegen() -> str:
+    """Host helper of the input generator (variable-resolution node sweep)."""
+    tmp = NODEGEN_LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", NODEGEN_SRC, "-o", tmp, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling {NODEGEN_SRC} failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, NODEGEN_LIB)
+    return NODEGEN_LIB
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source (always) and link liblabfm.so next to this file."""
     os.makedirs(OBJDIR, exist_ok=True)
+    build_nodegen()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

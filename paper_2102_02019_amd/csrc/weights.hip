@@ -17,7 +17,10 @@
 //      wave.
 // Hermite ABFs use the probabilists' polynomials He_a(x/h), which equal the
 // paper's H_a(x/(h sqrt 2)) / sqrt(2^a).
+#include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -385,6 +388,410 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Four wavefronts per node
+// ---------------------------------------------------------------------------
+//
+// The same steps with a 256-thread workgroup per node: wave 0 builds the
+// basis tables of 16 neighbours at a time; the four waves share the MFMA tiles
+// of M~ (tile t goes to wave t mod 4); the LU's trailing updates, the back
+// substitution and the weights run over all 256 threads; per-node sums are
+// reduced in a fixed order (bitwise reproducible). Used one workgroup per
+// node, or persistently: workgroups take node indices from a work list
+// (heaviest orders first) through an atomic counter until it is exhausted.
+
+struct BuildArgs {
+  const double* x;
+  const double* y;
+  const double* h;
+  const double* s;
+  const int8_t* order;
+  int n;
+  labfm_box box;
+  const int* row_ptr;
+  const int* col;
+  long long nnz;
+  double* w;
+  float* w32;
+  double* kappa;
+  double* rowsum;
+  int8_t* status;
+};
+
+constexpr int kBlock = 256;
+
+template <int MMAX>
+struct BlockSmem {
+  using S = Shape<MMAX>;
+  double A[S::NMAX * S::LDA];
+  double T[kChunk * S::TABLE];
+  double part[kChunk * 8];  // per-neighbour-slot partial sums (6 row sums, F0)
+  int qa[S::NMAX], qb[S::NMAX];
+  int piv;
+  int next;
+};
+
+// Every value that steers control flow around a barrier is made wave-uniform
+// with readfirstlane (all lanes hold the same value): with conditions the
+// compiler cannot prove uniform, it may structure the loops so that the
+// waves of the workgroup pass through different sequences of barriers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <int MMAX>
+__device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm) {
+  using S = Shape<MMAX>;
+  constexpr int TPW = (S::NB * S::NB + 3) / 4;  // MFMA tiles per wave
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int i = uniform(i_in);
+  const int m = uniform(g.order[i]);
+  const int e0 = uniform(g.row_ptr[i]);
+  const int K = uniform(g.row_ptr[i + 1]) - e0;
+  // one exit: every path below ends at the final barrier, and every branch
+  // around a barrier depends on wave-uniform values only
+  const bool valid = (m >= 1 && m <= MMAX);
+  bool singular = false;
+  if (valid) {
+  const int n = moments_of(m);
+  const int nb = (n + 15) / 16;
+  const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
+  const int px = g.box.periodic_x, py = g.box.periodic_y;
+  for (int p = tid; p < n; p += kBlock) exponents_of(p, sm.qa[p], sm.qb[p]);
+  __syncthreads();
+
+  // ---- basis tables and MFMA assembly --------------------------------------
+  int tP[TPW], tQ[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int t = wave + 4 * k;
+    tP[k] = (t < nb * nb) ? t / nb : -1;
+    tQ[k] = (t < nb * nb) ? t % nb : -1;
+  }
+  double4_t acc[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += kChunk) {
+    if (tid < 64) {
+      const int kk = lane >> 2, t = lane & 3;
+      const int k = k0 + kk;
+      double* tab = &sm.T[kk * S::TABLE + t * S::TW];
+      if (k < K) {
+        const int j = g.col[e0 + k];
+        const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
+        const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+        const double xs = dx / h, ys = dy / h;
+        const double z = (t == 0 || t == 2) ? xs : ys;
+        if (t < 2) {
+          double v = 1.0;
+          tab[0] = 1.0;
+#pragma unroll
+          for (int a = 1; a <= MMAX; ++a) {
+            v = v * z / static_cast<double>(a);
+            tab[a] = v;
+          }
+        } else {
+          const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+          double h0 = 1.0, h1 = z;
+          tab[0] = psi;
+          tab[1] = psi * z;
+#pragma unroll
+          for (int a = 1; a < MMAX; ++a) {
+            const double h2 = z * h1 - static_cast<double>(a) * h0;
+            h0 = h1;
+            h1 = h2;
+            tab[a + 1] = psi * h2;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a <= MMAX; ++a) tab[a] = 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kChunk / 4; ++ks) {
+      const double* tk = &sm.T[(ks * 4 + (lane >> 4)) * S::TABLE];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        if (tP[k] >= 0) {  // wave-uniform
+          const int p = tP[k] * 16 + (lane & 15);
+          const int q = tQ[k] * 16 + (lane & 15);
+          double av = 0.0, bv = 0.0;
+          if (p < n) av = tk[sm.qa[p]] * tk[S::TW + sm.qb[p]];
+          if (q < n) bv = tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]];
+          acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // element v of lane l holds D[l/16 + 4v][l%16] of its tile
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    if (tP[k] >= 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = tP[k] * 16 + (lane >> 4) + 4 * v;
+        const int c = tQ[k] * 16 + (lane & 15);
+        if (r < n && c < n) sm.A[r * S::LDA + c] = acc[k][v];
+      }
+    }
+  }
+  for (int t = tid; t < n * LABFM_NUM_OPS; t += kBlock)
+    sm.A[(t / LABFM_NUM_OPS) * S::LDA + S::NMAX + t % LABFM_NUM_OPS] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    const double h1 = 1.0 / h, h2 = 1.0 / (h * h);
+    const int C0 = S::NMAX;
+    sm.A[0 * S::LDA + C0 + LABFM_OP_X] = h1;
+    sm.A[1 * S::LDA + C0 + LABFM_OP_Y] = h1;
+    if (m >= 2) {
+      sm.A[index_of(2, 0) * S::LDA + C0 + LABFM_OP_L] = h2;
+      sm.A[index_of(0, 2) * S::LDA + C0 + LABFM_OP_L] = h2;
+      sm.A[index_of(2, 0) * S::LDA + C0 + LABFM_OP_XX] = h2;
+      sm.A[index_of(1, 1) * S::LDA + C0 + LABFM_OP_XY] = h2;
+    }
+    const int mp = (m % 2 == 0) ? m : m - 1;
+    if (mp >= 2) {
+      double hp = 1.0;
+      for (int k = 0; k < mp; ++k) hp *= h;
+      const int half = mp / 2;
+      double binom = 1.0;
+      for (int p = 0; p <= half; ++p) {
+        sm.A[index_of(2 * p, mp - 2 * p) * S::LDA + C0 + LABFM_OP_HYP] = binom / hp;
+        binom = binom * static_cast<double>(half - p) / static_cast<double>(p + 1);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- LU with partial pivoting on [M~ | C~] --------------------------------
+  int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
+  for (int c = 0; c < n; ++c) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int r = c + lane; r < n; r += 64) {
+        const double v = fabs(sm.A[r * S::LDA + c]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) sm.piv = (best > 0.0) ? bi : -1;  // -1: zero or non-finite column
+    }
+    __syncthreads();
+    const int bi = uniform(sm.piv);
+    if (bi < 0) {
+      singular = true;
+      break;
+    }
+    const int width = (n - c) + LABFM_NUM_OPS;  // columns c..n-1 and the RHS
+    if (bi != c) {
+      for (int t = tid; t < width; t += kBlock) {
+        const int jj = (t < n - c) ? (c + t) : (S::NMAX + t - (n - c));
+        const double t0 = sm.A[c * S::LDA + jj];
+        sm.A[c * S::LDA + jj] = sm.A[bi * S::LDA + jj];
+        sm.A[bi * S::LDA + jj] = t0;
+      }
+    }
+    __syncthreads();
+    const double pv = sm.A[c * S::LDA + c];
+    for (int r = c + 1 + tid; r < n; r += kBlock) sm.A[r * S::LDA + c] = sm.A[r * S::LDA + c] / pv;
+    __syncthreads();
+    const int W = width - 1;  // columns right of c
+    const int groups = kBlock / W;
+    const int rg = tid / W;
+    if (rg < groups) {
+      const int t = tid - rg * W;
+      const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
+      const double ucj = sm.A[c * S::LDA + jj];
+      for (int r = c + 1 + rg; r < n; r += groups)
+        sm.A[r * S::LDA + jj] -= sm.A[r * S::LDA + c] * ucj;
+    }
+    __syncthreads();
+  }
+  if (!singular) {
+  // ---- back substitution ----------------------------------------------------
+  for (int c = n - 1; c >= 0; --c) {
+    if (tid < LABFM_NUM_OPS) {
+      const int jj = S::NMAX + tid;
+      sm.A[c * S::LDA + jj] = sm.A[c * S::LDA + jj] / sm.A[c * S::LDA + c];
+    }
+    __syncthreads();
+    for (int t = tid; t < c * LABFM_NUM_OPS; t += kBlock) {
+      const int r = t / LABFM_NUM_OPS, d = t - r * LABFM_NUM_OPS;
+      const int jj = S::NMAX + d;
+      sm.A[r * S::LDA + jj] -= sm.A[r * S::LDA + c] * sm.A[c * S::LDA + jj];
+    }
+    __syncthreads();
+  }
+
+  // ---- weights, filter calibration, row sums --------------------------------
+  // threads 0..191: neighbour slot k = t/12, operator d = (t/2)%6, half = t%2
+  const int slot = tid / 12, dop = (tid / 2) % 6, half = tid & 1;
+  const double kf = 2.0 * M_PI / (3.0 * s);
+  double rs = 0.0, f0 = 0.0;
+  for (int k0 = 0; k0 < K; k0 += kChunk) {
+    if (tid < 64) {
+      // basis tables of 16 neighbours (the psi He_a and He_b ones are used)
+      const int kk = lane >> 2, t = lane & 3;
+      const int k = k0 + kk;
+      double* tab = &sm.T[kk * S::TABLE + t * S::TW];
+      if (t >= 2) {
+        if (k < K) {
+          const int j = g.col[e0 + k];
+          const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
+          const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+          const double xs = dx / h, ys = dy / h;
+          const double z = (t == 2) ? xs : ys;
+          const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+          double h0 = 1.0, h1 = z;
+          tab[0] = psi;
+          tab[1] = psi * z;
+#pragma unroll
+          for (int a = 1; a < MMAX; ++a) {
+            const double h2 = z * h1 - static_cast<double>(a) * h0;
+            h0 = h1;
+            h1 = h2;
+            tab[a + 1] = psi * h2;
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a <= MMAX; ++a) tab[a] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 12 * kChunk) {
+      const int k = k0 + slot;
+      const double* tk = &sm.T[slot * S::TABLE];
+      double acc = 0.0;
+      for (int q = half; q < n; q += 2)
+        acc += (tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]]) *
+               sm.A[q * S::LDA + S::NMAX + dop];
+      acc += __shfl_xor(acc, 1);
+      if (k < K) {
+        if (half == 0) {
+          const long long e = e0 + k;
+          g.w[dop * g.nnz + e] = acc;
+          if (g.w32) g.w32[dop * g.nnz + e] = static_cast<float>(acc);
+          if (dop == LABFM_OP_HYP) {
+            const int j = g.col[e];
+            const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
+            const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+            f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * acc;
+          }
+        }
+        rs += acc;
+      }
+    }
+    __syncthreads();
+  }
+  // deterministic reduction over the 16 neighbour slots
+  if (tid < 12 * kChunk && half == 0) {
+    sm.part[slot * 8 + dop] = rs;
+    if (dop == LABFM_OP_HYP) sm.part[slot * 8 + 6] = f0;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double v = 0.0;
+    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 8 + tid];
+    if (tid < 6) {
+      if (g.rowsum) g.rowsum[tid * (long long)g.n + i] = v;
+    } else {
+      const bool bad = !isfinite(v) || v == 0.0;
+      g.kappa[i] = bad ? 0.0 : 2.0 / (3.0 * v);
+      if (st == LABFM_NODE_OK && bad) st = LABFM_NODE_BAD_FILTER;
+      g.status[i] = static_cast<int8_t>(st);
+    }
+  }
+  }  // !singular
+  }  // valid
+  if (!valid || singular) {
+    for (int k = tid; k < K; k += kBlock)
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        g.w[d * g.nnz + e0 + k] = 0.0;
+        if (g.w32) g.w32[d * g.nnz + e0 + k] = 0.0f;
+      }
+    if (tid == 0) {
+      g.kappa[i] = 0.0;
+      g.status[i] = valid ? LABFM_NODE_SINGULAR : LABFM_NODE_BAD_ORDER;
+      if (g.rowsum)
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// one workgroup per node of the list (or per node when list is null)
+template <int MMAX>
+__global__ void __launch_bounds__(kBlock)
+build_block_kernel(BuildArgs g, const int* __restrict__ list, int count) {
+  __shared__ BlockSmem<MMAX> sm;
+  const int k = blockIdx.x;
+  if (k >= count) return;
+  build_node_block<MMAX>(list ? list[k] : k, g, sm);
+}
+
+// persistent: workgroups take list entries through *counter until exhausted
+template <int MMAX>
+__global__ void __launch_bounds__(kBlock)
+build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, int* counter) {
+  __shared__ BlockSmem<MMAX> sm;
+  for (;;) {
+    if (threadIdx.x == 0) sm.next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int k = uniform(sm.next);
+    if (k >= count) break;  // the same value for every thread of the workgroup
+    // ends with a barrier, so sm.next is read by all before it is rewritten
+    build_node_block<MMAX>(list[k], g, sm);
+  }
+}
+
+// Work list: node indices grouped by order, highest order first (counting
+// sort; the order inside a group is immaterial, every node's result is its
+// own).
+__global__ void order_histogram_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = m[i];
+  o = o < 0 ? 0 : (o > 15 ? 15 : o);
+  atomicAdd(&hist[15 - o], 1);
+}
+
+__global__ void order_offsets_kernel(int* __restrict__ hist) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < 16; ++b) {
+      const int c = hist[b];
+      hist[16 + b] = acc;  // start of bucket b
+      hist[b] = acc;       // cursor
+      acc += c;
+    }
+    hist[32] = acc;
+  }
+}
+
+__global__ void order_scatter_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist,
+                                     int* __restrict__ list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = m[i];
+  o = o < 0 ? 0 : (o > 15 ? 15 : o);
+  list[atomicAdd(&hist[15 - o], 1)] = i;
+}
+
 __global__ void max_order_kernel(const int8_t* __restrict__ m, int n, int* out) {
   __shared__ int sh[256];
   int v = 0;
@@ -411,10 +818,71 @@ hipError_t launch_build(const double* x, const double* y, const double* h, const
   return hipGetLastError();
 }
 
+template <int MMAX>
+hipError_t launch_block(const BuildArgs& g, const int* list, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(build_block_kernel<MMAX>, dim3(count), dim3(kBlock), 0, st, g, list, count);
+  return hipGetLastError();
+}
+
+template <int MMAX>
+hipError_t launch_persistent(const BuildArgs& g, const int* list, int count, int* counter,
+                             int per_cu, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int dev = 0, cus = 0, blocks = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, build_persistent_kernel<MMAX>,
+                                                     kBlock, 0);
+  if (e != hipSuccess) return e;
+  blocks = std::max(1, blocks);
+  if (per_cu > 0) blocks = std::min(blocks, per_cu);
+  const int grid = std::max(1, std::min(count, cus * blocks));
+  e = hipMemsetAsync(counter, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(build_persistent_kernel<MMAX>, dim3(grid), dim3(kBlock), 0, st, g, list,
+                     count, counter);
+  return hipGetLastError();
+}
+
+template <class Fn>
+hipError_t with_mmax(int mmax, Fn&& fn) {
+  if (mmax <= 4) return fn(std::integral_constant<int, 4>{});
+  if (mmax <= 6) return fn(std::integral_constant<int, 6>{});
+  if (mmax <= 8) return fn(std::integral_constant<int, 8>{});
+  return fn(std::integral_constant<int, 10>{});  // orders above 10: LABFM_NODE_BAD_ORDER
+}
+
+std::mutex g_build_mutex;
+labfm_build_config g_build_cfg = {LABFM_BUILD_BLOCK, 0};
+
 }  // namespace
 }  // namespace labfm
 
 using namespace labfm;
+
+extern "C" int labfm_set_build_config(const labfm_build_config* cfg) {
+  clear_error();
+  labfm_build_config c{LABFM_BUILD_BLOCK, 0};
+  if (cfg) {
+    LABFM_REQUIRE(cfg->mode >= LABFM_BUILD_WAVE && cfg->mode <= LABFM_BUILD_BUCKETED,
+                  "set_build_config: unknown mode %d", cfg->mode);
+    LABFM_REQUIRE(cfg->workgroups_per_cu >= 0, "set_build_config: negative workgroups_per_cu");
+    c = *cfg;
+  }
+  std::lock_guard<std::mutex> lock(g_build_mutex);
+  g_build_cfg = c;
+  return LABFM_OK;
+}
+
+extern "C" int labfm_get_build_config(labfm_build_config* cfg) {
+  clear_error();
+  LABFM_REQUIRE(cfg, "get_build_config: null argument");
+  std::lock_guard<std::mutex> lock(g_build_mutex);
+  *cfg = g_build_cfg;
+  return LABFM_OK;
+}
 
 extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
                                    const double* s, const int8_t* order_m, int32_t n,
@@ -427,30 +895,125 @@ extern "C" int labfm_build_weights(const double* x, const double* y, const doubl
                 "build_weights: null pointer argument");
   LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "build_weights: bad CSR arguments");
   hipStream_t st = as_stream(stream_);
-  int* d_max = nullptr;
-  LABFM_HIP(hipMalloc(&d_max, sizeof(int)));
-  hipLaunchKernelGGL(max_order_kernel, dim3(1), dim3(256), 0, st, order_m, n, d_max);
-  hipError_t le = hipGetLastError();
+  labfm_build_config cfg;
+  {
+    std::lock_guard<std::mutex> lock(g_build_mutex);
+    cfg = g_build_cfg;
+  }
+  // work list grouped by order (highest first) and the bucket sizes
+  struct Temp {
+    void* p = nullptr;
+    ~Temp() {
+      if (p) (void)hipFree(p);
+    }
+  } tmp;
+  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (64 + static_cast<size_t>(n))));
+  int* hist = static_cast<int*>(tmp.p);  // [0,16) cursors, [16,32) starts, [32] total
+  int* counter = hist + 40;
+  int* list = hist + 64;
+  LABFM_HIP(hipMemsetAsync(hist, 0, sizeof(int) * 64, st));
+  hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
+                     n, hist);
+  hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(64), 0, st, hist);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
+                     n, hist, list);
+  LABFM_LAUNCHED();
+  int starts[17] = {0};
+  LABFM_HIP(hipMemcpyAsync(starts, hist + 16, sizeof(int) * 17, hipMemcpyDeviceToHost, st));
+  LABFM_HIP(hipStreamSynchronize(st));
+  // bucket b holds order 15 - b; the highest order present sets the template
   int mmax = 0;
-  if (le == hipSuccess) le = hipMemcpyAsync(&mmax, d_max, sizeof(int), hipMemcpyDeviceToHost, st);
-  if (le == hipSuccess) le = hipStreamSynchronize(st);
-  (void)hipFree(d_max);
-  LABFM_HIP(le);
-  hipError_t e;
-  if (mmax <= 4) {
-    e = launch_build<4>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
-                        status, st);
-  } else if (mmax <= 6) {
-    e = launch_build<6>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
-                        status, st);
-  } else if (mmax <= 8) {
-    e = launch_build<8>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
-                        status, st);
-  } else {
-    // orders above 10 are reported per node as LABFM_NODE_BAD_ORDER
-    e = launch_build<10>(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
-                         status, st);
+  for (int b = 0; b < 16; ++b)
+    if (starts[b + 1] > starts[b]) {
+      mmax = 15 - b;
+      break;
+    }
+  const BuildArgs g{x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum, status};
+  hipError_t e = hipSuccess;
+  switch (cfg.mode) {
+    case LABFM_BUILD_WAVE:
+      e = with_mmax(mmax, [&](auto M) {
+        return launch_build<decltype(M)::value>(x, y, h, s, order_m, n, box, row_ptr, col, nnz,
+                                                w, w32, kappa, rowsum, status, st);
+      });
+      break;
+    case LABFM_BUILD_BLOCK:
+      e = with_mmax(mmax, [&](auto M) { return launch_block<decltype(M)::value>(g, list, n, st); });
+      break;
+    case LABFM_BUILD_PERSISTENT:
+      e = with_mmax(mmax, [&](auto M) {
+        return launch_persistent<decltype(M)::value>(g, list, n, counter, cfg.workgroups_per_cu,
+                                                     st);
+      });
+      break;
+    case LABFM_BUILD_BUCKETED: {
+      // one launch per order class, each with its own template
+      const int hi[4] = {15, 10, 8, 6};
+      const int lo[4] = {9, 7, 5, 0};
+      for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        const int b0 = 15 - hi[c], b1 = 15 - lo[c];  // buckets b0..b1
+        const int first = starts[b0], count = starts[b1 + 1] - first;
+        e = with_mmax(std::min(hi[c], 10), [&](auto M) {
+          return launch_block<decltype(M)::value>(g, list + first, count, st);
+        });
+      }
+      break;
+    }
+    default:
+      e = hipErrorInvalidValue;
   }
   LABFM_HIP(e);
+  // the work list is freed on return
+  LABFM_HIP(hipStreamSynchronize(st));
   return LABFM_OK;
+}
+
+extern "C" int labfm_tune_build(const double* x, const double* y, const double* h,
+                                const double* s, const int8_t* order_m, int32_t n, labfm_box box,
+                                const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                                double* w, float* w32, double* kappa, double* rowsum,
+                                int8_t* status, labfm_build_config* best, double* best_ms,
+                                void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(best && best_ms, "tune_build: null output");
+  hipStream_t st = as_stream(stream_);
+  const labfm_build_config cands[5] = {{LABFM_BUILD_WAVE, 0},
+                                       {LABFM_BUILD_BLOCK, 0},
+                                       {LABFM_BUILD_PERSISTENT, 0},
+                                       {LABFM_BUILD_PERSISTENT, 2},
+                                       {LABFM_BUILD_BUCKETED, 0}};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LABFM_HIP(hipEventCreate(&e0));
+  LABFM_HIP(hipEventCreate(&e1));
+  double bms = 1e300;
+  labfm_build_config bc = cands[1];
+  int rc = LABFM_OK;
+  for (int k = 0; k < 5 && rc == LABFM_OK; ++k) {
+    labfm_set_build_config(&cands[k]);
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess)
+      rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa,
+                               rowsum, status, stream_);
+    if (rc == LABFM_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+    if (rc == LABFM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (rc == LABFM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      set_error("tune_build: %s", hipGetErrorString(e));
+      rc = LABFM_ERR_HIP;
+    }
+    if (rc == LABFM_OK && ms < bms) {
+      bms = ms;
+      bc = cands[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LABFM_OK) return rc;
+  labfm_set_build_config(&bc);
+  *best = bc;
+  *best_ms = bms;
+  // leave the outputs of the chosen distribution in place
+  return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
+                             status, stream_);
 }

@@ -23,6 +23,7 @@ OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
 F64, F32W, F32_COMP = 0, 1, 2
 
 KERNEL_STAGE, KERNEL_FILTER, KERNEL_APPLY = 0, 1, 2
+BUILD_WAVE, BUILD_BLOCK, BUILD_PERSISTENT, BUILD_BUCKETED = 1, 2, 3, 4
 XCD_ORDER, STREAMING = 1, 2
 OK, ERR_ARG, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 NODE_OK, NODE_SINGULAR, NODE_FEW_NEIGHBOURS, NODE_BAD_FILTER, NODE_BAD_ORDER = range(5)
@@ -68,6 +69,10 @@ class _Transpose(ctypes.Structure):
                 ("rowsum", ctypes.c_void_p)]
 
 
+class _BuildConfig(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32)]
+
+
 class _Timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("filter_ms", ctypes.c_double),
                 ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64)]
@@ -96,6 +101,12 @@ _SIGNATURES = {
     "labfm_rk_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_Operators),
                                         ctypes.POINTER(_Transpose), ctypes.POINTER(_RKParams),
                                         ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "labfm_set_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
+    "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
+    "labfm_tune_build": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
+                                        ctypes.c_int64, _P, _P, _P, _P, _P,
+                                        ctypes.POINTER(_BuildConfig),
+                                        ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_get_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                                ctypes.c_int64, ctypes.POINTER(_LaunchConfig)]),
@@ -216,7 +227,7 @@ class Operators:
 
 
 def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
-                  rowsum: bool = False, tiles: bool = True) -> Operators:
+                  rowsum: bool = False, tiles: bool = True, tune: bool = False) -> Operators:
     """Weights of the six operators, filter coefficients and node status;
     with ``tiles`` also the node tiles used by the LDS-staged kernels."""
     n = x.numel()
@@ -231,10 +242,14 @@ def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
     kappa = torch.empty(n, dtype=torch.float64, device=dev)
     rs = torch.empty((6, n), dtype=torch.float64, device=dev) if rowsum else None
     status = torch.empty(n, dtype=torch.int8, device=dev)
-    code = lib().labfm_build_weights(_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box),
-                                     _ptr(row_ptr), _ptr(col), nnz, _ptr(w), _ptr(w32),
-                                     _ptr(kappa), _ptr(rs), _ptr(status), _stream())
-    _check(code)
+    args = (_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box), _ptr(row_ptr), _ptr(col),
+            nnz, _ptr(w), _ptr(w32), _ptr(kappa), _ptr(rs), _ptr(status))
+    if tune:
+        best, ms = _BuildConfig(), ctypes.c_double(0.0)
+        _check(lib().labfm_tune_build(*args, ctypes.byref(best), ctypes.byref(ms), _stream()))
+        build_weights.last_tuned = (best.mode, best.workgroups_per_cu, ms.value)
+    else:
+        _check(lib().labfm_build_weights(*args, _stream()))
     ops = Operators(row_ptr, col, w, w32, kappa, rs, status)
     if tiles:
         build_tiles(ops)
@@ -415,3 +430,19 @@ class RKSolve(torch.autograd.Function):
         g0 = rk_adjoint(q0, qbar, ops, flow, dt, n_steps, ckpt_every, filter)
         rho0 = torch.exp(q0[:n])
         return (g0[:n] / rho0, g0[n:2 * n], g0[2 * n:], None, None, None, None, None, None)
+
+
+def set_build_config(mode: int = 0, workgroups_per_cu: int = 0) -> None:
+    """Choose how build_weights spreads nodes over the GPU (mode 0 restores
+    the default, one workgroup per node)."""
+    if mode == 0:
+        _check(lib().labfm_set_build_config(None))
+    else:
+        c = _BuildConfig(mode, workgroups_per_cu)
+        _check(lib().labfm_set_build_config(ctypes.byref(c)))
+
+
+def get_build_config() -> tuple:
+    c = _BuildConfig()
+    _check(lib().labfm_get_build_config(ctypes.byref(c)))
+    return c.mode, c.workgroups_per_cu

@@ -567,3 +567,87 @@ def test_tiled_kernels_bitwise_equal_untiled(dev, tg64, prec_name):
         outs.append((q.cpu().numpy(), r.cpu().numpy()))
     ops.use_tiles = True
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# ------------------------------------------------ build modes, graded nodes
+
+@pytest.fixture(scope="module")
+def holes20k():
+    return inputs.graded_holes(20000, seed=3)
+
+
+def test_build_modes_agree(dev, holes20k):
+    """Workgroup-per-node, persistent and per-order-class launches run the same
+    per-node code (bitwise equal); the one-wavefront kernel sums the weights in
+    another order (equal to rounding)."""
+    from paper_2102_02019_amd import labfm
+
+    nodes = holes20k
+    outs = {}
+    try:
+        for mode in (labfm.BUILD_WAVE, labfm.BUILD_BLOCK, labfm.BUILD_PERSISTENT,
+                     labfm.BUILD_BUCKETED):
+            labfm.set_build_config(mode)
+            ops = gpu_setup(nodes, dev)
+            outs[mode] = (ops.w.cpu().numpy(), ops.kappa.cpu().numpy(), ops.status.cpu().numpy())
+    finally:
+        labfm.set_build_config(0)
+    ref = outs[labfm.BUILD_BLOCK]
+    for mode in (labfm.BUILD_PERSISTENT, labfm.BUILD_BUCKETED):
+        for a, b in zip(outs[mode], ref):
+            assert np.array_equal(a, b), mode
+    w1, k1, s1 = outs[labfm.BUILD_WAVE]
+    assert np.array_equal(s1, ref[2])
+    # per-node weight differences on nodes with a full-rank system (nodes with
+    # fewer neighbours than moments have no unique weights); rounding is
+    # amplified by cond(M~), large for some m = 10 nodes of the grading ramp
+    rp = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)[0]
+    d = []
+    for i in np.nonzero(ref[2] == 0)[0]:
+        a, b = rp[i], rp[i + 1]
+        d.append(np.max(np.linalg.norm(w1[:, a:b] - ref[0][:, a:b], axis=1)
+                        / np.linalg.norm(ref[0][:, a:b], axis=1)))
+    d = np.array(d)
+    assert np.median(d) <= 1e-10 and np.quantile(d, 0.99) <= 1e-8, (np.median(d), d.max())
+
+
+def test_tune_build_picks_a_mode(dev, holes20k):
+    """The build autotuner installs one of the distributions and leaves the
+    weights of that distribution in place (block-type modes agree bitwise)."""
+    from paper_2102_02019_amd import labfm
+
+    nodes = holes20k
+    x, y, h, s = (T(a, dev) for a in (nodes.x, nodes.y, nodes.h, nodes.s))
+    m = T(nodes.m, dev)
+    rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+    try:
+        ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, tune=True)
+        mode, wpc, ms = labfm.build_weights.last_tuned
+        assert mode in (labfm.BUILD_WAVE, labfm.BUILD_BLOCK, labfm.BUILD_PERSISTENT,
+                        labfm.BUILD_BUCKETED) and ms > 0
+        assert labfm.get_build_config() == (mode, wpc)
+        again = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col)
+        assert torch.equal(ops.w, again.w) and torch.equal(ops.status, again.status)
+    finally:
+        labfm.set_build_config(0)
+    assert labfm.get_build_config() == (labfm.BUILD_BLOCK, 0)
+
+
+def test_graded_holes_weights_sampled(dev, holes20k):
+    """Orders 4, 6 and 10 with uneven stencils in one launch, checked against
+    the oracle on sampled nodes of every order."""
+    nodes = holes20k
+    ops = gpu_setup(nodes, dev)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    assert np.array_equal(ops.row_ptr.cpu().numpy(), rp)
+    sample = []
+    for m in (4, 6, 10):
+        idx = np.nonzero(nodes.m == m)[0]
+        sample += list(idx[:: max(1, idx.size // 12)])
+    W = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, nodes.m, rp, col, nodes.box, nodes=sample)
+    W.update(row_ptr=rp, col=col)
+    st = ops.status.cpu().numpy()
+    ok = [i for i in sample if W["status"][i] == 0]
+    _check_weights(nodes, ops, W, ok)
+    for i in sample:
+        assert st[i] == W["status"][i]
