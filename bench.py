@@ -12,11 +12,20 @@ value  = node-updates per second per RK stage for the whole job
 roofline: the fused RK stage kernel, algorithmic bytes per launch
          (44 K + 104 bytes per node, K = mean neighbours) over its mean
          duration from HIP events recorded on its stream during the timed
-         region;
+         region; traffic: HBM bytes per launch from the committed rocprofv3
+         FETCH_SIZE / WRITE_SIZE summary of the same kernel, if it was taken
+         on the current source;
+graph_replayed_steps: the same RK steps replayed from a HIP graph;
+build: stencil search and weight build of the workload (HIP events) and
+         the build's algorithmic FP64 FLOP/s against the FP64 peak;
 f32w, f32_comp: the same job with float32 weights (float64 sums, or
          float32 compensated Dot2 sums), speedup and per-field error against
          the float64 run;
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
+
+Launch shapes of the gather kernels are autotuned on the workload before the
+timed region. --profile-run runs a 1 GiB calibration copy, the tuner and one
+job per precision, for rocprofv3 counter passes.
 
 Prints one JSON line.
 """
@@ -37,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node-updates/s per RK stage + HBM roofline frac, FP32-comp vs FP64 at stated err"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -49,6 +59,10 @@ def parse():
                     help="RK steps per job (default: the workload's run length)")
     ap.add_argument("--no-f32", action="store_true", help="skip the float32 compensated job")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-shapes", default=None,
+                    help="pin the gather kernels' launch shapes instead of tuning: JSON "
+                         "{prec: {kernel: [lanes_per_node, flags]}} inline, or the path of a "
+                         "JSON file holding it under 'launch_shapes' (a bench output line)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: a 1 GiB copy, then warmup jobs only")
     return ap.parse_args()
@@ -119,29 +133,58 @@ def main():
         t1 = time.perf_counter()
         return ops, tms, (t1 - t0) / max(1, steps)
 
+    precs = {"f64": labfm.F64, "f32w": labfm.F32W, "f32_comp": labfm.F32_COMP}
+    if args.no_f32:
+        precs = {"f64": labfm.F64}
+    if args.launch_shapes:
+        tuned = pinned_shapes(args.launch_shapes, precs, labfm)
+    else:
+        tuned = {key: tune(p) for key, p in precs.items()}
+    # the stage kernels the jobs launch (names as a profiler shows them)
+    use_tiles = True
+    names = {k: stage_kernel_name(v["stage"], use_tiles, PREC_TAG[k]) for k, v in tuned.items()}
+
     if args.profile_run:
+        # the tuned shapes stay installed; the counters of the last dispatches
+        # of each stage kernel belong to these jobs
         job(labfm.F64)
         if not args.no_f32:
             job(labfm.F32W)
             job(labfm.F32_COMP)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": "done", "workload": wl.name, "nodes": N}))
+        print(json.dumps({"profile_run": "done", "workload": wl.name, "nodes": N,
+                          "rk_steps": rk_steps, "stage_kernels": names, "launch_shapes": tuned}))
         return
 
-    tuned = {"f64": tune(labfm.F64)}
     ops, tms, sec = timed(labfm.F64, args.steps, args.warmup)
     q64 = q.clone()
     nnz = ops.nnz
     kbar = nnz / N
-    stage_ms = sum(t["stage_ms"] for t in tms) / sum(t["stage_launches"] for t in tms)
+    launches = sum(t["stage_launches"] for t in tms)
+    stage_ms = sum(t["stage_ms"] for t in tms) / launches
     filter_ms = sum(t["filter_ms"] for t in tms) / max(1, sum(t["filter_launches"] for t in tms))
     value = N * 4 * rk_steps / sec
     bytes_stage = (44.0 * kbar + 104.0) * N
+    bytes_filter = (12.0 * kbar + 56.0) * N
     achieved = bytes_stage / (stage_ms * 1e-3) / 1e9
-    traffic = profiling.load_traffic("rk_stage_f64", wl.name,
-                                     profiling.kernel_source("operators.hip"))
+    traffic = profiling.load_traffic("rk_stage_f64", wl.name, names["f64"])
     status_hist = np.bincount(ops.status.cpu().numpy().astype(np.int64), minlength=5).tolist()
     finite = bool(torch.isfinite(q64).all().item())
+
+    # full RK steps replayed from a HIP graph (4 stages + filter), per stage
+    q.copy_(q0)
+    dt = labfm.time_step(q, s, prm.c2, prm.mu)
+    labfm.rk_step(q, ops, prm, dt, 10, workspace=ws, use_graph=True)
+    torch.cuda.synchronize()
+    q.copy_(q0)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    labfm.rk_step(q, ops, prm, dt, rk_steps, workspace=ws, use_graph=True)
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - tg0
+    graph_equal = bool(torch.equal(q, q64))
+
+    build = build_rate(labfm, torch, np, nodes, x, y, h, s, m)
 
     out = {
         "metric": METRIC,
@@ -160,13 +203,21 @@ def main():
                    "mean_neighbours": round(kbar, 2), "rk_steps_per_job": rk_steps,
                    "filter": "every step", "domain": "[0,2pi)^2 periodic, +/-0.3s jitter",
                    "flow": "Taylor-Green, Re=100, Ma=0.1"},
-        "roofline": {"bound": "hbm", "kernel": "rk_stage_kernel<f64>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": names["f64"], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "bytes_per_node_stage": 44.0 * kbar + 104.0,
-                     "mean_launch_ms": stage_ms, "launches": sum(t["stage_launches"] for t in tms)},
+                     "algorithmic_bytes_per_launch": bytes_stage,
+                     "mean_launch_ms": stage_ms, "launches": launches},
         "stage_kernel_node_updates_per_s": N / (stage_ms * 1e-3),
-        "filter_kernel_ms": filter_ms,
+        "graph_replayed_steps": {"node_updates_per_s": N * 4 * rk_steps / graph_s,
+                                 "ms_per_rk_step": graph_s * 1e3 / rk_steps,
+                                 "bitwise_equal_to_eager": graph_equal},
+        "filter_kernel": {"mean_launch_ms": filter_ms,
+                          "achieved_GBs": bytes_filter / (filter_ms * 1e-3) / 1e9,
+                          "frac": bytes_filter / (filter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "bytes_per_node": 12.0 * kbar + 56.0},
+        "build": build,
         "setup_ms_per_job": sec * 1e3 - sum(t["stage_ms"] + t["filter_ms"] for t in tms) / len(tms),
         "final_state_finite": finite,
         "node_status_histogram": status_hist,
@@ -176,7 +227,6 @@ def main():
     for prec, key in ((labfm.F32W, "f32w"), (labfm.F32_COMP, "f32_comp")):
         if args.no_f32:
             break
-        tuned[key] = tune(prec)
         ops32, tms32, sec32 = timed(prec, args.steps, args.warmup)
         q32 = q.clone()
         st32 = sum(t["stage_ms"] for t in tms32) / sum(t["stage_launches"] for t in tms32)
@@ -202,6 +252,7 @@ def main():
             "stage_mean_launch_ms": st32,
             "stage_achieved_GBs": b32 / (st32 * 1e-3) / 1e9,
             "stage_frac": b32 / (st32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "stage_kernel": names[key],
             "bytes_per_node_stage": 24.0 * kbar + 104.0,
             "final_state_rel_err_vs_f64": err,
             "operator_rel_err_vs_f64": op_err,
@@ -211,6 +262,66 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, rk_steps, N)
 
     print(json.dumps(out))
+
+
+PREC_TAG = {"f64": "F64", "f32w": "F32W", "f32_comp": "F32Comp"}
+
+
+def pinned_shapes(spec, precs, labfm):
+    """Install the launch shapes given on the command line (see --launch-shapes)."""
+    text = spec if spec.lstrip().startswith("{") else open(spec).read().strip().splitlines()[-1]
+    d = json.loads(text)
+    d = d.get("launch_shapes", d)
+    kernels = {"stage": labfm.KERNEL_STAGE, "filter": labfm.KERNEL_FILTER,
+               "apply": labfm.KERNEL_APPLY}
+    out = {}
+    for key, p in precs.items():
+        out[key] = {}
+        for kname, kid in kernels.items():
+            lpn, flags = d[key][kname][0], d[key][kname][1]
+            labfm.set_launch_config(kid, p, lpn, flags)
+            out[key][kname] = [lpn, flags, None]
+    return out
+
+
+def stage_kernel_name(shape, tiled, prec_tag):
+    """Name pattern of the fused RK stage kernel for a tuned launch shape
+    (lanes per node, flags); '*' joins the parts of a profiler's name."""
+    lpn, flags = shape[0], shape[1]
+    kern = "rk_stage_tiled_kernel" if tiled else "rk_stage_kernel"
+    return f"{kern}<{lpn}, {flags}, *{prec_tag}>"
+
+
+def build_flops(m, K):
+    """Algorithmic FP64 flops of one node's weight build: assembly 2Kn^2,
+    LU (2/3)n^3, six solves 12n^2, weights 12Kn, basis K(3n + 4m + 20)."""
+    n = (m * m + 3 * m) // 2
+    return 2 * K * n * n + (2.0 / 3.0) * n ** 3 + 12 * n * n + 12 * K * n + K * (3 * n + 4 * m + 20)
+
+
+def build_rate(labfm, torch, np, nodes, x, y, h, s, m):
+    """Stencil search and weight build of the workload, timed with HIP events
+    on the current stream (best of 3), and the weight build's FP64 FLOP/s."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    best = None
+    for _ in range(3):
+        ev[0].record()
+        rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+        ev[1].record()
+        labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True, tiles=False)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t = (ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]))
+        best = t if best is None or t[1] < best[1] else best
+    K = np.diff(rp.cpu().numpy()).astype(np.float64)
+    fl = float(np.sum(build_flops(nodes.m.astype(np.float64), K)))
+    mode = labfm.get_build_config()
+    return {"neighbours_ms": best[0], "weights_ms": best[1], "gflop": fl / 1e9,
+            "achieved_TFLOPs": fl / (best[1] * 1e-3) / 1e12,
+            "peak_TFLOPs": FP64_PEAK_TFLOPS,
+            "frac": fl / (best[1] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "distribution": {1: "wavefront-per-node", 2: "workgroup-per-node",
+                             3: "persistent", 4: "per-order-class"}.get(mode[0], str(mode[0]))}
 
 
 def cpu_baseline(wl, rk_steps, N_full):

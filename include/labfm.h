@@ -302,9 +302,10 @@ int labfm_set_launch_config(int32_t kernel, labfm_prec prec, const labfm_launch_
 
 /*
  * Autotuner: times every supported launch shape of the stage, filter and
- * apply kernels on the given operators and state (reps launches each, HIP
- * events on `stream`), installs the fastest as the process-wide setting for
- * `prec` and reports it.
+ * apply kernels on the given operators and state (two interleaved passes of
+ * reps launches each, HIP events on `stream`, best mean kept), installs the
+ * fastest as the process-wide setting for `prec` and reports it. The default
+ * shape is kept unless another is more than 2% faster.
  *
  *   q          float64[3n] state the stage kernel reads (not modified).
  *   workspace  labfm_rk_workspace_bytes(n) bytes (overwritten).

@@ -228,12 +228,17 @@ extern "C" int labfm_tune(const labfm_operators* ops, const double* q, labfm_pre
   LABFM_HIP(hipEventCreate(&e1));
   hipError_t err = hipSuccess;
   const int lpns[4] = {4, 8, 16, 32};
+  constexpr int kCands = 16, kPasses = 2;
   for (int kernel = 0; kernel < 3 && err == hipSuccess; ++kernel) {
-    double bms = 1e300;
-    LaunchCfg bc{0, 0};
-    for (int li = 0; li < 4 && err == hipSuccess; ++li) {
-      for (int fl_bits = 0; fl_bits < 4 && err == hipSuccess; ++fl_bits) {
-        const LaunchCfg c{lpns[li], fl_bits};
+    // every candidate is timed in kPasses interleaved passes and keeps its
+    // best mean; the default shape stays unless another is more than
+    // kMargin faster (timing noise does not flip the choice)
+    constexpr double kMargin = 0.02;
+    double t[kCands];
+    for (int k = 0; k < kCands; ++k) t[k] = 1e300;
+    for (int pass = 0; pass < kPasses && err == hipSuccess; ++pass) {
+      for (int k = 0; k < kCands && err == hipSuccess; ++k) {
+        const LaunchCfg c{lpns[k / 4], k % 4};
         auto launch = [&]() -> hipError_t {
           return with_prec(prec, ops, [&](auto pol, const auto* w) {
             using P = decltype(pol);
@@ -251,20 +256,23 @@ extern "C" int labfm_tune(const labfm_operators* ops, const double* q, labfm_pre
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        const double mean = static_cast<double>(ms) / reps;
-        if (err == hipSuccess && mean < bms) {
-          bms = mean;
-          bc = c;
-        }
+        if (err == hipSuccess) t[k] = std::min(t[k], static_cast<double>(ms) / reps);
       }
     }
-    if (err == hipSuccess) {
-      best[kernel].lanes_per_node = bc.lpn;
-      best[kernel].flags = bc.flags;
-      best_ms[kernel] = bms;
-      std::lock_guard<std::mutex> lock(g_cfg_mutex);
-      g_cfg[kernel][prec_slot(prec)] = best[kernel];
-    }
+    if (err != hipSuccess) break;
+    const LaunchCfg d = default_cfg(kernel, prec, n, ops->nnz);
+    int kd = 0;
+    for (int k = 0; k < kCands; ++k)
+      if (lpns[k / 4] == d.lpn && k % 4 == d.flags) kd = k;
+    int kb = kd;
+    for (int k = 0; k < kCands; ++k)
+      if (t[k] < t[kb]) kb = k;
+    if (!(t[kb] < (1.0 - kMargin) * t[kd])) kb = kd;
+    best[kernel].lanes_per_node = lpns[kb / 4];
+    best[kernel].flags = kb % 4;
+    best_ms[kernel] = t[kb];
+    std::lock_guard<std::mutex> lock(g_cfg_mutex);
+    g_cfg[kernel][prec_slot(prec)] = best[kernel];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

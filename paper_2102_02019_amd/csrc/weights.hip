@@ -744,9 +744,19 @@ build_block_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   build_node_block<MMAX>(list ? list[k] : k, g, sm);
 }
 
+// Waves per SIMD that the workgroup-per-node kernel reaches for each MMAX (by
+// its register and LDS use). The loop of the persistent kernel keeps more
+// values live, and without this bound the register allocator would give it
+// one resident workgroup per CU less.
+template <int MMAX>
+constexpr int persistent_waves() {
+  return MMAX <= 6 ? 5 : (MMAX <= 8 ? 4 : 3);
+}
+
 // persistent: workgroups take list entries through *counter until exhausted
 template <int MMAX>
 __global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(persistent_waves<MMAX>())))
 build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, int* counter) {
   __shared__ BlockSmem<MMAX> sm;
   for (;;) {
@@ -762,12 +772,23 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
 // Work list: node indices grouped by order, highest order first (counting
 // sort; the order inside a group is immaterial, every node's result is its
 // own).
-__global__ void order_histogram_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Histogram and scatter count in LDS and issue one global atomic per order
+// per workgroup.
+__device__ __forceinline__ int order_bucket(const int8_t* m, int i) {
   int o = m[i];
   o = o < 0 ? 0 : (o > 15 ? 15 : o);
-  atomicAdd(&hist[15 - o], 1);
+  return 15 - o;
+}
+
+__global__ void __launch_bounds__(256)
+order_histogram_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist) {
+  __shared__ int local[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x < 16) local[threadIdx.x] = 0;
+  __syncthreads();
+  if (i < n) atomicAdd(&local[order_bucket(m, i)], 1);
+  __syncthreads();
+  if (threadIdx.x < 16 && local[threadIdx.x] > 0) atomicAdd(&hist[threadIdx.x], local[threadIdx.x]);
 }
 
 __global__ void order_offsets_kernel(int* __restrict__ hist) {
@@ -783,13 +804,21 @@ __global__ void order_offsets_kernel(int* __restrict__ hist) {
   }
 }
 
-__global__ void order_scatter_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist,
-                                     int* __restrict__ list) {
+__global__ void __launch_bounds__(256)
+order_scatter_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist,
+                     int* __restrict__ list) {
+  __shared__ int local[16];
+  __shared__ int base[16];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int o = m[i];
-  o = o < 0 ? 0 : (o > 15 ? 15 : o);
-  list[atomicAdd(&hist[15 - o], 1)] = i;
+  if (threadIdx.x < 16) local[threadIdx.x] = 0;
+  __syncthreads();
+  const int b = (i < n) ? order_bucket(m, i) : 0;
+  const int rank = (i < n) ? atomicAdd(&local[b], 1) : 0;
+  __syncthreads();
+  if (threadIdx.x < 16 && local[threadIdx.x] > 0)
+    base[threadIdx.x] = atomicAdd(&hist[threadIdx.x], local[threadIdx.x]);
+  __syncthreads();
+  if (i < n) list[base[b] + rank] = i;
 }
 
 __global__ void max_order_kernel(const int8_t* __restrict__ m, int n, int* out) {
@@ -947,13 +976,22 @@ extern "C" int labfm_build_weights(const double* x, const double* y, const doubl
       });
       break;
     case LABFM_BUILD_BUCKETED: {
-      // one launch per order class, each with its own template
-      const int hi[4] = {15, 10, 8, 6};
+      // one launch per order class, each with the template of the highest
+      // order present in it
+      // classes by template: orders 9..15 (MMAX 10), 7..8, 5..6, 0..4
+      const int hi[4] = {15, 8, 6, 4};
       const int lo[4] = {9, 7, 5, 0};
       for (int c = 0; c < 4 && e == hipSuccess; ++c) {
         const int b0 = 15 - hi[c], b1 = 15 - lo[c];  // buckets b0..b1
         const int first = starts[b0], count = starts[b1 + 1] - first;
-        e = with_mmax(std::min(hi[c], 10), [&](auto M) {
+        if (count <= 0) continue;
+        int top = lo[c];
+        for (int b = b0; b <= b1; ++b)
+          if (starts[b + 1] > starts[b]) {
+            top = 15 - b;
+            break;
+          }
+        e = with_mmax(std::min(top, 10), [&](auto M) {
           return launch_block<decltype(M)::value>(g, list + first, count, st);
         });
       }

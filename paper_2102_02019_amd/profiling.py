@@ -36,28 +36,56 @@ def read_counter_csv(pattern: str) -> list:
     return rows
 
 
+def kernel_matches(name: str, pattern: str) -> bool:
+    """pattern is a plain substring, or several substrings joined by '*'
+    that must appear in that order."""
+    pos = 0
+    for part in pattern.split("*"):
+        k = name.find(part, pos)
+        if k < 0:
+            return False
+        pos = k + len(part)
+    return True
+
+
 def counter_per_dispatch(rows: list, kernel_substr: str, counter: str) -> list:
-    """Values of `counter` for each dispatch whose kernel name contains
-    kernel_substr (summed over the counter's dimensions)."""
+    """Values of `counter` for each dispatch whose kernel name matches
+    kernel_substr (summed over the counter's dimensions), in dispatch order."""
     per = {}
     for r in rows:
         name = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
-        if kernel_substr not in name or r.get("Counter_Name") != counter:
+        if not kernel_matches(name, kernel_substr) or r.get("Counter_Name") != counter:
             continue
         key = r.get("Dispatch_Id") or r.get("Correlation_Id")
         per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
     return [per[k] for k in sorted(per, key=lambda s: int(s))]
 
 
-def load_traffic(kernel: str, workload: str, source: str):
+# the gather kernels (apply, RK stage, filter) and their launch code
+GATHER_SOURCES = ("gather.hpp", "operators.hip", "common.hpp")
+
+
+def sources_hash(names=GATHER_SOURCES) -> str:
+    h = hashlib.sha256()
+    for name in names:
+        with open(kernel_source(name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, kernel_name: str = None):
     """HBM bytes per dispatch of `kernel` on `workload` from a committed
-    summary, or None if there is none or it was taken on other source."""
+    summary, or None if there is none, it was taken on other source, or (when
+    kernel_name is given) on another launch variant."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         s = json.load(f)
-    if s.get("source_hash") != source_hash(source):
+    if s.get("source_hash") != sources_hash():
+        return None
+    if kernel_name is not None and not kernel_matches(kernel_name, s["kernel_name_contains"]) \
+            and s["kernel_name_contains"] != kernel_name:
         return None
     return s.get("hbm_bytes_per_dispatch")
 
@@ -68,15 +96,21 @@ CALIBRATION_BYTES = 1 << 30       # 1 GiB read by the copy, 1 GiB written by fil
 
 
 def traffic_summary(kernel_tag: str, kernel_substr: str, workload: str, fetch_glob: str,
-                    write_glob: str, source: str, command: str) -> dict:
-    """Summarise FETCH_SIZE / WRITE_SIZE of one kernel, scaled by the same
-    counters read for the 1 GiB calibration copy of a profile run."""
+                    write_glob: str, command: str, last: int = 0,
+                    algorithmic_bytes: float = None) -> dict:
+    """Summarise FETCH_SIZE / WRITE_SIZE of one kernel (the last `last`
+    matching dispatches when last > 0), scaled by the same counters read for
+    the 1 GiB calibration copy of a profile run."""
     fr = read_counter_csv(fetch_glob)
     wr = read_counter_csv(write_glob)
     copy_fetch = max(counter_per_dispatch(fr, COPY_KERNEL, "FETCH_SIZE"))
     copy_write = max(counter_per_dispatch(wr, COPY_KERNEL, "WRITE_SIZE"))
     f = counter_per_dispatch(fr, kernel_substr, "FETCH_SIZE")
     w = counter_per_dispatch(wr, kernel_substr, "WRITE_SIZE")
+    if not f or not w:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel_substr!r}")
+    if last > 0:
+        f, w = f[-last:], w[-last:]
     fetch_factor = CALIBRATION_BYTES / (copy_fetch * 1024.0)
     write_factor = CALIBRATION_BYTES / (copy_write * 1024.0)
     fkib = sum(f) / len(f)
@@ -92,7 +126,8 @@ def traffic_summary(kernel_tag: str, kernel_substr: str, workload: str, fetch_gl
                              "write_kib": copy_write, "fetch_factor": fetch_factor,
                              "write_factor": write_factor},
         "hbm_bytes_per_dispatch": fkib * 1024.0 * fetch_factor + wkib * 1024.0 * write_factor,
-        "source_hash": source_hash(source),
+        "algorithmic_bytes_per_dispatch": algorithmic_bytes,
+        "source_hash": sources_hash(),
         "command": command,
     }
 
@@ -111,3 +146,38 @@ def kernel_stats_markdown(stats_csv: str, top: int = 12) -> str:
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
     return "\n".join(lines)
+
+
+def main(argv=None) -> None:
+    """Command line: write a traffic summary (JSON) or a kernel-trace table
+    (markdown) under profiles/ from rocprofv3 CSV output."""
+    import argparse
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2102_02019_amd.profiling")
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("traffic", help="FETCH_SIZE / WRITE_SIZE summary of one kernel")
+    t.add_argument("--tag", required=True, help="short kernel tag, e.g. rk_stage_f64")
+    t.add_argument("--match", required=True, help="kernel name pattern ('*' joins parts)")
+    t.add_argument("--workload", required=True)
+    t.add_argument("--fetch", required=True, help="glob of the FETCH_SIZE counter CSV files")
+    t.add_argument("--write", required=True, help="glob of the WRITE_SIZE counter CSV files")
+    t.add_argument("--last", type=int, default=0, help="use the last N matching dispatches")
+    t.add_argument("--algorithmic-bytes", type=float, default=None)
+    t.add_argument("--command", required=True, help="the rocprofv3 commands, for the record")
+    k = sub.add_parser("stats", help="markdown table of a --stats kernel summary")
+    k.add_argument("--csv", required=True, help="glob of the kernel_stats CSV file")
+    k.add_argument("--top", type=int, default=14)
+    a = ap.parse_args(argv)
+    if a.what == "traffic":
+        s = traffic_summary(a.tag, a.match, a.workload, a.fetch, a.write, a.command, a.last,
+                            a.algorithmic_bytes)
+        path = os.path.join(PROFILES, f"{a.tag}_{a.workload}_traffic.json")
+        with open(path, "w") as f:
+            json.dump(s, f, indent=1)
+        print(path, s["hbm_bytes_per_dispatch"])
+    else:
+        print(kernel_stats_markdown(a.csv, a.top))
+
+
+if __name__ == "__main__":
+    main()
