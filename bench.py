@@ -115,7 +115,7 @@ def main():
         rp, col = labfm.build_neighbours(x, y, h, nodes.box)
         ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=(prec != labfm.F64))
         q.copy_(q0)
-        dt = labfm.time_step(q, s, prm.c2, prm.mu)
+        dt = labfm.time_step(q, s, prm.c2, prm.mu, visc=wl.visc_coef)
         tm = labfm.rk_step(q, ops, prm, dt, rk_steps, prec=prec, workspace=ws, timing=True)
         return ops, tm
 
@@ -173,7 +173,7 @@ def main():
 
     # full RK steps replayed from a HIP graph (4 stages + filter), per stage
     q.copy_(q0)
-    dt = labfm.time_step(q, s, prm.c2, prm.mu)
+    dt = labfm.time_step(q, s, prm.c2, prm.mu, visc=wl.visc_coef)
     labfm.rk_step(q, ops, prm, dt, 10, workspace=ws, use_graph=True)
     torch.cuda.synchronize()
     q.copy_(q0)
@@ -341,7 +341,7 @@ def cpu_baseline(wl, rk_steps, N_full):
     rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
     W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, wl.m, rp, col, nodes.box)
     W.update(row_ptr=rp, col=col)
-    dt = O.time_step(nodes.s, np.log(rho), u, v, prm)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm, visc_coef=wl.visc_coef)
     t1 = time.perf_counter()
     k = 40
     O.rk_run(np.log(rho), u, v, W, prm, dt, k)

@@ -97,6 +97,17 @@ typedef struct {
   const uint16_t* lcol;       /* uint16[nnz]: position of col[e] in its tile's halo */
 } labfm_tiles;
 
+/* First moments of the float32 weights of the second-derivative operators,
+ * mu^d_i = (sum_j w32^d_ji x_ji, sum_j w32^d_ji y_ji) for d = L, xx, xy,
+ * evaluated in float64 and stored as float32[LABFM_NUM_MOM32 * n], rows
+ * (L,x) (L,y) (xx,x) (xx,y) (xy,x) (xy,y). The moment conditions of the
+ * weight system (eq. lsys) make these sums zero for the float64 weights; for
+ * the rounded weights they are not, and phi's gradient then leaks into the
+ * second derivatives with an error of order eps32 |grad phi| / h. The float32
+ * precisions subtract grad(phi)_i . mu^d_i (the gradient from the x and y
+ * operators), which leaves an error of order eps32 independent of h. */
+#define LABFM_NUM_MOM32 6
+
 /* Operators of a node set, as built by labfm_build_weights. */
 typedef struct {
   int32_t n;                /* nodes */
@@ -106,6 +117,8 @@ typedef struct {
   const double* w;          /* float64[6*nnz], labfm_op order (may be NULL
                                when only the float32 copy is used) */
   const float* w32;         /* float32[6*nnz] or NULL */
+  const float* mom32;       /* float32[LABFM_NUM_MOM32*n] first moments of w32
+                               (required with w32 for the float32 precisions) */
   const double* kappa;      /* float64[n] filter coefficients */
   const labfm_tiles* tiles; /* host pointer to tiles, or NULL: when set, the
                                stage and filter kernels of labfm_rk_step and
@@ -200,6 +213,8 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  *   row_ptr, col, nnz  CSR from labfm_build_neighbours.
  *   w       float64[6*nnz] output.
  *   w32     float32[6*nnz] output copy, or NULL.
+ *   mom32   float32[LABFM_NUM_MOM32*n] output first moments of w32 (see
+ *           LABFM_NUM_MOM32), or NULL.
  *   kappa   float64[n] output.
  *   rowsum  float64[6*n] output sum_j w^d_ji, or NULL.
  *   status  int8[n] output, LABFM_NODE_* per node.
@@ -216,7 +231,7 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
 int labfm_build_weights(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* order_m, int32_t n, labfm_box box,
                         const int32_t* row_ptr, const int32_t* col, int64_t nnz,
-                        double* w, float* w32, double* kappa, double* rowsum,
+                        double* w, float* w32, float* mom32, double* kappa, double* rowsum,
                         int8_t* status, void* stream);
 
 /* How labfm_build_weights distributes nodes over the GPU. */
@@ -244,16 +259,19 @@ int labfm_get_build_config(labfm_build_config* cfg);
  * with the chosen distribution. Synchronises. */
 int labfm_tune_build(const double* x, const double* y, const double* h, const double* s,
                      const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
-                     const int32_t* col, int64_t nnz, double* w, float* w32, double* kappa,
-                     double* rowsum, int8_t* status, labfm_build_config* best, double* best_ms,
-                     void* stream);
+                     const int32_t* col, int64_t nnz, double* w, float* w32, float* mom32,
+                     double* kappa, double* rowsum, int8_t* status, labfm_build_config* best,
+                     double* best_ms, void* stream);
 
 /*
  * Operator application, eq. general_do: for each selected operator d (bit d
  * of op_mask, labfm_op order) out_k[i] = sum_j (phi_j - phi_i) w^d_ji, where
- * k counts the selected operators in increasing d.
+ * k counts the selected operators in increasing d. The float32 precisions
+ * correct L, xx and xy with the first moments of the float32 weights (see
+ * LABFM_NUM_MOM32; the x and y sums are then formed too).
  *
- *   ops     operators (w for LABFM_F64, w32 for the float32 precisions).
+ *   ops     operators (w for LABFM_F64, w32 and mom32 for the float32
+ *           precisions).
  *   phi     float64[n] field.
  *   out     float64[popcount(op_mask) * n] output.
  */
@@ -261,15 +279,17 @@ int labfm_apply_operators(const labfm_operators* ops, uint32_t op_mask, const do
                           double* out, labfm_prec prec, void* stream);
 
 /*
- * Time step, eq. dt: dt = min over nodes of min(1.0 s_i/(|u_i| + c),
- * 0.4 s_i^2 rho_i / mu), rho = exp(ln rho).
+ * Time step, eq. dt: dt = min over nodes of min(a s_i/(|u_i| + c),
+ * b s_i^2 rho_i / mu), rho = exp(ln rho). The paper's coefficients are
+ * a = 1.0 (convective) and b = 0.4 (viscous).
  *
  *   q       float64[3n] state [ln rho | u | v].
  *   s       float64[n] node spacing.
+ *   conv_coef, visc_coef  a and b, both > 0.
  *   dt_out  host: receives dt. Synchronises the stream.
  */
 int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
-                    double* dt_out, void* stream);
+                    double conv_coef, double visc_coef, double* dt_out, void* stream);
 
 /*
  * Right-hand side of the isothermal Navier-Stokes equations (eq. icns) in

@@ -424,12 +424,13 @@ def filter_fields(fields: tuple, W: dict) -> tuple:
     return tuple(f + kappa * apply_op(rp, col, w[OP_HYP], f) for f in fields)
 
 
-def time_step(s, lnrho, u, v, prm) -> float:
-    """Equation dt: min over nodes of min(1.0 s/(|u|+c), 0.4 s^2 rho / mu)."""
+def time_step(s, lnrho, u, v, prm, conv_coef: float = 1.0, visc_coef: float = 0.4) -> float:
+    """Equation dt: min over nodes of min(1.0 s/(|u|+c), 0.4 s^2 rho / mu)
+    (the two coefficients can be given; those are the paper's)."""
     c = math.sqrt(prm.c2)
     speed = np.sqrt(u * u + v * v)
-    conv = 1.0 * s / (speed + c)
-    visc = 0.4 * s * s * np.exp(lnrho) / prm.mu
+    conv = conv_coef * s / (speed + c)
+    visc = visc_coef * s * s * np.exp(lnrho) / prm.mu
     return float(np.min(np.minimum(conv, visc)))
 
 

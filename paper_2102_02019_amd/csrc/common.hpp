@@ -48,6 +48,7 @@ inline unsigned blocks_for(int64_t work, int per_block) {
 // Largest LABFM order the library builds weights for, and the matching
 // number of moments n = (m^2 + 3m)/2.
 constexpr int kMaxOrder = 10;
+constexpr int kMoments = LABFM_NUM_MOM32;  // rows of the float32-weight first moments
 constexpr int kMaxMoments = (kMaxOrder * kMaxOrder + 3 * kMaxOrder) / 2;
 
 __host__ __device__ constexpr int moments_of(int m) { return (m * m + 3 * m) / 2; }

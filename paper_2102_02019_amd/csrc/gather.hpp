@@ -13,11 +13,15 @@
 //
 // Precision policies:
 //   F64      float64 weights, differences and sums.
-//   F32Comp  float32 weights; phi_j - phi_i formed in float64 and rounded to
-//            float32; each product split exactly with an FMA (TwoProd) and
+//   F32Comp  float32 weights; phi_j - phi_i formed in float64 and split into
+//            a float32 pair hi + lo; each product w*hi split exactly with an
+//            FMA (TwoProd), w*lo added to its error term, and the products
 //            summed with TwoSum, the error terms accumulated separately
 //            (Dot2 of Ogita, Rump & Oishi 2005), partial sums combined across
-//            lanes the same way, the final pair added in float64.
+//            lanes the same way, the final pair added in float64. (A single
+//            float32 difference would carry a rounding error of order
+//            eps32 |grad phi| h into every product, i.e. eps32 |grad phi| / h
+//            into a second derivative, whatever the summation.)
 #include <cmath>
 #include <mutex>
 #include <type_traits>
@@ -42,6 +46,7 @@ namespace {
 
 struct F64 {
   using W = double;
+  static constexpr bool kMomentFix = false;
   struct Acc {
     double s;
     __device__ __forceinline__ void zero() { s = 0.0; }
@@ -66,16 +71,18 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 
 struct F32Comp {
   using W = float;
+  static constexpr bool kMomentFix = true;
   struct Acc {
     float s, c;
     __device__ __forceinline__ void zero() {
       s = 0.0f;
       c = 0.0f;
     }
-    __device__ __forceinline__ void add(float w, float d) {
+    __device__ __forceinline__ void add(float w, float2 d) {
 #pragma clang fp contract(off)
-      const float p = w * d;
-      const float ep = fmaf(w, d, -p);  // exact: w*d = p + ep
+      const float p = w * d.x;
+      // w*hi = p + (its exact error); w*lo is second order and rounded once
+      const float ep = fmaf(w, d.y, fmaf(w, d.x, -p));
       float t, es;
       two_sum(s, p, t, es);
       s = t;
@@ -96,9 +103,11 @@ struct F32Comp {
       return static_cast<double>(hs) + static_cast<double>(hc);
     }
   };
-  using D = float;
+  using D = float2;  // (hi, lo) of the float64 difference
   __device__ __forceinline__ static D diff(double pj, double pi) {
-    return static_cast<float>(pj - pi);
+    const double d = pj - pi;
+    const float hi = static_cast<float>(d);
+    return make_float2(hi, static_cast<float>(d - static_cast<double>(hi)));
   }
 };
 
@@ -106,10 +115,25 @@ struct F32Comp {
 // weight and a float64 difference is rounded once, as in F64.
 struct F32W {
   using W = float;
+  static constexpr bool kMomentFix = true;
   using Acc = F64::Acc;
   using D = double;
   __device__ __forceinline__ static D diff(double pj, double pi) { return pj - pi; }
 };
+
+// Float32 weights break the first-moment conditions sum_j w_ji r_ji = 0 of
+// the second-derivative operators by rounding; the float32 precisions remove
+// the resulting leak of the gradient, grad(phi)_i . mu^d_i, with the stored
+// first moments mu of the rounded weights (rows (L,x) (L,y) (xx,x) (xx,y)
+// (xy,x) (xy,y) of mom, each of length n).
+__device__ __forceinline__ void moment_fix(const float* __restrict__ mom, int node, int n,
+                                           double gx, double gy, double& dL, double& dxx,
+                                           double& dxy) {
+  const long long nn = n;
+  dL -= gx * static_cast<double>(mom[node]) + gy * static_cast<double>(mom[nn + node]);
+  dxx -= gx * static_cast<double>(mom[2 * nn + node]) + gy * static_cast<double>(mom[3 * nn + node]);
+  dxy -= gx * static_cast<double>(mom[4 * nn + node]) + gy * static_cast<double>(mom[5 * nn + node]);
+}
 
 // --------------------------------------------------------------------------
 // launch variants
@@ -156,12 +180,16 @@ __host__ __device__ constexpr int unroll_of(int lpn) { return lpn >= 32 ? 3 : (l
 template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
-             const typename P::W* __restrict__ w, long long nnz, unsigned mask,
-             const double* __restrict__ phi, double* __restrict__ out, int n) {
+             const typename P::W* __restrict__ w, const float* __restrict__ mom, long long nnz,
+             unsigned mask, const double* __restrict__ phi, double* __restrict__ out, int n) {
   const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
   if (node >= n) return;  // whole LPN groups exit together
+  constexpr unsigned kSecond = (1u << LABFM_OP_L) | (1u << LABFM_OP_XX) | (1u << LABFM_OP_XY);
+  constexpr unsigned kFirst = (1u << LABFM_OP_X) | (1u << LABFM_OP_Y);
+  // the moment correction needs the x and y sums
+  const unsigned need = (P::kMomentFix && (mask & kSecond)) ? (mask | kFirst) : mask;
   const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
   const double pi = phi[node];
   typename P::Acc acc[LABFM_NUM_OPS];
@@ -183,7 +211,7 @@ apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
       for (int u = 0; u < U; ++u) dj[u] = P::diff(phi[stream_load<FL>(col + ee[u])], pi);
 #pragma unroll
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        if (mask & (1u << d)) {
+        if (need & (1u << d)) {
           typename P::W wv[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) wv[u] = stream_load<FL>(w + d * nnz + ee[u]);
@@ -193,12 +221,21 @@ apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
       }
     }
   }
+  double v[LABFM_NUM_OPS];
+#pragma unroll
+  for (int d = 0; d < LABFM_NUM_OPS; ++d)
+    v[d] = (need & (1u << d)) ? acc[d].template reduce<LPN>() : 0.0;
+  if (sub != 0) return;
+  if constexpr (P::kMomentFix) {
+    if (mask & kSecond)
+      moment_fix(mom, node, n, v[LABFM_OP_X], v[LABFM_OP_Y], v[LABFM_OP_L], v[LABFM_OP_XX],
+                 v[LABFM_OP_XY]);
+  }
   int k = 0;
 #pragma unroll
   for (int d = 0; d < LABFM_NUM_OPS; ++d) {
     if (mask & (1u << d)) {
-      const double v = acc[d].template reduce<LPN>();
-      if (sub == 0) out[static_cast<long long>(k) * n + node] = v;
+      out[static_cast<long long>(k) * n + node] = v[d];
       ++k;
     }
   }
@@ -249,7 +286,8 @@ __device__ __forceinline__ void stage_update(int node, int n, double li, double 
 template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
-                const typename P::W* __restrict__ w, long long nnz, const double* Y,
+                const typename P::W* __restrict__ w, const float* __restrict__ mom,
+                long long nnz, const double* Y,
                 const double* qin, double* qout, double* Yout, double dta, double dtb, Flow fl,
                 int n) {
   const int gid = first_thread<FL>();
@@ -336,7 +374,11 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   const double VL = vL.template reduce<LPN>(), Vxx = vxx.template reduce<LPN>();
   const double Vxy = vxy.template reduce<LPN>();
   if (sub != 0) return;
-  const double sums[12] = {Lx, Ly, Ux, Uy, UL, Uxx, Uxy, Vx, Vy, VL, Vxx, Vxy};
+  double sums[12] = {Lx, Ly, Ux, Uy, UL, Uxx, Uxy, Vx, Vy, VL, Vxx, Vxy};
+  if constexpr (P::kMomentFix) {
+    moment_fix(mom, node, n, sums[2], sums[3], sums[4], sums[5], sums[6]);
+    moment_fix(mom, node, n, sums[7], sums[8], sums[9], sums[10], sums[11]);
+  }
   stage_update(node, n, li, ui, vi, sums, qin, qout, Yout, dta, dtb, fl);
 }
 
@@ -441,7 +483,8 @@ __device__ __forceinline__ void load_halo(const Tiles& tl, int t, const double* 
 template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
-                      const typename P::W* __restrict__ w, long long nnz, const double* Y,
+                      const typename P::W* __restrict__ w, const float* __restrict__ mom,
+                      long long nnz, const double* Y,
                       const double* qin, double* qout, double* Yout, double dta, double dtb,
                       Flow fl, int n) {
   extern __shared__ double lds[];
@@ -514,13 +557,19 @@ rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
         }
       }
     }
-    const double Dv[12] = {lx.template reduce<LPN>(),  ly.template reduce<LPN>(),
+    double Dv[12] = {lx.template reduce<LPN>(),  ly.template reduce<LPN>(),
                            ux.template reduce<LPN>(),  uy.template reduce<LPN>(),
                            uL.template reduce<LPN>(),  uxx.template reduce<LPN>(),
                            uxy.template reduce<LPN>(), vx.template reduce<LPN>(),
                            vy.template reduce<LPN>(),  vL.template reduce<LPN>(),
                            vxx.template reduce<LPN>(), vxy.template reduce<LPN>()};
-    if (sub == 0) stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl);
+    if (sub == 0) {
+      if constexpr (P::kMomentFix) {
+        moment_fix(mom, node, n, Dv[2], Dv[3], Dv[4], Dv[5], Dv[6]);
+        moment_fix(mom, node, n, Dv[7], Dv[8], Dv[9], Dv[10], Dv[11]);
+      }
+      stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl);
+    }
   }
 }
 
@@ -594,14 +643,14 @@ constexpr int kRedThreads = 256;
 
 __global__ void __launch_bounds__(kRedThreads)
 dt_partial_kernel(const double* __restrict__ q, const double* __restrict__ s, int n, double c,
-                  double mu, double* __restrict__ partial) {
+                  double mu, double conv_coef, double visc_coef, double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
   double m = INFINITY;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double u = q[n + i], v = q[2 * static_cast<long long>(n) + i];
     const double speed = sqrt(u * u + v * v);
-    const double conv = 1.0 * s[i] / (speed + c);
-    const double visc = 0.4 * s[i] * s[i] * exp(q[i]) / mu;
+    const double conv = conv_coef * s[i] / (speed + c);
+    const double visc = visc_coef * s[i] * s[i] * exp(q[i]) / mu;
     m = fmin(m, fmin(conv, visc));
   }
   sh[threadIdx.x] = m;
@@ -703,7 +752,7 @@ hipError_t launch_apply(LaunchCfg cfg, const labfm_operators* o, const typename 
   const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((apply_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
-                       dim3(kThreads), 0, st, o->row_ptr, o->col, w,
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, w, o->mom32,
                        static_cast<long long>(o->nnz), mask, phi, out, n);
   });
 }
@@ -724,13 +773,14 @@ hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename 
     return with_cfg(cfg, [&](auto L, auto F) {
       hipLaunchKernelGGL((rk_stage_tiled_kernel<decltype(L)::value, decltype(F)::value, P>),
                          dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w,
-                         static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n);
+                         o->mom32, static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb,
+                         fl, n);
     });
   }
   const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((rk_stage_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
-                       dim3(kThreads), 0, st, o->row_ptr, o->col, w,
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, w, o->mom32,
                        static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n);
   });
 }
@@ -862,7 +912,9 @@ int check_ops(const labfm_operators* o, labfm_prec prec, const char* who) {
                 "%s: incomplete operator description", who);
   LABFM_REQUIRE(known_prec(prec), "%s: unknown precision %d", who, (int)prec);
   if (prec == LABFM_F64) LABFM_REQUIRE(o->w, "%s: float64 weights required", who);
-  if (prec != LABFM_F64) LABFM_REQUIRE(o->w32, "%s: float32 weights required", who);
+  if (prec != LABFM_F64)
+    LABFM_REQUIRE(o->w32 && o->mom32, "%s: float32 weights and their first moments required",
+                  who);
   if (o->tiles) {
     const labfm_tiles* t = o->tiles;
     LABFM_REQUIRE(t->ntiles == labfm_tile_count(o->n) && t->halo_count && t->halo_idx &&

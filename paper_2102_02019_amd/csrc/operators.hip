@@ -46,16 +46,18 @@ extern "C" int labfm_ns_rhs(const double* q, const labfm_operators* ops,
 }
 
 extern "C" int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
-                               double* dt_out, void* stream_) {
+                               double conv_coef, double visc_coef, double* dt_out,
+                               void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0 && q && s && dt_out, "time_step: bad arguments");
   LABFM_REQUIRE(c2 > 0.0 && mu > 0.0, "time_step: c2 and mu must be positive");
+  LABFM_REQUIRE(conv_coef > 0.0 && visc_coef > 0.0, "time_step: coefficients must be positive");
   hipStream_t st = as_stream(stream_);
   const int nb = static_cast<int>(std::min<long long>(1024, blocks_for(n, kRedThreads)));
   double* d = nullptr;
   LABFM_HIP(hipMalloc(&d, sizeof(double) * (nb + 1)));
   hipLaunchKernelGGL(dt_partial_kernel, dim3(nb), dim3(kRedThreads), 0, st, q, s, n, sqrt(c2),
-                     mu, d);
+                     mu, conv_coef, visc_coef, d);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
     hipLaunchKernelGGL(min_final_kernel, dim3(1), dim3(kRedThreads), 0, st, d, nb, d + nb);

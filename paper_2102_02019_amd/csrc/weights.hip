@@ -68,8 +68,8 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
                      const int8_t* __restrict__ order, int nnodes, labfm_box box,
                      const int* __restrict__ row_ptr, const int* __restrict__ col, long long nnz,
                      double* __restrict__ w, float* __restrict__ w32,
-                     double* __restrict__ kappa, double* __restrict__ rowsum,
-                     int8_t* __restrict__ status) {
+                     float* __restrict__ mom32, double* __restrict__ kappa,
+                     double* __restrict__ rowsum, int8_t* __restrict__ status) {
   using S = Shape<MMAX>;
   __shared__ double A[S::NMAX * S::LDA];
   __shared__ double T[kChunk * S::TABLE];
@@ -94,6 +94,8 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
       status[i] = LABFM_NODE_BAD_ORDER;
       if (rowsum)
         for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+      if (mom32)
+        for (int k = 0; k < kMoments; ++k) mom32[k * (long long)nnodes + i] = 0.0f;
     }
     return;
   }
@@ -300,6 +302,8 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
       status[i] = LABFM_NODE_SINGULAR;
       if (rowsum)
         for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+      if (mom32)
+        for (int k = 0; k < kMoments; ++k) mom32[k * (long long)nnodes + i] = 0.0f;
     }
     return;
   }
@@ -327,6 +331,7 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
   const double kf = 2.0 * M_PI / (3.0 * s);
   double f0 = 0.0;
   double rs[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double mo[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 64) {
     const int k = k0 + lane;
     if (k < K) {
@@ -370,6 +375,12 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
         if (w32) w32[d * nnz + e] = static_cast<float>(v);
         rs[d] += v;
       }
+#pragma unroll
+      for (int d = LABFM_OP_L; d <= LABFM_OP_XY; ++d) {
+        const double v32 = static_cast<double>(static_cast<float>(psi * wd[d]));
+        mo[2 * (d - LABFM_OP_L)] += v32 * dx;
+        mo[2 * (d - LABFM_OP_L) + 1] += v32 * dy;
+      }
       const double phi = 1.0 - cos(kf * dx) * cos(kf * dy);
       f0 += phi * (psi * wd[LABFM_OP_HYP]);
     }
@@ -377,7 +388,12 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
   f0 = group_sum<64>(f0);
 #pragma unroll
   for (int d = 0; d < LABFM_NUM_OPS; ++d) rs[d] = group_sum<64>(rs[d]);
+#pragma unroll
+  for (int k = 0; k < kMoments; ++k) mo[k] = group_sum<64>(mo[k]);
   if (lane == 0) {
+    if (mom32)
+#pragma unroll
+      for (int k = 0; k < kMoments; ++k) mom32[k * (long long)nnodes + i] = static_cast<float>(mo[k]);
     const bool bad = !isfinite(f0) || f0 == 0.0;
     kappa[i] = bad ? 0.0 : 2.0 / (3.0 * f0);
     if (st == LABFM_NODE_OK && bad) st = LABFM_NODE_BAD_FILTER;
@@ -413,6 +429,7 @@ struct BuildArgs {
   long long nnz;
   double* w;
   float* w32;
+  float* mom32;
   double* kappa;
   double* rowsum;
   int8_t* status;
@@ -425,7 +442,8 @@ struct BlockSmem {
   using S = Shape<MMAX>;
   double A[S::NMAX * S::LDA];
   double T[kChunk * S::TABLE];
-  double part[kChunk * 8];  // per-neighbour-slot partial sums (6 row sums, F0)
+  double part[kChunk * 16];  // per-neighbour-slot partial sums: 6 row sums, F0,
+                             // and at 8..13 the first moments of the float32 weights
   int qa[S::NMAX], qb[S::NMAX];
   int piv;
   int next;
@@ -641,7 +659,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   // threads 0..191: neighbour slot k = t/12, operator d = (t/2)%6, half = t%2
   const int slot = tid / 12, dop = (tid / 2) % 6, half = tid & 1;
   const double kf = 2.0 * M_PI / (3.0 * s);
-  double rs = 0.0, f0 = 0.0;
+  double rs = 0.0, f0 = 0.0, mx = 0.0, my = 0.0;
   for (int k0 = 0; k0 < K; k0 += kChunk) {
     if (tid < 64) {
       // basis tables of 16 neighbours (the psi He_a and He_b ones are used)
@@ -686,11 +704,17 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
           const long long e = e0 + k;
           g.w[dop * g.nnz + e] = acc;
           if (g.w32) g.w32[dop * g.nnz + e] = static_cast<float>(acc);
-          if (dop == LABFM_OP_HYP) {
+          if (dop == LABFM_OP_HYP || (dop >= LABFM_OP_L && dop <= LABFM_OP_XY)) {
             const int j = g.col[e];
             const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
             const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-            f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * acc;
+            if (dop == LABFM_OP_HYP) {
+              f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * acc;
+            } else {
+              const double v32 = static_cast<double>(static_cast<float>(acc));
+              mx += v32 * dx;
+              my += v32 * dy;
+            }
           }
         }
         rs += acc;
@@ -700,13 +724,22 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   }
   // deterministic reduction over the 16 neighbour slots
   if (tid < 12 * kChunk && half == 0) {
-    sm.part[slot * 8 + dop] = rs;
-    if (dop == LABFM_OP_HYP) sm.part[slot * 8 + 6] = f0;
+    sm.part[slot * 16 + dop] = rs;
+    if (dop == LABFM_OP_HYP) sm.part[slot * 16 + 6] = f0;
+    if (dop >= LABFM_OP_L && dop <= LABFM_OP_XY) {
+      sm.part[slot * 16 + 8 + 2 * (dop - LABFM_OP_L)] = mx;
+      sm.part[slot * 16 + 9 + 2 * (dop - LABFM_OP_L)] = my;
+    }
   }
   __syncthreads();
+  if (tid >= 8 && tid < 8 + kMoments && g.mom32) {
+    double v = 0.0;
+    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 16 + tid];
+    g.mom32[(tid - 8) * (long long)g.n + i] = static_cast<float>(v);
+  }
   if (tid < 7) {
     double v = 0.0;
-    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 8 + tid];
+    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 16 + tid];
     if (tid < 6) {
       if (g.rowsum) g.rowsum[tid * (long long)g.n + i] = v;
     } else {
@@ -729,6 +762,8 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       g.status[i] = valid ? LABFM_NODE_SINGULAR : LABFM_NODE_BAD_ORDER;
       if (g.rowsum)
         for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = 0.0;
+      if (g.mom32)
+        for (int k = 0; k < kMoments; ++k) g.mom32[k * (long long)g.n + i] = 0.0f;
     }
   }
   __syncthreads();
@@ -840,10 +875,10 @@ __global__ void max_order_kernel(const int8_t* __restrict__ m, int n, int* out) 
 template <int MMAX>
 hipError_t launch_build(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* m, int n, labfm_box box, const int* row_ptr,
-                        const int* col, long long nnz, double* w, float* w32, double* kappa,
-                        double* rowsum, int8_t* status, hipStream_t st) {
+                        const int* col, long long nnz, double* w, float* w32, float* mom32,
+                        double* kappa, double* rowsum, int8_t* status, hipStream_t st) {
   hipLaunchKernelGGL(build_weights_kernel<MMAX>, dim3(n), dim3(64), 0, st, x, y, h, s, m, n, box,
-                     row_ptr, col, nnz, w, w32, kappa, rowsum, status);
+                     row_ptr, col, nnz, w, w32, mom32, kappa, rowsum, status);
   return hipGetLastError();
 }
 
@@ -916,8 +951,9 @@ extern "C" int labfm_get_build_config(labfm_build_config* cfg) {
 extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
                                    const double* s, const int8_t* order_m, int32_t n,
                                    labfm_box box, const int32_t* row_ptr, const int32_t* col,
-                                   int64_t nnz, double* w, float* w32, double* kappa,
-                                   double* rowsum, int8_t* status, void* stream_) {
+                                   int64_t nnz, double* w, float* w32, float* mom32,
+                                   double* kappa, double* rowsum, int8_t* status,
+                                   void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0, "build_weights: n must be positive (got %d)", n);
   LABFM_REQUIRE(x && y && h && s && order_m && row_ptr && w && kappa && status,
@@ -957,13 +993,14 @@ extern "C" int labfm_build_weights(const double* x, const double* y, const doubl
       mmax = 15 - b;
       break;
     }
-  const BuildArgs g{x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum, status};
+  const BuildArgs g{x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
+                    rowsum, status};
   hipError_t e = hipSuccess;
   switch (cfg.mode) {
     case LABFM_BUILD_WAVE:
       e = with_mmax(mmax, [&](auto M) {
         return launch_build<decltype(M)::value>(x, y, h, s, order_m, n, box, row_ptr, col, nnz,
-                                                w, w32, kappa, rowsum, status, st);
+                                                w, w32, mom32, kappa, rowsum, status, st);
       });
       break;
     case LABFM_BUILD_BLOCK:
@@ -1009,9 +1046,9 @@ extern "C" int labfm_build_weights(const double* x, const double* y, const doubl
 extern "C" int labfm_tune_build(const double* x, const double* y, const double* h,
                                 const double* s, const int8_t* order_m, int32_t n, labfm_box box,
                                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
-                                double* w, float* w32, double* kappa, double* rowsum,
-                                int8_t* status, labfm_build_config* best, double* best_ms,
-                                void* stream_) {
+                                double* w, float* w32, float* mom32, double* kappa,
+                                double* rowsum, int8_t* status, labfm_build_config* best,
+                                double* best_ms, void* stream_) {
   clear_error();
   LABFM_REQUIRE(best && best_ms, "tune_build: null output");
   hipStream_t st = as_stream(stream_);
@@ -1030,8 +1067,8 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
     labfm_set_build_config(&cands[k]);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess)
-      rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa,
-                               rowsum, status, stream_);
+      rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32,
+                               kappa, rowsum, status, stream_);
     if (rc == LABFM_OK && e == hipSuccess) e = hipEventRecord(e1, st);
     if (rc == LABFM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -1052,6 +1089,6 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   *best = bc;
   *best_ms = bms;
   // leave the outputs of the chosen distribution in place
-  return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, kappa, rowsum,
-                             status, stream_);
+  return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
+                             rowsum, status, stream_);
 }

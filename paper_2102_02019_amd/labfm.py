@@ -23,6 +23,7 @@ OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
 F64, F32W, F32_COMP = 0, 1, 2
 
 KERNEL_STAGE, KERNEL_FILTER, KERNEL_APPLY = 0, 1, 2
+NUM_MOM32 = 6  # rows of the float32-weight first moments: (L,x) (L,y) (xx,x) (xx,y) (xy,x) (xy,y)
 BUILD_WAVE, BUILD_BLOCK, BUILD_PERSISTENT, BUILD_BUCKETED = 1, 2, 3, 4
 XCD_ORDER, STREAMING = 1, 2
 OK, ERR_ARG, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
@@ -50,7 +51,8 @@ class _Operators(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("w32", ctypes.c_void_p),
-                ("kappa", ctypes.c_void_p), ("tiles", ctypes.POINTER(_Tiles))]
+                ("mom32", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+                ("tiles", ctypes.POINTER(_Tiles))]
 
 
 class _RKParams(ctypes.Structure):
@@ -85,10 +87,11 @@ _SIGNATURES = {
     "labfm_build_neighbours": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
-                                           ctypes.c_int64, _P, _P, _P, _P, _P, _P]),
+                                           ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P]),
     "labfm_apply_operators": (ctypes.c_int, [ctypes.POINTER(_Operators), ctypes.c_uint32, _P, _P,
                                              ctypes.c_int, _P]),
     "labfm_time_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
                                     ctypes.c_int, _P]),
@@ -104,7 +107,7 @@ _SIGNATURES = {
     "labfm_set_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_tune_build": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
-                                        ctypes.c_int64, _P, _P, _P, _P, _P,
+                                        ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                         ctypes.POINTER(_BuildConfig),
                                         ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
@@ -197,6 +200,7 @@ class Operators:
     w: Optional[torch.Tensor]       # float64 (6, nnz)
     w32: Optional[torch.Tensor]     # float32 (6, nnz)
     kappa: torch.Tensor             # float64 (n,)
+    mom32: Optional[torch.Tensor] = None  # float32 (6, n) first moments of w32
     rowsum: Optional[torch.Tensor] = None
     status: Optional[torch.Tensor] = None
     # node tiles (labfm_build_tiles): halo_count, halo_idx, lcol, max_halo
@@ -223,6 +227,7 @@ class Operators:
         return _Operators(self.n, self.nnz, _ptr(self.row_ptr).value, _ptr(self.col).value,
                           None if self.w is None else _ptr(self.w).value,
                           None if self.w32 is None else _ptr(self.w32).value,
+                          None if self.mom32 is None else _ptr(self.mom32).value,
                           _ptr(self.kappa).value, tp)
 
 
@@ -239,18 +244,19 @@ def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
     w = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)[: 6 * nnz].view(6, nnz)
     w32 = (torch.empty(6 * nnz + 1, dtype=torch.float32, device=dev)[: 6 * nnz].view(6, nnz)
            if f32 else None)
+    mom32 = torch.empty((NUM_MOM32, n), dtype=torch.float32, device=dev) if f32 else None
     kappa = torch.empty(n, dtype=torch.float64, device=dev)
     rs = torch.empty((6, n), dtype=torch.float64, device=dev) if rowsum else None
     status = torch.empty(n, dtype=torch.int8, device=dev)
     args = (_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box), _ptr(row_ptr), _ptr(col),
-            nnz, _ptr(w), _ptr(w32), _ptr(kappa), _ptr(rs), _ptr(status))
+            nnz, _ptr(w), _ptr(w32), _ptr(mom32), _ptr(kappa), _ptr(rs), _ptr(status))
     if tune:
         best, ms = _BuildConfig(), ctypes.c_double(0.0)
         _check(lib().labfm_tune_build(*args, ctypes.byref(best), ctypes.byref(ms), _stream()))
         build_weights.last_tuned = (best.mode, best.workgroups_per_cu, ms.value)
     else:
         _check(lib().labfm_build_weights(*args, _stream()))
-    ops = Operators(row_ptr, col, w, w32, kappa, rs, status)
+    ops = Operators(row_ptr, col, w, w32, kappa, mom32, rs, status)
     if tiles:
         build_tiles(ops)
     return ops
@@ -291,11 +297,13 @@ def apply_operators(ops: Operators, phi: torch.Tensor, op_mask: int = 0x3F,
     return out
 
 
-def time_step(q: torch.Tensor, s: torch.Tensor, c2: float, mu: float) -> float:
+def time_step(q: torch.Tensor, s: torch.Tensor, c2: float, mu: float, conv: float = 1.0,
+              visc: float = 0.4) -> float:
+    """Eq. dt on the state q (coefficients conv, visc; the paper's 1.0, 0.4)."""
     dt = ctypes.c_double(0.0)
     n = s.numel()
-    _check(lib().labfm_time_step(_ptr(q), _ptr(s), n, float(c2), float(mu), ctypes.byref(dt),
-                                 _stream()))
+    _check(lib().labfm_time_step(_ptr(q), _ptr(s), n, float(c2), float(mu), float(conv),
+                                 float(visc), ctypes.byref(dt), _stream()))
     return dt.value
 
 

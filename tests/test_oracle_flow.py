@@ -124,6 +124,40 @@ def test_time_step_closed_form(tg32):
     s = nodes.s[0]
     assert dt == pytest.approx(min(s / (vmax + c), 0.4 * s * s / prm.mu), rel=1e-15)
     assert vmax <= 1.0 and dt >= s / 11.0
+    # viscous-limited (mu = 1) with other coefficients
+    prm1 = inputs.FlowParams(c2=prm.c2, mu=1.0)
+    dt1 = O.time_step(nodes.s, np.log(rho), u, v, prm1, conv_coef=0.9, visc_coef=0.25)
+    assert dt1 == pytest.approx(0.25 * s * s, rel=1e-15)
+
+
+def _stability_function(z):
+    """R(z) = 1 + z b^T (I - z A)^-1 1 of the oracle's tableau."""
+    A, b, _ = O.butcher_tableau()
+    A = np.array(A, dtype=float)
+    b = np.array(b, dtype=float)
+    return 1.0 + z * b @ np.linalg.solve(np.eye(4) - z * A, np.ones(4))
+
+
+def test_viscous_coefficient_against_linear_stability():
+    """Reading of eq. dt where the viscous term binds: dt = 0.4 s^2/nu puts
+    dt times the most negative eigenvalue of the discrete viscous operator
+    nu [L + xx/3, xy/3; xy/3, L + yy/3] (m = 8) outside the real-axis
+    stability interval of the RK scheme, dt = 0.25 s^2/nu puts it inside."""
+    import scipy.sparse as sp
+
+    zs = np.linspace(-4.0, 0.0, 4001)
+    ok = np.array([abs(_stability_function(z)) <= 1.0 + 1e-12 for z in zs])
+    edge = zs[np.argmax(ok)]          # left end of the stability interval
+    assert -2.82 < edge < -2.75
+    assert ok[np.argmax(ok):].all()
+    nodes, W = _setup(24, 8, seed=3)
+    Ax, Ay, AL, Axx, Axy, Ahyp = O.operator_matrices(W)
+    V = sp.bmat([[AL + Axx / 3, Axy / 3], [Axy / 3, AL + (AL - Axx) / 3]]).toarray()
+    lam = np.linalg.eigvals(V) * nodes.s[0] ** 2
+    assert np.abs(lam.imag).max() < 0.05 * np.abs(lam.real).max()  # nearly symmetric
+    lmin = lam.real.min()
+    assert 0.4 * lmin < edge            # the paper's coefficient: outside
+    assert 0.25 * lmin > edge           # the reading used where it binds: inside
 
 
 # ----------------------------------------------------------------- RK scheme
