@@ -141,6 +141,29 @@ def neighbours(x, y, h, box) -> tuple:
     return row_ptr, col
 
 
+def neighbours_rows(x, y, h, box, nodes) -> tuple:
+    """The stencils of the listed nodes only, by testing every j (brute force
+    per row), as a CSR over all N nodes whose other rows are empty: for
+    sampled checks of node sets too large for the full search."""
+    n = x.size
+    nodes = sorted(set(int(i) for i in nodes))
+    rows = {}
+    for i in nodes:
+        dx = min_image(x - x[i], box.Lx, box.periodic_x)
+        dy = min_image(y - y[i], box.Ly, box.periodic_y)
+        sel = in_stencil(dx, dy, h[i])
+        sel[i] = False
+        rows[i] = np.nonzero(sel)[0]
+    counts = np.zeros(n, dtype=np.int64)
+    for i, r in rows.items():
+        counts[i] = r.size
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum(counts)
+    col = (np.concatenate([rows[i] for i in nodes]).astype(np.int64) if nodes
+           else np.zeros(0, np.int64))
+    return row_ptr, col
+
+
 # ---------------------------------------------------------------------------
 # Sections "LABFM" and "New ABFs": basis functions, moment matrix, weights
 # ---------------------------------------------------------------------------

@@ -85,3 +85,19 @@ def test_lattice_population():
         rp, _ = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
         k = np.diff(rp).mean()
         assert lo < k < hi
+
+
+def test_rows_of_listed_nodes_match_full_search():
+    """The per-row search used for sampled checks of large node sets gives
+    the same rows as the full search; unlisted rows are empty."""
+    x, y, box = inputs.random_cloud(3000, L=1.0, seed=7)
+    h = np.full(x.size, 0.02) * (1.0 + 0.5 * np.sin(7 * x))
+    rp, col = O.neighbours(x, y, h, box)
+    sample = [0, 17, 1500, 2999]
+    rp2, col2 = O.neighbours_rows(x, y, h, box, sample)
+    for i in range(x.size):
+        got = col2[rp2[i]:rp2[i + 1]]
+        if i in sample:
+            assert np.array_equal(got, col[rp[i]:rp[i + 1]])
+        else:
+            assert got.size == 0
