@@ -445,7 +445,7 @@ struct BlockSmem {
   double part[kChunk * 16];  // per-neighbour-slot partial sums: 6 row sums, F0,
                              // and at 8..13 the first moments of the float32 weights
   int qa[S::NMAX], qb[S::NMAX];
-  int piv;
+  unsigned long long key[3];  // pivot keys of three consecutive columns
   int next;
 };
 
@@ -454,6 +454,20 @@ struct BlockSmem {
 // compiler cannot prove uniform, it may structure the loops so that the
 // waves of the workgroup pass through different sequences of barriers.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// Pivot key of a candidate a at row r: the bits of |a| (ordered like the
+// values, |a| >= 0) with the 7 lowest mantissa bits replaced by 127 - r, so
+// the largest key is the largest |a| and, among values equal to 2^-45
+// relative, the first row. Rows are < 128 (n <= 65).
+__device__ __forceinline__ unsigned long long pivot_key(double a, int r) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(fabs(a)));
+  return (b & ~0x7Full) | static_cast<unsigned long long>(127 - r);
+}
 
 template <int MMAX>
 __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm) {
@@ -480,12 +494,23 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
 
   // ---- basis tables and MFMA assembly --------------------------------------
   int tP[TPW], tQ[TPW];
+  // LDS offsets of this lane's A and B operands in a neighbour's tables
+  // (-1: moment index beyond n, operand 0)
+  int oa[TPW], ob[TPW], oc[TPW], od[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
     const int t = wave + 4 * k;
     tP[k] = (t < nb * nb) ? t / nb : -1;
     tQ[k] = (t < nb * nb) ? t % nb : -1;
+    const int p = tP[k] * 16 + (lane & 15);
+    const int q = tQ[k] * 16 + (lane & 15);
+    const bool pok = tP[k] >= 0 && p < n, qok = tQ[k] >= 0 && q < n;
+    oa[k] = pok ? sm.qa[p] : -1;
+    ob[k] = pok ? S::TW + sm.qb[p] : -1;
+    oc[k] = qok ? 2 * S::TW + sm.qa[q] : -1;
+    od[k] = qok ? 3 * S::TW + sm.qb[q] : -1;
   }
+  const double hinv = 1.0 / h;
   double4_t acc[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
@@ -498,14 +523,14 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         const int j = g.col[e0 + k];
         const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
         const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-        const double xs = dx / h, ys = dy / h;
+        const double xs = dx * hinv, ys = dy * hinv;
         const double z = (t == 0 || t == 2) ? xs : ys;
         if (t < 2) {
           double v = 1.0;
           tab[0] = 1.0;
 #pragma unroll
           for (int a = 1; a <= MMAX; ++a) {
-            v = v * z / static_cast<double>(a);
+            v = v * z * (1.0 / static_cast<double>(a));  // z^a / a!
             tab[a] = v;
           }
         } else {
@@ -533,11 +558,8 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
         if (tP[k] >= 0) {  // wave-uniform
-          const int p = tP[k] * 16 + (lane & 15);
-          const int q = tQ[k] * 16 + (lane & 15);
-          double av = 0.0, bv = 0.0;
-          if (p < n) av = tk[sm.qa[p]] * tk[S::TW + sm.qb[p]];
-          if (q < n) bv = tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]];
+          const double av = (oa[k] >= 0) ? tk[oa[k]] * tk[ob[k]] : 0.0;
+          const double bv = (oc[k] >= 0) ? tk[oc[k]] * tk[od[k]] : 0.0;
           acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
         }
       }
@@ -585,35 +607,25 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   __syncthreads();
 
   // ---- LU with partial pivoting on [M~ | C~] --------------------------------
+  // One barrier per column (two when rows are swapped): the threads that
+  // update column c+1 in step c also propose its pivot (LDS atomic max of the
+  // keys), so there is no separate pivot search. The multipliers are not
+  // kept (the right-hand sides are eliminated along).
   int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
+  if (tid < 3) sm.key[tid] = 0ull;
+  __syncthreads();
+  for (int r = tid; r < n; r += kBlock) atomicMax(&sm.key[0], pivot_key(sm.A[r * S::LDA], r));
+  __syncthreads();
   for (int c = 0; c < n; ++c) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int r = c + lane; r < n; r += 64) {
-        const double v = fabs(sm.A[r * S::LDA + c]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) sm.piv = (best > 0.0) ? bi : -1;  // -1: zero or non-finite column
-    }
-    __syncthreads();
-    const int bi = uniform(sm.piv);
-    if (bi < 0) {
+    const unsigned long long kc = uniform64(sm.key[c % 3]);
+    const unsigned long long vb = kc & ~0x7Full;
+    if (vb == 0ull || vb >= 0x7FF0000000000000ull) {  // zero or non-finite column
       singular = true;
       break;
     }
+    const int bi = 127 - static_cast<int>(kc & 0x7Full);
+    // the key of column c+2 is next written in step c+1, after a barrier
+    if (tid == 0) sm.key[(c + 2) % 3] = 0ull;
     const int width = (n - c) + LABFM_NUM_OPS;  // columns c..n-1 and the RHS
     if (bi != c) {
       for (int t = tid; t < width; t += kBlock) {
@@ -622,11 +634,9 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         sm.A[c * S::LDA + jj] = sm.A[bi * S::LDA + jj];
         sm.A[bi * S::LDA + jj] = t0;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const double pv = sm.A[c * S::LDA + c];
-    for (int r = c + 1 + tid; r < n; r += kBlock) sm.A[r * S::LDA + c] = sm.A[r * S::LDA + c] / pv;
-    __syncthreads();
+    const double inv = 1.0 / sm.A[c * S::LDA + c];
     const int W = width - 1;  // columns right of c
     const int groups = kBlock / W;
     const int rg = tid / W;
@@ -634,8 +644,18 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       const int t = tid - rg * W;
       const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
       const double ucj = sm.A[c * S::LDA + jj];
-      for (int r = c + 1 + rg; r < n; r += groups)
-        sm.A[r * S::LDA + jj] -= sm.A[r * S::LDA + c] * ucj;
+      unsigned long long best = 0ull;
+#pragma unroll 4
+      for (int r = c + 1 + rg; r < n; r += groups) {
+        const double l = sm.A[r * S::LDA + c] * inv;
+        const double v = fma(-l, ucj, sm.A[r * S::LDA + jj]);
+        sm.A[r * S::LDA + jj] = v;
+        if (t == 0) {
+          const unsigned long long kv = pivot_key(v, r);
+          best = kv > best ? kv : best;
+        }
+      }
+      if (t == 0 && best != 0ull) atomicMax(&sm.key[(c + 1) % 3], best);
     }
     __syncthreads();
   }
@@ -671,7 +691,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
           const int j = g.col[e0 + k];
           const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
           const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-          const double xs = dx / h, ys = dy / h;
+          const double xs = dx * hinv, ys = dy * hinv;
           const double z = (t == 2) ? xs : ys;
           const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
           double h0 = 1.0, h1 = z;
@@ -695,6 +715,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       const int k = k0 + slot;
       const double* tk = &sm.T[slot * S::TABLE];
       double acc = 0.0;
+#pragma unroll 4
       for (int q = half; q < n; q += 2)
         acc += (tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]]) *
                sm.A[q * S::LDA + S::NMAX + dop];

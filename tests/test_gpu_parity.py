@@ -642,8 +642,11 @@ def holes20k():
 
 def test_build_modes_agree(dev, holes20k):
     """Workgroup-per-node, persistent and per-order-class launches run the same
-    per-node code (bitwise equal); the one-wavefront kernel sums the weights in
-    another order (equal to rounding)."""
+    per-node code (bitwise equal). The one-wavefront kernel has its own LU
+    (pivot search, division instead of a reciprocal), so its weights differ
+    by up to cond(M~) eps, which is large for some m = 10 nodes whose
+    stencils a hole cuts: every node whose weights differ by more than 1e-9
+    is checked against 100 cond(M~) eps with the oracle's moment matrix."""
     from paper_2102_02019_amd import labfm
 
     nodes = holes20k
@@ -662,17 +665,19 @@ def test_build_modes_agree(dev, holes20k):
             assert np.array_equal(a, b), mode
     w1, k1, s1 = outs[labfm.BUILD_WAVE]
     assert np.array_equal(s1, ref[2])
-    # per-node weight differences on nodes with a full-rank system (nodes with
-    # fewer neighbours than moments have no unique weights); rounding is
-    # amplified by cond(M~), large for some m = 10 nodes of the grading ramp
-    rp = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)[0]
-    d = []
-    for i in np.nonzero(ref[2] == 0)[0]:
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    assert np.array_equal(ops.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(ops.col.cpu().numpy(), col)
+    ok = np.nonzero(ref[2] == 0)[0]
+    far = []
+    for i in ok:
         a, b = rp[i], rp[i + 1]
-        d.append(np.max(np.linalg.norm(w1[:, a:b] - ref[0][:, a:b], axis=1)
-                        / np.linalg.norm(ref[0][:, a:b], axis=1)))
-    d = np.array(d)
-    assert np.median(d) <= 1e-10 and np.quantile(d, 0.99) <= 1e-8, (np.median(d), d.max())
+        d = np.max(np.linalg.norm(w1[:, a:b] - ref[0][:, a:b], axis=1)
+                   / np.linalg.norm(ref[0][:, a:b], axis=1))
+        if d > 1e-9:
+            far.append((i, d))
+    for i, d in far:
+        assert d <= 100 * _cond(nodes, rp, col, i) * 2.2e-16, (i, d)
 
 
 def test_tune_build_picks_a_mode(dev, holes20k):
