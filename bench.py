@@ -260,6 +260,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, rk_steps, N)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(wl, rk_steps, N)
 
     print(json.dumps(out))
 
@@ -322,6 +323,63 @@ def build_rate(labfm, torch, np, nodes, x, y, h, s, m):
             "frac": fl / (best[1] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "distribution": {1: "wavefront-per-node", 2: "workgroup-per-node",
                              3: "persistent", 4: "per-order-class"}.get(mode[0], str(mode[0]))}
+
+
+def _oracle_sample(args):
+    """One oracle sample run (in a worker process): the same steps as
+    cpu_baseline on a 64 x 64 lattice of its own seed; returns the nodes,
+    the stencil + weight time and the RK time."""
+    wl_name, seed, k = args
+    import numpy as np
+
+    from oracle import labfm_oracle as O
+    from paper_2102_02019_amd import inputs
+
+    wl = inputs.WORKLOADS[wl_name]
+    nodes = inputs.jittered_lattice(64, L=wl.L, seed=seed, m=wl.m)
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    t0 = time.perf_counter()
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, wl.m, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm, visc_coef=wl.visc_coef)
+    t1 = time.perf_counter()
+    O.rk_run(np.log(rho), u, v, W, prm, dt, k)
+    t2 = time.perf_counter()
+    return nodes.n, t1 - t0, t2 - t1
+
+
+def cpu_baseline_all_cores(wl, rk_steps, N_full):
+    """The oracle on every host core: one single-threaded oracle process per
+    core, each on its own 64 x 64 sample (the node set splits into
+    independent pieces the way the GPU job would shard), aggregate
+    throughput over the wall time of the slowest, scaled per node to the
+    full job like cpu_baseline."""
+    import multiprocessing as mp
+
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    k = 20
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_sample, [(wl.name, 100 + c, k) for c in range(cores)])
+    wall = time.perf_counter() - t0
+    n_tot = sum(r[0] for r in res)
+    setup = max(r[1] for r in res)
+    step = max(r[2] for r in res)
+    setup_per_node = setup / (n_tot / cores)
+    step_per_node = step / (n_tot / cores * k)
+    job_s = N_full * (setup_per_node + rk_steps * step_per_node) / cores
+    return {
+        "value": N_full * 4 * rk_steps / job_s,
+        "unit": "node-updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{cores} processes x {n_tot // cores} nodes (64x64, m={wl.m}), stencils + "
+                   f"weights and {k} RK steps each, {wall:.1f} s wall; scaled per node to "
+                   f"{N_full} nodes and {rk_steps} steps"),
+    }
 
 
 def cpu_baseline(wl, rk_steps, N_full):
