@@ -55,7 +55,7 @@ template <int MMAX>
 struct Shape {
   static constexpr int NMAX = moments_of(MMAX);
   static constexpr int NB = (NMAX + 15) / 16;   // 16-wide MFMA tiles per side
-  static constexpr int LDA = NMAX + 6 + 1;       // row stride of [M | C] (odd)
+  static constexpr int LDA = (NMAX + 6) | 1;     // row stride of [M | C] (odd)
   static constexpr int TW = MMAX + 1;            // one basis table's length
   static constexpr int TABLE = 4 * TW;           // four tables per neighbour
   static constexpr int HW = 2 * TW + 1;          // per-lane Hermite row (odd)
@@ -440,13 +440,21 @@ constexpr int kBlock = 256;
 template <int MMAX>
 struct BlockSmem {
   using S = Shape<MMAX>;
-  double A[S::NMAX * S::LDA];
-  double T[kChunk * S::TABLE];
-  double part[kChunk * 16];  // per-neighbour-slot partial sums: 6 row sums, F0,
-                             // and at 8..13 the first moments of the float32 weights
+  // [M | C] from the end of the assembly to the end of the back substitution.
+  // Before it (assembly) and after it (weights) the same storage holds the
+  // basis tables of 16 neighbours (T) and, in the weights phase, the
+  // per-neighbour-slot partial sums (part: 6 row sums, F0, and at 8..13 the
+  // first moments of the float32 weights). This keeps a workgroup of m = 10
+  // within a quarter of the CU's LDS (four resident).
+  static constexpr int kAliased = kChunk * S::TABLE + kChunk * 16;
+  static constexpr int kSize = S::NMAX * S::LDA > kAliased ? S::NMAX * S::LDA : kAliased;
+  double A[kSize];
+  double psi[S::NMAX * LABFM_NUM_OPS];  // the solution, copied out of A
   int qa[S::NMAX], qb[S::NMAX];
   unsigned long long key[3];  // pivot keys of three consecutive columns
   int next;
+  __device__ double* T() { return A; }
+  __device__ double* part() { return A + kChunk * S::TABLE; }
 };
 
 // Every value that steers control flow around a barrier is made wave-uniform
@@ -470,10 +478,9 @@ __device__ __forceinline__ unsigned long long pivot_key(double a, int r) {
 }
 
 template <int MMAX>
-__device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm) {
+__device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm, int tid) {
   using S = Shape<MMAX>;
   constexpr int TPW = (S::NB * S::NB + 3) / 4;  // MFMA tiles per wave
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int i = uniform(i_in);
@@ -518,7 +525,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     if (tid < 64) {
       const int kk = lane >> 2, t = lane & 3;
       const int k = k0 + kk;
-      double* tab = &sm.T[kk * S::TABLE + t * S::TW];
+      double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
       if (k < K) {
         const int j = g.col[e0 + k];
         const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
@@ -554,7 +561,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < kChunk / 4; ++ks) {
-      const double* tk = &sm.T[(ks * 4 + (lane >> 4)) * S::TABLE];
+      const double* tk = &sm.T()[(ks * 4 + (lane >> 4)) * S::TABLE];
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
         if (tP[k] >= 0) {  // wave-uniform
@@ -676,6 +683,10 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   }
 
   // ---- weights, filter calibration, row sums --------------------------------
+  // the solution leaves A, whose storage the tables and sums take over
+  for (int t = tid; t < n * LABFM_NUM_OPS; t += kBlock)
+    sm.psi[t] = sm.A[(t / LABFM_NUM_OPS) * S::LDA + S::NMAX + t % LABFM_NUM_OPS];
+  __syncthreads();
   // threads 0..191: neighbour slot k = t/12, operator d = (t/2)%6, half = t%2
   const int slot = tid / 12, dop = (tid / 2) % 6, half = tid & 1;
   const double kf = 2.0 * M_PI / (3.0 * s);
@@ -685,7 +696,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       // basis tables of 16 neighbours (the psi He_a and He_b ones are used)
       const int kk = lane >> 2, t = lane & 3;
       const int k = k0 + kk;
-      double* tab = &sm.T[kk * S::TABLE + t * S::TW];
+      double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
       if (t >= 2) {
         if (k < K) {
           const int j = g.col[e0 + k];
@@ -713,12 +724,12 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     __syncthreads();
     if (tid < 12 * kChunk) {
       const int k = k0 + slot;
-      const double* tk = &sm.T[slot * S::TABLE];
+      const double* tk = &sm.T()[slot * S::TABLE];
       double acc = 0.0;
 #pragma unroll 4
       for (int q = half; q < n; q += 2)
         acc += (tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]]) *
-               sm.A[q * S::LDA + S::NMAX + dop];
+               sm.psi[q * LABFM_NUM_OPS + dop];
       acc += __shfl_xor(acc, 1);
       if (k < K) {
         if (half == 0) {
@@ -745,22 +756,22 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   }
   // deterministic reduction over the 16 neighbour slots
   if (tid < 12 * kChunk && half == 0) {
-    sm.part[slot * 16 + dop] = rs;
-    if (dop == LABFM_OP_HYP) sm.part[slot * 16 + 6] = f0;
+    sm.part()[slot * 16 + dop] = rs;
+    if (dop == LABFM_OP_HYP) sm.part()[slot * 16 + 6] = f0;
     if (dop >= LABFM_OP_L && dop <= LABFM_OP_XY) {
-      sm.part[slot * 16 + 8 + 2 * (dop - LABFM_OP_L)] = mx;
-      sm.part[slot * 16 + 9 + 2 * (dop - LABFM_OP_L)] = my;
+      sm.part()[slot * 16 + 8 + 2 * (dop - LABFM_OP_L)] = mx;
+      sm.part()[slot * 16 + 9 + 2 * (dop - LABFM_OP_L)] = my;
     }
   }
   __syncthreads();
   if (tid >= 8 && tid < 8 + kMoments && g.mom32) {
     double v = 0.0;
-    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 16 + tid];
+    for (int k = 0; k < kChunk; ++k) v += sm.part()[k * 16 + tid];
     g.mom32[(tid - 8) * (long long)g.n + i] = static_cast<float>(v);
   }
   if (tid < 7) {
     double v = 0.0;
-    for (int k = 0; k < kChunk; ++k) v += sm.part[k * 16 + tid];
+    for (int k = 0; k < kChunk; ++k) v += sm.part()[k * 16 + tid];
     if (tid < 6) {
       if (g.rowsum) g.rowsum[tid * (long long)g.n + i] = v;
     } else {
@@ -791,13 +802,22 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
 }
 
 // one workgroup per node of the list (or per node when list is null)
+// Waves per SIMD for the workgroup-per-node kernel: up to m = 8 the LDS of
+// seven workgroups fits a CU and the register allocator fits seven without
+// spilling; m = 10 is bounded by its LDS (four workgroups).
+template <int MMAX>
+constexpr int block_waves() {
+  return MMAX <= 8 ? 7 : 4;
+}
+
 template <int MMAX>
 __global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(block_waves<MMAX>())))
 build_block_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   __shared__ BlockSmem<MMAX> sm;
   const int k = blockIdx.x;
   if (k >= count) return;
-  build_node_block<MMAX>(list ? list[k] : k, g, sm);
+  build_node_block<MMAX>(list ? list[k] : k, g, sm, threadIdx.x);
 }
 
 // Waves per SIMD that the workgroup-per-node kernel reaches for each MMAX (by
@@ -806,7 +826,7 @@ build_block_kernel(BuildArgs g, const int* __restrict__ list, int count) {
 // one resident workgroup per CU less.
 template <int MMAX>
 constexpr int persistent_waves() {
-  return MMAX <= 6 ? 5 : (MMAX <= 8 ? 4 : 3);
+  return MMAX <= 8 ? 6 : 4;
 }
 
 // persistent: workgroups take list entries through *counter until exhausted
@@ -821,7 +841,12 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
     const int k = uniform(sm.next);
     if (k >= count) break;  // the same value for every thread of the workgroup
     // ends with a barrier, so sm.next is read by all before it is rewritten
-    build_node_block<MMAX>(list[k], g, sm);
+    // the thread index passes through an empty asm statement in every
+    // iteration, so nothing derived from it is kept live across nodes (which
+    // would cost registers and occupancy)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    build_node_block<MMAX>(list[k], g, sm, tid);
   }
 }
 
