@@ -446,7 +446,7 @@ struct BlockSmem {
   // per-neighbour-slot partial sums (part: 6 row sums, F0, and at 8..13 the
   // first moments of the float32 weights). This keeps a workgroup of m = 10
   // within a quarter of the CU's LDS (four resident).
-  static constexpr int kAliased = kChunk * S::TABLE + kChunk * 16;
+  static constexpr int kAliased = kChunk * S::TABLE + kChunk * 16 + 4 * kChunk;
   static constexpr int kSize = S::NMAX * S::LDA > kAliased ? S::NMAX * S::LDA : kAliased;
   double A[kSize];
   double psi[S::NMAX * LABFM_NUM_OPS];  // the solution, copied out of A
@@ -455,6 +455,38 @@ struct BlockSmem {
   int next;
   __device__ double* T() { return A; }
   __device__ double* part() { return A + kChunk * S::TABLE; }
+  // weights phase: offsets and filter cosines of the chunk's neighbours
+  __device__ double* nb() { return A + kChunk * S::TABLE + kChunk * 16; }
+};
+
+// Coordinates of one neighbour per table lane, fetched ahead of their chunk:
+// the column index two chunks ahead and the coordinates one chunk ahead, so
+// that no dependent global load sits between a chunk's barrier and its
+// tables (the LDS-only barriers leave these loads in flight).
+struct NbrPrefetch {
+  int j2;          // column index of the lane's neighbour two chunks ahead (-1: none)
+  double x1, y1;   // coordinates of its neighbour one chunk ahead
+  bool v1;
+  __device__ void init(const BuildArgs& g, int e0, int K, int kk) {
+    v1 = kk < K;
+    const int j = v1 ? g.col[e0 + kk] : 0;
+    x1 = v1 ? g.x[j] : 0.0;
+    y1 = v1 ? g.y[j] : 0.0;
+    j2 = (kChunk + kk < K) ? g.col[e0 + kChunk + kk] : -1;
+  }
+  // this chunk's coordinates (false: no neighbour); issues the next loads
+  __device__ bool advance(const BuildArgs& g, int e0, int K, int k0, int kk, double& xj,
+                          double& yj) {
+    xj = x1;
+    yj = y1;
+    const bool v = v1;
+    v1 = j2 >= 0;
+    x1 = v1 ? g.x[j2] : 0.0;
+    y1 = v1 ? g.y[j2] : 0.0;
+    const int k3 = k0 + 2 * kChunk + kk;
+    j2 = (k3 < K) ? g.col[e0 + k3] : -1;
+    return v;
+  }
 };
 
 // Every value that steers control flow around a barrier is made wave-uniform
@@ -462,10 +494,28 @@ struct BlockSmem {
 // compiler cannot prove uniform, it may structure the loops so that the
 // waves of the workgroup pass through different sequences of barriers.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroup barrier that orders LDS only: the workgroup shares no global
+// data within a node (positions are read-only, each weight is written by one
+// thread), so outstanding global loads and stores stay in flight across it
+// (a full __syncthreads waits for all of them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
   const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
   const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
   return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// a / b for 0 <= a <= 256 and 1 <= b <= 128 (no integer divide instruction):
+// (a + 1/2) / b is at least 1/(2b) away from an integer, far more than the
+// float32 rounding of (a + 1/2) * rcp(b).
+__device__ __forceinline__ int small_div(int a, int b) {
+  return static_cast<int>((static_cast<float>(a) + 0.5f) *
+                          __builtin_amdgcn_rcpf(static_cast<float>(b)));
 }
 
 // Pivot key of a candidate a at row r: the bits of |a| (ordered like the
@@ -497,7 +547,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
   const int px = g.box.periodic_x, py = g.box.periodic_y;
   for (int p = tid; p < n; p += kBlock) exponents_of(p, sm.qa[p], sm.qb[p]);
-  __syncthreads();
+  lds_barrier();
 
   // ---- basis tables and MFMA assembly --------------------------------------
   int tP[TPW], tQ[TPW];
@@ -521,15 +571,17 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   double4_t acc[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+  NbrPrefetch pf;
+  if (tid < 64) pf.init(g, e0, K, lane >> 2);
   for (int k0 = 0; k0 < K; k0 += kChunk) {
     if (tid < 64) {
       const int kk = lane >> 2, t = lane & 3;
-      const int k = k0 + kk;
+      double xj, yj;
+      const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
       double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
-      if (k < K) {
-        const int j = g.col[e0 + k];
-        const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
-        const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+      if (have) {
+        const double dx = wrap_axis(xj - xi, g.box.Lx, px);
+        const double dy = wrap_axis(yj - yi, g.box.Ly, py);
         const double xs = dx * hinv, ys = dy * hinv;
         const double z = (t == 0 || t == 2) ? xs : ys;
         if (t < 2) {
@@ -558,7 +610,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         for (int a = 0; a <= MMAX; ++a) tab[a] = 0.0;
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int ks = 0; ks < kChunk / 4; ++ks) {
       const double* tk = &sm.T()[(ks * 4 + (lane >> 4)) * S::TABLE];
@@ -571,7 +623,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   // element v of lane l holds D[l/16 + 4v][l%16] of its tile
 #pragma unroll
@@ -587,7 +639,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   }
   for (int t = tid; t < n * LABFM_NUM_OPS; t += kBlock)
     sm.A[(t / LABFM_NUM_OPS) * S::LDA + S::NMAX + t % LABFM_NUM_OPS] = 0.0;
-  __syncthreads();
+  lds_barrier();
   if (tid == 0) {
     const double h1 = 1.0 / h, h2 = 1.0 / (h * h);
     const int C0 = S::NMAX;
@@ -611,7 +663,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // ---- LU with partial pivoting on [M~ | C~] --------------------------------
   // One barrier per column (two when rows are swapped): the threads that
@@ -620,9 +672,9 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   // kept (the right-hand sides are eliminated along).
   int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
   if (tid < 3) sm.key[tid] = 0ull;
-  __syncthreads();
+  lds_barrier();
   for (int r = tid; r < n; r += kBlock) atomicMax(&sm.key[0], pivot_key(sm.A[r * S::LDA], r));
-  __syncthreads();
+  lds_barrier();
   for (int c = 0; c < n; ++c) {
     const unsigned long long kc = uniform64(sm.key[c % 3]);
     const unsigned long long vb = kc & ~0x7Full;
@@ -641,12 +693,12 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         sm.A[c * S::LDA + jj] = sm.A[bi * S::LDA + jj];
         sm.A[bi * S::LDA + jj] = t0;
       }
-      __syncthreads();
+      lds_barrier();
     }
     const double inv = 1.0 / sm.A[c * S::LDA + c];
     const int W = width - 1;  // columns right of c
-    const int groups = kBlock / W;
-    const int rg = tid / W;
+    const int groups = small_div(kBlock, W);
+    const int rg = small_div(tid, W);
     if (rg < groups) {
       const int t = tid - rg * W;
       const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
@@ -664,7 +716,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       }
       if (t == 0 && best != 0ull) atomicMax(&sm.key[(c + 1) % 3], best);
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (!singular) {
   // ---- back substitution ----------------------------------------------------
@@ -673,35 +725,42 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       const int jj = S::NMAX + tid;
       sm.A[c * S::LDA + jj] = sm.A[c * S::LDA + jj] / sm.A[c * S::LDA + c];
     }
-    __syncthreads();
+    lds_barrier();
     for (int t = tid; t < c * LABFM_NUM_OPS; t += kBlock) {
       const int r = t / LABFM_NUM_OPS, d = t - r * LABFM_NUM_OPS;
       const int jj = S::NMAX + d;
       sm.A[r * S::LDA + jj] -= sm.A[r * S::LDA + c] * sm.A[c * S::LDA + jj];
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---- weights, filter calibration, row sums --------------------------------
   // the solution leaves A, whose storage the tables and sums take over
   for (int t = tid; t < n * LABFM_NUM_OPS; t += kBlock)
     sm.psi[t] = sm.A[(t / LABFM_NUM_OPS) * S::LDA + S::NMAX + t % LABFM_NUM_OPS];
-  __syncthreads();
+  lds_barrier();
   // threads 0..191: neighbour slot k = t/12, operator d = (t/2)%6, half = t%2
   const int slot = tid / 12, dop = (tid / 2) % 6, half = tid & 1;
   const double kf = 2.0 * M_PI / (3.0 * s);
   double rs = 0.0, f0 = 0.0, mx = 0.0, my = 0.0;
+  double* nbx = sm.nb();  // [0, 16): dx, [16, 32): dy, [32, 48): cos(kf dx), [48, 64): cos(kf dy)
+  if (tid < 64) pf.init(g, e0, K, lane >> 2);
   for (int k0 = 0; k0 < K; k0 += kChunk) {
     if (tid < 64) {
-      // basis tables of 16 neighbours (the psi He_a and He_b ones are used)
+      // basis tables of 16 neighbours (the psi He_a and He_b ones are used);
+      // lanes t = 0, 1 keep each neighbour's offset and filter cosine
       const int kk = lane >> 2, t = lane & 3;
-      const int k = k0 + kk;
+      double xj, yj;
+      const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
       double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
-      if (t >= 2) {
-        if (k < K) {
-          const int j = g.col[e0 + k];
-          const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
-          const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+      const double dx = have ? wrap_axis(xj - xi, g.box.Lx, px) : 0.0;
+      const double dy = have ? wrap_axis(yj - yi, g.box.Ly, py) : 0.0;
+      if (t < 2) {
+        const double d = (t == 0) ? dx : dy;
+        nbx[t * kChunk + kk] = d;
+        nbx[(2 + t) * kChunk + kk] = have ? cos(kf * d) : 1.0;
+      } else {
+        if (have) {
           const double xs = dx * hinv, ys = dy * hinv;
           const double z = (t == 2) ? xs : ys;
           const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
@@ -721,7 +780,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 12 * kChunk) {
       const int k = k0 + slot;
       const double* tk = &sm.T()[slot * S::TABLE];
@@ -736,23 +795,18 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
           const long long e = e0 + k;
           g.w[dop * g.nnz + e] = acc;
           if (g.w32) g.w32[dop * g.nnz + e] = static_cast<float>(acc);
-          if (dop == LABFM_OP_HYP || (dop >= LABFM_OP_L && dop <= LABFM_OP_XY)) {
-            const int j = g.col[e];
-            const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
-            const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-            if (dop == LABFM_OP_HYP) {
-              f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * acc;
-            } else {
-              const double v32 = static_cast<double>(static_cast<float>(acc));
-              mx += v32 * dx;
-              my += v32 * dy;
-            }
+          if (dop == LABFM_OP_HYP) {
+            f0 += (1.0 - nbx[2 * kChunk + slot] * nbx[3 * kChunk + slot]) * acc;
+          } else if (dop >= LABFM_OP_L && dop <= LABFM_OP_XY) {
+            const double v32 = static_cast<double>(static_cast<float>(acc));
+            mx += v32 * nbx[slot];
+            my += v32 * nbx[kChunk + slot];
           }
         }
         rs += acc;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   // deterministic reduction over the 16 neighbour slots
   if (tid < 12 * kChunk && half == 0) {
@@ -763,7 +817,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       sm.part()[slot * 16 + 9 + 2 * (dop - LABFM_OP_L)] = my;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (tid >= 8 && tid < 8 + kMoments && g.mom32) {
     double v = 0.0;
     for (int k = 0; k < kChunk; ++k) v += sm.part()[k * 16 + tid];
@@ -798,7 +852,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         for (int k = 0; k < kMoments; ++k) g.mom32[k * (long long)g.n + i] = 0.0f;
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // one workgroup per node of the list (or per node when list is null)
@@ -837,7 +891,7 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
   __shared__ BlockSmem<MMAX> sm;
   for (;;) {
     if (threadIdx.x == 0) sm.next = atomicAdd(counter, 1);
-    __syncthreads();
+    lds_barrier();
     const int k = uniform(sm.next);
     if (k >= count) break;  // the same value for every thread of the workgroup
     // ends with a barrier, so sm.next is read by all before it is rewritten
