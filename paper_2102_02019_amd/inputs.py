@@ -249,6 +249,27 @@ def _place_nodes(L: float, smin: float, sgrid: np.ndarray, max_nodes: int) -> tu
     return x[:n].copy(), y[:n].copy()
 
 
+def variable_resolution(s0: float, m: int = 6, L: float = 1.0, grid: int = 1024) -> NodeSet:
+    """Periodic square of side L whose spacing varies smoothly with x, from
+    s0 at x = 0, L/2, L to s0/2 at x = L/4, 3L/4:
+        s(x) = s0 (3 + cos(4 pi x / L)) / 4,
+    nodes placed by the paper's sweep for that spacing (no iterative
+    shifting: the shifting iteration as read clusters nodes), h = (h/s)_m s
+    with s scaled to the sweep's packing like graded_holes, Morton ordered."""
+    g = (np.arange(grid) + 0.5) * (L / grid)
+    sgrid = np.tile(s0 * (3.0 + np.cos(4.0 * np.pi * g / L)) / 4.0, (grid, 1))
+    x, y = _place_nodes(L, 0.5 * s0, sgrid, int(8 * L * L / (0.25 * s0 * s0)))
+    s = s0 * (3.0 + np.cos(4.0 * np.pi * x / L)) / 4.0 * SWEEP_SPACING_FACTOR
+    h = H_OVER_S[m] * s
+    box = Box(L, L, True, True)
+    order = morton_order(x, y, box, 0.5 * s0)
+    return NodeSet(
+        x=np.ascontiguousarray(x[order]), y=np.ascontiguousarray(y[order]),
+        s=np.ascontiguousarray(s[order]), h=np.ascontiguousarray(h[order]),
+        m=np.full(x.size, m, dtype=np.int8), box=box, meta={"s0": s0},
+    )
+
+
 @dataclass(frozen=True)
 class HoleField:
     centres: np.ndarray  # (k, 2)

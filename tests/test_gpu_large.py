@@ -218,3 +218,39 @@ def test_graded_holes_1m_build(dev):
         assert idx.size > 0
         sample += list(idx[:: max(1, idx.size // 10)][:10])
     check_sampled_rows(nodes, blk, sample)
+
+
+# ------------------------------------------------------- variable resolution
+
+@pytest.mark.parametrize("m", [6, 8])
+def test_variable_resolution_convergence(dev, m):
+    """Smoothly varying resolution (s from s0 to s0/2, eq. square of the
+    variable-resolution section): over s0 = 1/64 ... 1/192 the GPU gradient
+    converges at rate about m and the Laplacian at m - 1 or better; at
+    s0 = 1/64 (m = 6) the oracle gives the same errors."""
+    import math
+
+    from fields import square_wave
+    from paper_2102_02019_amd import labfm
+
+    res = [64, 96, 128, 192]
+    errs = []
+    for r in res:
+        nodes = inputs.variable_resolution(1.0 / r, m=m)
+        ops = gpu_setup(nodes, dev)
+        assert int((ops.status != 0).sum().item()) == 0
+        phi, px, py, lap = square_wave(nodes.x, nodes.y)
+        d = labfm.apply_operators(ops, T(phi, dev), (1 << 0) | (1 << 1) | (1 << 2)).cpu().numpy()
+        eg = math.sqrt(np.sum((d[0] - px) ** 2 + (d[1] - py) ** 2) / np.sum(px ** 2 + py ** 2))
+        el = rel(d[2], lap)
+        errs.append((eg, el))
+        if r == 64 and m == 6:
+            rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+            W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box)
+            ref = [O.apply_op(rp, col, W["w"][k], phi) for k in range(3)]
+            for k in range(3):
+                assert rel(d[k], ref[k]) <= 1e-10, k
+    e = np.array(errs)
+    slopes = -np.diff(np.log(e), axis=0) / np.log(np.array(res[1:]) / np.array(res[:-1]))[:, None]
+    assert np.all(slopes[1:, 0] > m - 0.7), slopes
+    assert np.all(slopes[1:, 1] > m - 1.5), slopes
