@@ -14,8 +14,9 @@ OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # gfx950 HIP flags: packed fp32 instructions are switched off for all device
-# code; the stencil test in the neighbour search uses explicit round-to-nearest
-# intrinsics, so contraction elsewhere is left to the compiler.
+# code. Floating-point contraction is left to the compiler except where a
+# result must be rounded step by step (the stencil distance test and the
+# error-free transformations), which switch it off locally.
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
