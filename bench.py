@@ -63,6 +63,9 @@ def parse():
                     help="pin the gather kernels' launch shapes instead of tuning: JSON "
                          "{prec: {kernel: [lanes_per_node, flags]}} inline, or the path of a "
                          "JSON file holding it under 'launch_shapes' (a bench output line)")
+    ap.add_argument("--stencil-opt", action="store_true",
+                    help="instead of the solver job: time the stencil optimisation on the "
+                         "workload and on the 1.0M-node graded set (one JSON line)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: a 1 GiB copy, then warmup jobs only")
     return ap.parse_args()
@@ -81,6 +84,9 @@ def main():
     from paper_2102_02019_amd import inputs, labfm, profiling
 
     dev = torch.device("cuda:0")
+    if args.stencil_opt:
+        print(json.dumps(stencil_opt_bench(args, inputs, labfm, torch, np, dev)))
+        return
     wl = inputs.WORKLOADS[args.workload]
     rk_steps = wl.steps if args.rk_steps is None else args.rk_steps
     nodes = wl.nodes()
@@ -266,6 +272,60 @@ def main():
 
 
 PREC_TAG = {"f64": "F64", "f32w": "F32W", "f32_comp": "F32Comp"}
+
+
+def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
+    """The stencil optimisation (h_i from 2.8 s_i shrunk by 0.99 while the
+    node passes the residual and amplitude tests) on the workload's nodes and
+    on the 1.0M-node graded set: time (HIP events around the call, which
+    includes its h0 stencil search), tests per node, the FP64 FLOP/s of the
+    node systems it builds, neighbours before and after; and the oracle's
+    per-node loop timed on a sample of the workload."""
+    from oracle import labfm_oracle as O
+
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    res = {"metric": "stencil optimisation: nodes/s and FP64 FLOP/s of the per-node systems",
+           "runs": []}
+    sets = [(args.workload, inputs.WORKLOADS[args.workload].nodes()),
+            ("holes1m", inputs.graded_holes(1_000_000, seed=3))]
+    for name, nodes in sets:
+        x, y, s, m = T(nodes.x), T(nodes.y), T(nodes.s), T(nodes.m)
+        h0 = (O.STENCIL_H0_OVER_S * s).contiguous()
+        labfm.optimise_stencils(x, y, s, m, nodes.box, h0=h0)  # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        h, k = labfm.optimise_stencils(x, y, s, m, nodes.box, h0=h0)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        rp0, _ = labfm.build_neighbours(x, y, h0, nodes.box)
+        rp1, _ = labfm.build_neighbours(x, y, h, nodes.box)
+        rpu, _ = labfm.build_neighbours(x, y, T(nodes.h), nodes.box)
+        K0 = np.diff(rp0.cpu().numpy()).astype(np.float64)
+        kk = k.cpu().numpy().astype(np.float64)
+        tests = kk + 2.0  # the accepted scales and the one that failed
+        fl = float(np.sum(tests * build_flops(nodes.m.astype(np.float64), K0)))
+        res["runs"].append({
+            "nodes": nodes.n, "set": name, "orders": sorted(set(int(v) for v in nodes.m)),
+            "ms": ms, "nodes_per_s": nodes.n / (ms * 1e-3),
+            "tests_per_node": float(tests.mean()),
+            "gflop": fl / 1e9, "achieved_TFLOPs": fl / (ms * 1e-3) / 1e12,
+            "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "h_over_s_mean": float((h / s).mean().item()),
+            "neighbours_mean": {"h0": float(K0.mean()),
+                                "uniform_h_over_s": float(rpu[-1].item() / nodes.n),
+                                "optimised": float(rp1[-1].item() / nodes.n)}})
+    # the oracle's loop on a sample of the workload (one core)
+    nodes = sets[0][1]
+    sample = list(range(0, nodes.n, nodes.n // 24))
+    t0 = time.perf_counter()
+    O.optimise_stencils(nodes.x, nodes.y, nodes.s, nodes.m, nodes.box,
+                        h0=O.STENCIL_H0_OVER_S * nodes.s, nodes=sample)
+    t1 = time.perf_counter()
+    res["cpu_baseline"] = {"value": len(sample) / (t1 - t0), "unit": "nodes/s", "cores": 1,
+                           "kind": "oracle", "sample": f"{len(sample)} nodes of {sets[0][0]}"}
+    return res
 
 
 def pinned_shapes(spec, precs, labfm):

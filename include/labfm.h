@@ -234,6 +234,50 @@ int labfm_build_weights(const double* x, const double* y, const double* h, const
                         double* w, float* w32, float* mom32, double* kappa, double* rowsum,
                         int8_t* status, void* stream);
 
+/*
+ * Stencil optimisation (section "Stencil optimisation"): for every node, the
+ * stencil scale h_i shrinks from h0_i by the factor `shrink` while the
+ * stencil passes two tests, and the last scale that passed is kept (h0_i
+ * when none did):
+ *   1. the residual of the node's Laplacian system is small:
+ *        alpha_L = || M Psi^L - C^L ||_2 <= res_coef eps n^4 / (h_i m)
+ *      with M, Psi, C of the unscaled system (monomials x^a y^b/(a!b!),
+ *      C^L = 1 at x^2 and y^2), eps the float64 machine epsilon;
+ *   2. no amplitude response exceeds gain_max at the 16 wavenumbers
+ *      k = q pi / (16 s_i), q = 1..16:
+ *        A^x = L^x(sin k x)/k, A^y = L^y(sin k y)/k,
+ *        A^L = L^L(1/2 - cos(k x) cos(k y)/2)/k^2.
+ * Each test at scale h builds the node's system on its h0 stencil
+ * (neighbours beyond 2h have psi = 0 and drop out). The paper prints
+ * res_coef = 1e-4 for its own solver and notes it is solver-specific; with
+ * this residual even the initial stencils fail at 1e-4, and below about 1e4
+ * the test acts on rounding noise. The default, 1e4, stops the shrinking
+ * where the system becomes singular (the residual then jumps by many orders
+ * of magnitude from one scale to the next).
+ *
+ *   x, y, s, order_m   float64[n], int8[n] as for labfm_build_weights.
+ *   h0                 float64[n] initial stencil scales (the paper: 2.8 s).
+ *   row_ptr, col, nnz  CSR of the h0 stencils (labfm_build_neighbours with h0).
+ *   prm                host parameters, or NULL for {0.99, 1.01, 1e4, 200}.
+ *   h_out              float64[n] output scales.
+ *   iters              int32[n] output k with h_out = h0 shrink^k (by repeated
+ *                      multiplication), or NULL.
+ * Nodes with orders outside 1..10 keep h0. Synchronises; allocates a small
+ * work list.
+ */
+typedef struct {
+  double shrink;    /* factor applied to h per accepted step (paper: 0.99) */
+  double gain_max;  /* largest accepted amplitude response (paper: 1.01) */
+  double res_coef;  /* coefficient of the residual bound */
+  int32_t max_iter; /* cap on accepted shrinks per node */
+} labfm_stencil_opt_params;
+
+int labfm_optimise_stencils(const double* x, const double* y, const double* h0, const double* s,
+                            const int8_t* order_m, int32_t n, labfm_box box,
+                            const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                            const labfm_stencil_opt_params* prm, double* h_out, int32_t* iters,
+                            void* stream);
+
 /* How labfm_build_weights distributes nodes over the GPU. */
 enum {
   LABFM_BUILD_WAVE = 1,        /* one 64-lane wavefront per node */

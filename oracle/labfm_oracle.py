@@ -372,6 +372,90 @@ def weights_batched(x, y, h, s, m: int, row_ptr, col, box, chunk: int = 4096) ->
 
 
 # ---------------------------------------------------------------------------
+# Section "Stencil optimisation"
+# ---------------------------------------------------------------------------
+
+STENCIL_H0_OVER_S = 2.8   # initial h_i = 2.8 s_i
+STENCIL_SHRINK = 0.99     # h_i <- 0.99 h_i while both tests pass
+STENCIL_GAIN_MAX = 1.01   # largest accepted amplitude response
+STENCIL_N_K = 16          # wavenumbers k_Ny/16 ... k_Ny of the amplitude test
+
+
+def laplacian_residual(r: dict, h: float, m: int) -> float:
+    """alpha_L = || M Psi^L - C^L ||_2 of the node's unscaled system (the
+    scaled system M~ Psi = C~ is the unscaled one with row p multiplied by
+    h^-(a+b); C^L is 1 at x^2 and y^2)."""
+    deg = np.array([a + b for a, b in monomial_exponents(m)], dtype=float)
+    res = r["M"] @ r["Psi"][:, OP_L] - r["C"][:, OP_L]
+    return float(np.linalg.norm(res * h ** deg))
+
+
+def amplitude_responses(dx, dy, w: np.ndarray, s: float, n_k: int = STENCIL_N_K) -> tuple:
+    """A^x = L^x(sin k x)/k, A^y = L^y(sin k y)/k and
+    A^L = L^L(1/2 - cos(k x) cos(k y)/2)/k^2 at k = q k_Ny/n_k, q = 1..n_k,
+    k_Ny = pi/s (the fields vanish at the node itself)."""
+    k = (math.pi / s) * np.arange(1, n_k + 1) / n_k
+    ax = np.sin(np.outer(k, dx)) @ w[OP_X] / k
+    ay = np.sin(np.outer(k, dy)) @ w[OP_Y] / k
+    al = (0.5 - 0.5 * np.cos(np.outer(k, dx)) * np.cos(np.outer(k, dy))) @ w[OP_L] / k ** 2
+    return ax, ay, al
+
+
+STENCIL_RES_COEF = 1e4    # residual bound coefficient (the paper prints 1e-4 for its solver)
+
+
+def optimise_stencil_node(dx0, dy0, h0: float, s: float, m: int,
+                          res_coef: float = STENCIL_RES_COEF,
+                          shrink: float = STENCIL_SHRINK, gain_max: float = STENCIL_GAIN_MAX,
+                          max_iter: int = 200) -> tuple:
+    """The paper's loop for one node, on the offsets of its h0 stencil (the
+    neighbours beyond 2h have psi = 0 and drop out): build the system at h,
+    stop if the Laplacian residual exceeds res_coef eps n^4/(h m) or any
+    amplitude response exceeds gain_max, else keep h and shrink it. Returns
+    the last accepted h (h0 if none), the number k of shrinks that led to it
+    (h = h0 shrink^k, formed by repeated multiplication), and the test values
+    at the scale that stopped the loop."""
+    n = n_moments(m)
+    eps = np.finfo(float).eps
+    h, k, best, kbest = h0, 0, h0, 0
+    while True:
+        r = node_weights(dx0, dy0, h, s, m)
+        alpha = laplacian_residual(r, h, m) if np.all(np.isfinite(r["Psi"])) else math.inf
+        alpha0 = res_coef * eps * n ** 4 / (h * m)
+        amax = math.nan
+        ok = alpha <= alpha0
+        if ok:
+            ax, ay, al = amplitude_responses(dx0, dy0, r["w"], s)
+            amax = float(max(ax.max(), ay.max(), al.max()))
+            ok = amax <= gain_max
+        if not ok or k > max_iter:
+            return best, kbest, {"alpha": alpha, "alpha0": alpha0, "amax": amax}
+        best, kbest = h, k
+        h = h * shrink
+        k += 1
+
+
+def optimise_stencils(x, y, s, m, box, h0=None, nodes=None, **kw) -> tuple:
+    """optimise_stencil_node for every node (or the listed ones) on the
+    stencils of radius 2 h0 (h0 = 2.8 s by default). Returns h (N,), with h0
+    at unlisted nodes, and the accepted-shrink counts (-1 at unlisted
+    nodes)."""
+    N = x.size
+    m = np.broadcast_to(np.asarray(m), (N,))
+    h0 = STENCIL_H0_OVER_S * np.asarray(s) if h0 is None else np.asarray(h0)
+    listed = range(N) if nodes is None else nodes
+    rp, col = (neighbours(x, y, h0, box) if nodes is None
+               else neighbours_rows(x, y, h0, box, list(listed)))
+    h = np.array(h0, dtype=float, copy=True)
+    iters = np.full(N, -1, dtype=np.int64)
+    for i in listed:
+        dx, dy = stencil_offsets(x, y, box, rp, col, i)
+        h[i], iters[i], _ = optimise_stencil_node(dx, dy, float(h0[i]), float(s[i]), int(m[i]),
+                                                  **kw)
+    return h, iters
+
+
+# ---------------------------------------------------------------------------
 # Equation general_do: the discrete operator
 # ---------------------------------------------------------------------------
 

@@ -527,24 +527,20 @@ __device__ __forceinline__ unsigned long long pivot_key(double a, int r) {
   return (b & ~0x7Full) | static_cast<unsigned long long>(127 - r);
 }
 
+// Assembles [M~ | C~] of node i (order m, n moments, K neighbours from e0,
+// stencil scale h) in sm.A: basis tables of 16-neighbour chunks in LDS and
+// the moment matrix M~ = sum_j X~_j W_j^T on the FP64 matrix cores, then the
+// right-hand sides C~^d = C^d h^-(a+b) of the six operators. Ends with a
+// barrier.
 template <int MMAX>
-__device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm, int tid) {
+__device__ void assemble_system(const BuildArgs& g, int i, int m, int n, int e0, int K, double h,
+                                BlockSmem<MMAX>& sm, int tid) {
   using S = Shape<MMAX>;
   constexpr int TPW = (S::NB * S::NB + 3) / 4;  // MFMA tiles per wave
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int i = uniform(i_in);
-  const int m = uniform(g.order[i]);
-  const int e0 = uniform(g.row_ptr[i]);
-  const int K = uniform(g.row_ptr[i + 1]) - e0;
-  // one exit: every path below ends at the final barrier, and every branch
-  // around a barrier depends on wave-uniform values only
-  const bool valid = (m >= 1 && m <= MMAX);
-  bool singular = false;
-  if (valid) {
-  const int n = moments_of(m);
   const int nb = (n + 15) / 16;
-  const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
+  const double xi = g.x[i], yi = g.y[i];
   const int px = g.box.periodic_x, py = g.box.periodic_y;
   for (int p = tid; p < n; p += kBlock) exponents_of(p, sm.qa[p], sm.qb[p]);
   lds_barrier();
@@ -665,12 +661,21 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   }
   lds_barrier();
 
+}
+
+// LU with partial pivoting of [M~ | C~] in sm.A and back substitution: the
+// solution Psi^d is left in the right-hand-side columns. Returns true (the
+// same in every thread) for a zero or non-finite pivot column. Ends with a
+// barrier.
+template <int MMAX>
+__device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
+  using S = Shape<MMAX>;
+  bool singular = false;
   // ---- LU with partial pivoting on [M~ | C~] --------------------------------
   // One barrier per column (two when rows are swapped): the threads that
   // update column c+1 in step c also propose its pivot (LDS atomic max of the
   // keys), so there is no separate pivot search. The multipliers are not
   // kept (the right-hand sides are eliminated along).
-  int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
   if (tid < 3) sm.key[tid] = 0ull;
   lds_barrier();
   for (int r = tid; r < n; r += kBlock) atomicMax(&sm.key[0], pivot_key(sm.A[r * S::LDA], r));
@@ -734,6 +739,32 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     lds_barrier();
   }
 
+  }
+  return singular;
+}
+
+template <int MMAX>
+__device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& sm, int tid) {
+  using S = Shape<MMAX>;
+  const int lane = tid & 63;
+  const int i = uniform(i_in);
+  const int m = uniform(g.order[i]);
+  const int e0 = uniform(g.row_ptr[i]);
+  const int K = uniform(g.row_ptr[i + 1]) - e0;
+  // one exit: every path below ends at the final barrier, and every branch
+  // around a barrier depends on wave-uniform values only
+  const bool valid = (m >= 1 && m <= MMAX);
+  bool singular = false;
+  if (valid) {
+  const int n = moments_of(m);
+  const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
+  const int px = g.box.periodic_x, py = g.box.periodic_y;
+  const double hinv = 1.0 / h;
+  assemble_system<MMAX>(g, i, m, n, e0, K, h, sm, tid);
+  int st = (K < n) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
+  singular = factor_solve<MMAX>(n, sm, tid);
+  if (!singular) {
+
   // ---- weights, filter calibration, row sums --------------------------------
   // the solution leaves A, whose storage the tables and sums take over
   for (int t = tid; t < n * LABFM_NUM_OPS; t += kBlock)
@@ -744,6 +775,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   const double kf = 2.0 * M_PI / (3.0 * s);
   double rs = 0.0, f0 = 0.0, mx = 0.0, my = 0.0;
   double* nbx = sm.nb();  // [0, 16): dx, [16, 32): dy, [32, 48): cos(kf dx), [48, 64): cos(kf dy)
+  NbrPrefetch pf;
   if (tid < 64) pf.init(g, e0, K, lane >> 2);
   for (int k0 = 0; k0 < K; k0 += kChunk) {
     if (tid < 64) {
@@ -902,6 +934,226 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
     asm volatile("" : "+v"(tid));
     build_node_block<MMAX>(list[k], g, sm, tid);
   }
+}
+
+// ---- stencil optimisation (section "Stencil optimisation") -------------------
+
+// Parameters of the shrinking loop (labfm_stencil_opt_params) and the nodes'
+// initial stencils (the CSR of radius 2 h0).
+struct OptArgs {
+  BuildArgs b;        // x, y, s, order, CSR of the h0 stencils; b.h = h0
+  double* h_out;
+  int* iters;
+  double shrink, gain_max, res_coef;
+  int max_iter;
+};
+
+constexpr int kNk = 16;  // wavenumbers of the amplitude test
+
+// Scratch of the acceptance test beside BlockSmem: neighbour trig sequences
+// sin(k_q x), sin(k_q y), cos(k_q x), cos(k_q y) for q = 1..16 of a chunk, the
+// chunk's x, y and L weights, and the reductions.
+template <int MMAX>
+struct OptSmem {
+  double trig[4][kNk][kChunk];
+  double wv[3][kChunk];
+  double red[Shape<MMAX>::NMAX];
+  double amp[3 * kNk];
+  int pass;
+};
+
+// One node's acceptance test at stencil scale h (the solution Psi in
+// sm.psi): the residual of the unscaled Laplacian system,
+//   alpha_L = || sum_j X_j w^L_j - C^L ||_2  (X_j the monomials x^a y^b/(a!b!)),
+// below res_coef eps n^4 / (h m), and the amplitude responses
+//   A^x(k) = L^x(sin k x)/k, A^y(k) = L^y(sin k y)/k,
+//   A^L(k) = L^L(1/2 - cos k x cos k y / 2)/k^2
+// at k = q k_Ny / 16, q = 1..16, k_Ny = pi/s, none above gain_max. Returns
+// the same value in every thread; ends with a barrier.
+template <int MMAX>
+__device__ bool stencil_accepts(const OptArgs& a, int i, int m, int n, int e0, int K, double h,
+                                double s, BlockSmem<MMAX>& sm, OptSmem<MMAX>& os, int tid) {
+  using S = Shape<MMAX>;
+  const BuildArgs& g = a.b;
+  const int lane = tid & 63;
+  const double xi = g.x[i], yi = g.y[i];
+  const int px = g.box.periodic_x, py = g.box.periodic_y;
+  const double hinv = 1.0 / h;
+  const double k1 = M_PI / (s * kNk);
+  double res = 0.0;  // thread p < n: sum_j X~^p_j w^L_j
+  double amp = 0.0;  // thread 192 + 16 op + q: sum_j w^op_j f_op(k_q r_j)
+  const int aidx = tid - 192, aop = aidx >> 4, aq = aidx & 15;
+  // threads 0..95 form the weights: slot = t/6, operator (x, y, L) = (t/2)%3, half = t%2
+  const int slot = tid / 6, wop = (tid / 2) % 3, half = tid & 1;
+  const int wcol = (wop == 0) ? LABFM_OP_X : (wop == 1 ? LABFM_OP_Y : LABFM_OP_L);
+  NbrPrefetch pf;
+  if (tid < 64) pf.init(g, e0, K, lane >> 2);
+  for (int k0 = 0; k0 < K; k0 += kChunk) {
+    if (tid < 64) {
+      const int kk = lane >> 2, t = lane & 3;
+      double xj, yj;
+      const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
+      double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
+      const double dx = have ? wrap_axis(xj - xi, g.box.Lx, px) : 0.0;
+      const double dy = have ? wrap_axis(yj - yi, g.box.Ly, py) : 0.0;
+      const double xs = dx * hinv, ys = dy * hinv;
+      const double z = (t == 0 || t == 2) ? xs : ys;
+      if (!have) {
+#pragma unroll
+        for (int a2 = 0; a2 <= MMAX; ++a2) tab[a2] = 0.0;
+      } else if (t < 2) {
+        double v = 1.0;
+        tab[0] = 1.0;
+#pragma unroll
+        for (int a2 = 1; a2 <= MMAX; ++a2) {
+          v = v * z * (1.0 / static_cast<double>(a2));
+          tab[a2] = v;
+        }
+      } else {
+        const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+        double h0 = 1.0, h1 = z;
+        tab[0] = psi;
+        tab[1] = psi * z;
+#pragma unroll
+        for (int a2 = 1; a2 < MMAX; ++a2) {
+          const double h2 = z * h1 - static_cast<double>(a2) * h0;
+          h0 = h1;
+          h1 = h2;
+          tab[a2 + 1] = psi * h2;
+        }
+      }
+      // trig sequences by the recurrences f(q+1) = 2 cos(theta) f(q) - f(q-1)
+      const double d = (t == 0 || t == 2) ? dx : dy;
+      double sn, cs;
+      sincos(k1 * d, &sn, &cs);
+      double f0 = (t < 2) ? 0.0 : 1.0, f1 = (t < 2) ? sn : cs;
+      os.trig[t][0][kk] = f1;
+#pragma unroll
+      for (int q = 1; q < kNk; ++q) {
+        const double f2 = 2.0 * cs * f1 - f0;
+        f0 = f1;
+        f1 = f2;
+        os.trig[t][q][kk] = f1;
+      }
+    }
+    lds_barrier();
+    if (tid < 6 * kChunk) {
+      const double* tk = &sm.T()[slot * S::TABLE];
+      double acc = 0.0;
+#pragma unroll 4
+      for (int q = half; q < n; q += 2)
+        acc += (tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]]) *
+               sm.psi[q * LABFM_NUM_OPS + wcol];
+      acc += __shfl_xor(acc, 1);
+      if (half == 0) os.wv[wop][slot] = acc;
+    }
+    lds_barrier();
+    if (tid < n) {
+      for (int k = 0; k < kChunk; ++k) {
+        const double* tk = &sm.T()[k * S::TABLE];
+        res += (tk[sm.qa[tid]] * tk[S::TW + sm.qb[tid]]) * os.wv[2][k];
+      }
+    }
+    if (aidx >= 0 && aidx < 3 * kNk) {
+      for (int k = 0; k < kChunk; ++k) {
+        const double f = (aop == 2) ? 0.5 - 0.5 * os.trig[2][aq][k] * os.trig[3][aq][k]
+                                    : os.trig[aop][aq][k];
+        amp += os.wv[aop][k] * f;
+      }
+    }
+    lds_barrier();
+  }
+  if (tid < n) {
+    const int deg = sm.qa[tid] + sm.qb[tid];
+    double hp = 1.0;
+    for (int d2 = 0; d2 < deg; ++d2) hp *= h;
+    const double target = ((sm.qa[tid] == 2 && sm.qb[tid] == 0) ||
+                           (sm.qa[tid] == 0 && sm.qb[tid] == 2)) ? 1.0 : 0.0;
+    const double r = hp * res - target;
+    os.red[tid] = r * r;
+  }
+  if (aidx >= 0 && aidx < 3 * kNk) {
+    const double k = k1 * static_cast<double>(aq + 1);
+    os.amp[aidx] = (aop == 2) ? amp / (k * k) : amp / k;
+  }
+  lds_barrier();
+  if (tid == 0) {
+    double ss = 0.0;
+    for (int p = 0; p < n; ++p) ss += os.red[p];
+    double amax = -1.0;
+    bool nan_amp = false;
+    for (int q = 0; q < 3 * kNk; ++q) {
+      const double v = os.amp[q];
+      if (!(v == v)) nan_amp = true;
+      amax = v > amax ? v : amax;
+    }
+    double n4 = static_cast<double>(n);
+    n4 = n4 * n4 * n4 * n4;
+    const double alpha0 = a.res_coef * 2.220446049250313e-16 * n4 / (h * static_cast<double>(m));
+    const double alpha = sqrt(ss);
+    os.pass = (alpha <= alpha0) && !nan_amp && (amax <= a.gain_max) ? 1 : 0;
+  }
+  lds_barrier();
+  return uniform(os.pass) != 0;
+}
+
+// Shrinks h_i of node i from h0 by the factor `shrink` while the stencil
+// passes the acceptance test; the result is the last scale that passed (h0
+// when none did). The h0 stencil is used throughout: neighbours beyond 2h
+// have psi = 0 and drop out of the system and the weights.
+template <int MMAX>
+__device__ void optimise_node_block(int i_in, const OptArgs& a, BlockSmem<MMAX>& sm,
+                                    OptSmem<MMAX>& os, int tid) {
+  const BuildArgs& g = a.b;
+  const int i = uniform(i_in);
+  const int m = uniform(g.order[i]);
+  const int e0 = uniform(g.row_ptr[i]);
+  const int K = uniform(g.row_ptr[i + 1]) - e0;
+  const double h0 = g.h[i];
+  double best = h0;
+  int kbest = 0;
+  if (m >= 1 && m <= MMAX) {
+    const int n = moments_of(m);
+    const double s = g.s[i];
+    double h = h0;
+    int k = 0;
+    for (;;) {
+      // as in the persistent build: nothing derived from the thread index
+      // stays live across iterations
+      int tl = tid;
+      asm volatile("" : "+v"(tl));
+      assemble_system<MMAX>(g, i, m, n, e0, K, h, sm, tl);
+      bool ok = !factor_solve<MMAX>(n, sm, tl);
+      if (ok) {
+        for (int t = tl; t < n * LABFM_NUM_OPS; t += kBlock)
+          sm.psi[t] = sm.A[(t / LABFM_NUM_OPS) * Shape<MMAX>::LDA + Shape<MMAX>::NMAX +
+                           t % LABFM_NUM_OPS];
+        lds_barrier();
+        ok = stencil_accepts<MMAX>(a, i, m, n, e0, K, h, s, sm, os, tl);
+      }
+      if (!ok || k > a.max_iter) break;
+      best = h;
+      kbest = k;
+      h *= a.shrink;
+      ++k;
+    }
+  }
+  if (tid == 0) {
+    a.h_out[i] = best;
+    if (a.iters) a.iters[i] = kbest;
+  }
+  lds_barrier();
+}
+
+template <int MMAX>
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(MMAX <= 8 ? 4 : 3)))
+optimise_block_kernel(OptArgs a, const int* __restrict__ list, int count) {
+  __shared__ BlockSmem<MMAX> sm;
+  __shared__ OptSmem<MMAX> os;
+  const int k = blockIdx.x;
+  if (k >= count) return;
+  optimise_node_block<MMAX>(list[k], a, sm, os, threadIdx.x);
 }
 
 // Work list: node indices grouped by order, highest order first (counting
@@ -1191,4 +1443,64 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   // leave the outputs of the chosen distribution in place
   return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
                              rowsum, status, stream_);
+}
+
+extern "C" int labfm_optimise_stencils(const double* x, const double* y, const double* h0,
+                                       const double* s, const int8_t* order_m, int32_t n,
+                                       labfm_box box, const int32_t* row_ptr, const int32_t* col,
+                                       int64_t nnz, const labfm_stencil_opt_params* prm,
+                                       double* h_out, int32_t* iters, void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(n > 0, "optimise_stencils: n must be positive (got %d)", n);
+  LABFM_REQUIRE(x && y && h0 && s && order_m && row_ptr && h_out,
+                "optimise_stencils: null pointer argument");
+  LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "optimise_stencils: bad CSR arguments");
+  labfm_stencil_opt_params p{0.99, 1.01, 1e4, 200};
+  if (prm) p = *prm;
+  LABFM_REQUIRE(p.shrink > 0.0 && p.shrink < 1.0 && p.gain_max > 0.0 && p.res_coef > 0.0 &&
+                    p.max_iter >= 0 && p.max_iter <= 10000,
+                "optimise_stencils: bad parameters");
+  hipStream_t st = as_stream(stream_);
+  struct Temp {
+    void* p = nullptr;
+    ~Temp() {
+      if (p) (void)hipFree(p);
+    }
+  } tmp;
+  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (64 + static_cast<size_t>(n))));
+  int* hist = static_cast<int*>(tmp.p);
+  int* list = hist + 64;
+  LABFM_HIP(hipMemsetAsync(hist, 0, sizeof(int) * 64, st));
+  hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
+                     n, hist);
+  hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(64), 0, st, hist);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
+                     n, hist, list);
+  LABFM_LAUNCHED();
+  int starts[17] = {0};
+  LABFM_HIP(hipMemcpyAsync(starts, hist + 16, sizeof(int) * 17, hipMemcpyDeviceToHost, st));
+  LABFM_HIP(hipStreamSynchronize(st));
+  int mmax = 0;
+  for (int b = 0; b < 16; ++b)
+    if (starts[b + 1] > starts[b]) {
+      mmax = 15 - b;
+      break;
+    }
+  OptArgs a{};
+  a.b = BuildArgs{x, y, h0, s, order_m, n, box, row_ptr, col, nnz, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr};
+  a.h_out = h_out;
+  a.iters = iters;
+  a.shrink = p.shrink;
+  a.gain_max = p.gain_max;
+  a.res_coef = p.res_coef;
+  a.max_iter = p.max_iter;
+  const hipError_t e = with_mmax(mmax, [&](auto M) {
+    hipLaunchKernelGGL(optimise_block_kernel<decltype(M)::value>, dim3(n), dim3(kBlock), 0, st,
+                       a, list, n);
+    return hipGetLastError();
+  });
+  LABFM_HIP(e);
+  LABFM_HIP(hipStreamSynchronize(st));  // the work list is freed on return
+  return LABFM_OK;
 }

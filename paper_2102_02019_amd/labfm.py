@@ -66,6 +66,11 @@ class _LaunchConfig(ctypes.Structure):
     _fields_ = [("lanes_per_node", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
+class _StencilOptParams(ctypes.Structure):
+    _fields_ = [("shrink", ctypes.c_double), ("gain_max", ctypes.c_double),
+                ("res_coef", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
 class _Transpose(ctypes.Structure):
     _fields_ = [("tptr", ctypes.c_void_p), ("tsrc", ctypes.c_void_p), ("tw", ctypes.c_void_p),
                 ("rowsum", ctypes.c_void_p)]
@@ -106,6 +111,9 @@ _SIGNATURES = {
                                         ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
     "labfm_set_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
+    "labfm_optimise_stencils": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
+                                               ctypes.c_int64,
+                                               ctypes.POINTER(_StencilOptParams), _P, _P, _P]),
     "labfm_tune_build": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                         ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                         ctypes.POINTER(_BuildConfig),
@@ -454,3 +462,29 @@ def get_build_config() -> tuple:
     c = _BuildConfig()
     _check(lib().labfm_get_build_config(ctypes.byref(c)))
     return c.mode, c.workgroups_per_cu
+
+
+# ---------------------------------------------------------------------------
+# stencil optimisation
+# ---------------------------------------------------------------------------
+
+def optimise_stencils(x, y, s, m, box, h0=None, shrink: float = 0.99, gain_max: float = 1.01,
+                      res_coef: float = 1e4, max_iter: int = 200) -> tuple:
+    """The paper's stencil optimisation: per-node h shrunk from h0 (default
+    2.8 s) while the node's system stays solvable and no amplitude response
+    exceeds gain_max. Returns (h, accepted shrinks per node)."""
+    n = x.numel()
+    dev = x.device
+    if not torch.is_tensor(m):
+        m = torch.full((n,), int(m), dtype=torch.int8, device=dev)
+    if h0 is None:
+        h0 = 2.8 * s
+    h0 = h0.contiguous()
+    rp, col = build_neighbours(x, y, h0, box)
+    h = torch.empty(n, dtype=torch.float64, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    prm = _StencilOptParams(float(shrink), float(gain_max), float(res_coef), int(max_iter))
+    _check(lib().labfm_optimise_stencils(_ptr(x), _ptr(y), _ptr(h0), _ptr(s), _ptr(m), n,
+                                         _box(box), _ptr(rp), _ptr(col), col.numel(),
+                                         ctypes.byref(prm), _ptr(h), _ptr(iters), _stream()))
+    return h, iters
