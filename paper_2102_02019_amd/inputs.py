@@ -368,3 +368,124 @@ def graded_holes(n_target: int = 1_000_000, seed: int = 3, n_holes: int = 24,
         meta={"n_target": n_target, "seed": seed, "s0": s0, "n_holes": n_holes,
               "fluid_fraction": float(fluid), "holes": holes},
     )
+
+
+# --------------------------------------------------------------------------
+# Channel between two flat no-slip walls (Poiseuille start-up)
+# --------------------------------------------------------------------------
+
+# Levels of the 5-node orthogonal strip along a wall (section "Boundary
+# discretisation"): 0 is the wall node i0, 1..4 the nodes i1..i4 at q s along
+# the inward normal; -1 marks the bulk.
+STRIP_DEPTH = 5
+# Order of LABFM at strip levels 0..2 (the paper reduces it to 4 there).
+WALL_ORDER = 4
+# Stencil scale of a wall node: its one-sided finite-difference column reaches
+# i4 at 4 s, which must lie inside the stencil radius 2 h.
+WALL_H_OVER_S = 2.1
+# Stencil scale at strip levels 1 and 2. Their stencils are cut by the wall;
+# with the bulk's m = 4 value (1.55 s) the order-4 Laplacian there has weights
+# large enough that the viscous term makes the explicit step unstable (growth
+# ~1e9 per step at s = H/20); at 2.0 s the filtered step has spectral radius 1.
+NEAR_WALL_H_OVER_S = 2.0
+
+
+@dataclass(frozen=True)
+class Strips:
+    """Strip columns of a node set: for each wall node, the node indices of
+    i0..i4 (column[k, q] is level q) and the unit normal into the fluid."""
+
+    column: np.ndarray   # int32 (count, 5)
+    normal: np.ndarray   # float64 (count, 2)
+    level: np.ndarray    # int8 (n,), -1 off the strips
+
+    @property
+    def count(self) -> int:
+        return int(self.column.shape[0])
+
+
+def channel(n_x: int, H: float = 1.0, m: int = 6, jitter: float = 0.3, seed: int = 7,
+            morton: bool = True) -> tuple:
+    """Square channel [0, H) x [0, H], periodic in x, flat walls at y = 0 and
+    y = H, uniform spacing s = H / n_x (requires n_x >= 10).
+
+    Each wall carries the 5-node orthogonal strip: rows at y = q s (bottom) and
+    y = H - q s (top) for q = 0..4, n_x nodes per row at x = (k + 1/2) s, so
+    that every wall node has i1..i4 on its normal. Rows q = 5..n_x-5 form the
+    bulk, a lattice with each coordinate shifted by U(-jitter s, +jitter s)
+    (x wrapped). Orders: 4 on strip levels 0..2, m elsewhere; h = 2.1 s on the
+    walls, 2.0 s on levels 1 and 2, (h/s)_m s elsewhere.
+
+    Returns (NodeSet, Strips), nodes in Morton order of their lattice cell."""
+    if n_x < 2 * STRIP_DEPTH:
+        raise ValueError("channel needs n_x >= 10")
+    s = H / n_x
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    n_rows = n_x + 1
+    iy, ix = np.meshgrid(np.arange(n_rows), np.arange(n_x), indexing="ij")
+    ix, iy = ix.ravel(), iy.ravel()
+    lvl = np.minimum(iy, n_x - iy)
+    level = np.where(lvl < STRIP_DEPTH, lvl, -1).astype(np.int8)
+    bulk = level < 0
+    ex = np.where(bulk, rng.uniform(-jitter, jitter, ix.size), 0.0) * s
+    ey = np.where(bulk, rng.uniform(-jitter, jitter, ix.size), 0.0) * s
+    x = (ix + 0.5) * s + ex
+    y = iy * s + ey
+    y[iy == n_x] = H  # the top wall lies exactly on y = H
+    x = np.mod(x, H)
+    x[x >= H] -= H
+    order = (np.argsort(morton_key_2d(ix, iy), kind="stable") if morton
+             else np.arange(ix.size))
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    x, y, level = x[order], y[order], level[order]
+    # node index of lattice point (k, r)
+    idx = rank.reshape(n_rows, n_x)
+    q = np.arange(STRIP_DEPTH)
+    bottom = idx[q[None, :], np.arange(n_x)[:, None]]           # (n_x, 5)
+    top = idx[(n_x - q)[None, :], np.arange(n_x)[:, None]]      # (n_x, 5)
+    column = np.ascontiguousarray(np.concatenate([bottom, top]), dtype=np.int32)
+    normal = np.concatenate([np.tile([0.0, 1.0], (n_x, 1)), np.tile([0.0, -1.0], (n_x, 1))])
+    n = x.size
+    mm = np.where((level >= 0) & (level <= 2), WALL_ORDER, m).astype(np.int8)
+    hs = np.where(level == 0, WALL_H_OVER_S,
+                  np.where(mm == WALL_ORDER, NEAR_WALL_H_OVER_S, H_OVER_S[m]))
+    nodes = NodeSet(
+        x=np.ascontiguousarray(x), y=np.ascontiguousarray(y),
+        s=np.full(n, s), h=np.ascontiguousarray(hs * s), m=np.ascontiguousarray(mm),
+        box=Box(H, H, True, False),
+        meta={"n_x": n_x, "H": H, "m": m, "jitter": jitter, "seed": seed, "spacing": s},
+    )
+    return nodes, Strips(column=column, normal=np.ascontiguousarray(normal), level=level)
+
+
+@dataclass(frozen=True)
+class Poiseuille:
+    """Start-up of body-force driven flow between walls y = 0 and y = H, from
+    rest: Re = rho0 U0 H / mu, Ma = U0 / c with U0 = rho0 g H^2 / (8 mu) the
+    steady centre-line velocity."""
+
+    Re: float = 10.0
+    Ma: float = 0.05
+    H: float = 1.0
+    U0: float = 1.0
+    rho0: float = 1.0
+
+    @property
+    def mu(self) -> float:
+        return self.rho0 * self.U0 * self.H / self.Re
+
+    @property
+    def gx(self) -> float:
+        return 8.0 * self.mu * self.U0 / (self.rho0 * self.H * self.H)
+
+    def flow(self) -> FlowParams:
+        c = self.U0 / self.Ma
+        return FlowParams(c2=c * c, mu=self.mu, gx=self.gx, gy=0.0)
+
+    def time(self, t_star: float) -> float:
+        """Dimensional time of t* = t U0 / H."""
+        return t_star * self.H / self.U0
+
+
+POISEUILLE = Poiseuille()
