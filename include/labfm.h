@@ -123,6 +123,13 @@ typedef struct {
   const labfm_tiles* tiles; /* host pointer to tiles, or NULL: when set, the
                                stage and filter kernels of labfm_rk_step and
                                labfm_ns_rhs stage each tile's halo in LDS */
+  const double* wall_normal; /* float64[2n] or NULL: (n_x, n_y) of the unit
+                               normal into the fluid at no-slip wall nodes,
+                               (0, 0) at every other node (as written by
+                               labfm_boundary_weights). When set, the stage
+                               kernels solve the wall equation at wall nodes
+                               (see labfm_rk_step) and the filter leaves their
+                               velocity unchanged. */
 } labfm_operators;
 
 /* Constants of the isothermal flow and of the integration. */
@@ -277,6 +284,68 @@ int labfm_optimise_stencils(const double* x, const double* y, const double* h0, 
                             const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                             const labfm_stencil_opt_params* prm, double* h_out, int32_t* iters,
                             void* stream);
+
+/*
+ * Boundary strips (section "Boundaries", subsection "Boundary
+ * discretisation"). Along a wall the node set carries a locally orthogonal
+ * strip five nodes thick: each wall node i0 has nodes i1..i4 at
+ * r_i0 + q s n (q = 1..4), with s the wall node's spacing and n its unit
+ * normal pointing into the fluid. One column per wall node; every node lies
+ * in at most one column.
+ */
+#define LABFM_STRIP_DEPTH 5
+typedef struct {
+  int32_t count;          /* columns (wall nodes), >= 0 */
+  const int32_t* column;  /* int32[5*count]: column[5k + q] is the node at level q
+                             of column k (q = 0 the wall node) */
+  const double* normal;   /* float64[2*count]: (n_x, n_y) of column k, unit,
+                             into the fluid */
+} labfm_strips;
+
+/*
+ * Boundary operators of table tab:boundaries, written over the output of
+ * labfm_build_weights (which must have run first on the same stencils, with
+ * order 4 at levels 0..2 and stencils containing the whole column of every
+ * strip node). For every column and level q = 0, 1, 2, node i of the column,
+ * with t = (-n_y, n_x):
+ *   d/dxi:  5-point finite difference along the column with spacing s of the
+ *           column's wall node: one-sided (offsets 0..4) at i0, asymmetric
+ *           (-1..3) at i1, centred (-2..2) at i2;
+ *   d/deta: one-dimensional LABFM of order 4 (Appendix A) over B_i, the
+ *           stencil neighbours on the same level whose column normal is
+ *           within 60 degrees of n: eta_ji = r_ji . t, monomials
+ *           (eta/h)^k / k!, ABFs psi(|eta|/h) He_k(eta/h) (k = 1..4, the
+ *           probabilists' form of the appendix's H_k(z/sqrt2)/sqrt(2^k)),
+ *           target h^-1 e_1, solved with partial pivoting;
+ *   w^x = n_x w^xi + t_x w^eta,  w^y = n_y w^xi + t_y w^eta  (the Jacobian of
+ *           the subsection).
+ * At wall nodes (q = 0) also: w^L = w^xx = w^xy = 0 (the imposed velocity and
+ * the wall's ln rho equation use no second derivative); w^hyp = the 1D LABFM
+ * d^4/deta^4 (target h^-4 e_4), a filter along the wall only; kappa from
+ * w^hyp by the calibration of labfm_build_weights; wall_normal = n. Levels 1
+ * and 2 keep their two-dimensional second-derivative and filter operators.
+ *
+ *   x, y, h, s, n, box, row_ptr, col, nnz  as for labfm_build_weights.
+ *   strips        host pointer to the columns (device arrays inside).
+ *   w             float64[6*nnz], updated in place.
+ *   w32, mom32    float32 copies and first moments, updated to match, or NULL.
+ *   kappa         float64[n], updated at wall nodes.
+ *   status        int8[n], updated: LABFM_NODE_SINGULAR when the 1D system is
+ *                 singular, LABFM_NODE_FEW_NEIGHBOURS when a column node is
+ *                 missing from the stencil (the node's x and y weights are then
+ *                 zero), LABFM_NODE_BAD_FILTER; wall nodes otherwise
+ *                 LABFM_NODE_OK.
+ *   wall_normal   float64[2n] output: n at wall nodes, (0, 0) elsewhere.
+ *
+ * Returns LABFM_ERR_ARG for a node index outside 0..n-1, a node listed twice
+ * or a normal that is not of unit length (checked on the host: the call copies
+ * the columns back and synchronises). Allocates a temporary per-node map.
+ */
+int labfm_boundary_weights(const double* x, const double* y, const double* h, const double* s,
+                           int32_t n, labfm_box box, const int32_t* row_ptr, const int32_t* col,
+                           int64_t nnz, const labfm_strips* strips, double* w, float* w32,
+                           float* mom32, double* kappa, int8_t* status, double* wall_normal,
+                           void* stream);
 
 /* How labfm_build_weights distributes nodes over the GPU. */
 enum {
@@ -433,6 +502,8 @@ size_t labfm_adjoint_workspace_bytes(int32_t n, int32_t n_steps, int32_t ckpt_ev
  *                         qbar_end.
  *   workspace             labfm_adjoint_workspace_bytes(n, n_steps,
  *                         ckpt_every) bytes.
+ * Operators with wall nodes (ops->wall_normal set) are not supported
+ * (LABFM_ERR_UNSUPPORTED).
  */
 int labfm_rk_adjoint(const double* q0, const double* qbar_end, double* qbar_0,
                      const labfm_operators* ops, const labfm_transpose* tr,
@@ -449,6 +520,16 @@ size_t labfm_rk_workspace_bytes(int32_t n);
  * p = c2 rho so that grad(p)/rho = c2 grad(ln rho)), each step followed by
  * the filter phi <- phi + kappa_i L^hyp_i(phi) on ln rho, u and v when
  * prm->filter is set.
+ *
+ * With ops->wall_normal set, wall nodes (normal n != 0) of a no-slip wall
+ * keep their velocity (the caller starts them at u = v = 0) and evolve ln rho
+ * by the characteristic form eq. lodilnro: with xi along n, eta along
+ * t = (-n_y, n_x), c = sqrt(c2), L2 = 0 and the incoming wave set to
+ * L4 = L1 + 2 rho c g.n,
+ *   R_l = (c - u_xi)(d lnrho/dxi - (d u_xi/dxi)/c) - 2 (g.n)/c
+ *         - u_eta d lnrho/deta - d u_eta/deta,
+ * the derivatives taken from the node's x and y operators. The filter leaves
+ * the wall velocity unchanged.
  *
  *   q          float64[3n] state [ln rho | u | v], updated in place.
  *   ops        operators (w and kappa for LABFM_F64; w32 and kappa for

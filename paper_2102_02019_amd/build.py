@@ -22,7 +22,8 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
-SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip"]
+SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
+           "boundaries.hip"]
 
 
 def _compile(src: str) -> str:

@@ -320,6 +320,10 @@ extern "C" int labfm_rk_adjoint(const double* q0, const double* qbar_end, double
   clear_error();
   LABFM_REQUIRE(ops && ops->n > 0 && ops->w && ops->row_ptr && ops->kappa,
                 "rk_adjoint: float64 operators with kappa required");
+  if (ops->wall_normal) {
+    set_error("rk_adjoint: operators with wall nodes are not supported");
+    return LABFM_ERR_UNSUPPORTED;
+  }
   LABFM_REQUIRE(tr && tr->tptr && tr->tsrc && tr->tw && tr->rowsum,
                 "rk_adjoint: transposed stencils and row sums required");
   LABFM_REQUIRE(q0 && qbar_end && qbar_0 && prm, "rk_adjoint: null argument");

@@ -249,23 +249,58 @@ struct Flow {
   double c2, mu, gx, gy;
 };
 
+// Wall normal of a node, or (0, 0) off the walls and when wn is null.
+__device__ __forceinline__ bool wall_node(const double* wn, int node, double& nx, double& ny) {
+  if (!wn) return false;
+  nx = wn[2 * static_cast<long long>(node)];
+  ny = wn[2 * static_cast<long long>(node) + 1];
+  return nx != 0.0 || ny != 0.0;
+}
+
+// d(ln rho)/dt at a no-slip wall node (eq. lodilnro with L2 = 0 and the
+// incoming wave L4 = L1 + 2 rho c g.n). Along the normal xi, with
+// dp/dxi = c^2 rho d(ln rho)/dxi, -(L4 + L1)/(rho c^2) reduces to
+// (c - u_xi)(l_xi - (du_xi/dxi)/c) - 2 g.n / c; the tangential (eta) terms
+// follow.
+__device__ __forceinline__ double wall_lnrho_rate(double nx, double ny, double ui, double vi,
+                                                  double Lx, double Ly, double Ux, double Uy,
+                                                  double Vx, double Vy, const Flow& fl) {
+  const double c = sqrt(fl.c2);
+  const double tx = -ny, ty = nx;
+  const double l_xi = nx * Lx + ny * Ly;
+  const double l_eta = tx * Lx + ty * Ly;
+  const double u_xi = nx * ui + ny * vi;
+  const double u_eta = tx * ui + ty * vi;
+  const double dxi_uxi = nx * (nx * Ux + ny * Uy) + ny * (nx * Vx + ny * Vy);
+  const double deta_ueta = tx * (tx * Ux + ty * Uy) + ty * (tx * Vx + ty * Vy);
+  return (c - u_xi) * (l_xi - dxi_uxi / c) - 2.0 * (fl.gx * nx + fl.gy * ny) / c -
+         u_eta * l_eta - deta_ueta;
+}
+
 // Right-hand side of eq. icns at one node from its operator sums
 // D = (l_x, l_y, u_x, u_y, Lu, u_xx, u_xy, v_x, v_y, Lv, v_xx, v_xy), and the
 // two-register update: Y' = q + dta F (when Yout is set), q <- q + dtb F.
 // 4/3 u_xx + u_yy = L u + u_xx/3 and 4/3 v_yy + v_xx = L v + v_yy/3 with
 // v_yy = L v - v_xx. qin == nullptr evaluates the right-hand side alone.
+// Wall nodes (wn set and non-zero there) hold their velocity and take the
+// wall equation for ln rho.
 __device__ __forceinline__ void stage_update(int node, int n, double li, double ui, double vi,
                                              const double* D, const double* qin, double* qout,
                                              double* Yout, double dta, double dtb,
-                                             const Flow& fl) {
+                                             const Flow& fl, const double* wn) {
   const double Lx = D[0], Ly = D[1], Ux = D[2], Uy = D[3], UL = D[4], Uxx = D[5], Uxy = D[6];
   const double Vx = D[7], Vy = D[8], VL = D[9], Vxx = D[10], Vxy = D[11];
   const double nu = fl.mu / exp(li);
   const double third = 1.0 / 3.0;
-  const double rl = -(ui * Lx + vi * Ly) - (Ux + Vy);
-  const double ru = -(ui * Ux + vi * Uy) - fl.c2 * Lx + nu * (UL + third * (Uxx + Vxy)) + fl.gx;
-  const double rv =
-      -(ui * Vx + vi * Vy) - fl.c2 * Ly + nu * (VL + third * ((VL - Vxx) + Uxy)) + fl.gy;
+  double rl = -(ui * Lx + vi * Ly) - (Ux + Vy);
+  double ru = -(ui * Ux + vi * Uy) - fl.c2 * Lx + nu * (UL + third * (Uxx + Vxy)) + fl.gx;
+  double rv = -(ui * Vx + vi * Vy) - fl.c2 * Ly + nu * (VL + third * ((VL - Vxx) + Uxy)) + fl.gy;
+  double nx, ny;
+  if (wall_node(wn, node, nx, ny)) {
+    rl = wall_lnrho_rate(nx, ny, ui, vi, Lx, Ly, Ux, Uy, Vx, Vy, fl);
+    ru = 0.0;
+    rv = 0.0;
+  }
   const long long n2 = 2 * static_cast<long long>(n);
   const double ql = qin ? qin[node] : 0.0;
   const double qu = qin ? qin[n + node] : 0.0;
@@ -289,7 +324,7 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
                 const typename P::W* __restrict__ w, const float* __restrict__ mom,
                 long long nnz, const double* Y,
                 const double* qin, double* qout, double* Yout, double dta, double dtb, Flow fl,
-                int n) {
+                int n, const double* __restrict__ wn) {
   const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
@@ -379,7 +414,7 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
     moment_fix(mom, node, n, sums[2], sums[3], sums[4], sums[5], sums[6]);
     moment_fix(mom, node, n, sums[7], sums[8], sums[9], sums[10], sums[11]);
   }
-  stage_update(node, n, li, ui, vi, sums, qin, qout, Yout, dta, dtb, fl);
+  stage_update(node, n, li, ui, vi, sums, qin, qout, Yout, dta, dtb, fl, wn);
 }
 
 // --------------------------------------------------------------------------
@@ -390,7 +425,8 @@ template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
               const typename P::W* __restrict__ whyp, const double* __restrict__ kappa,
-              const double* __restrict__ in, double* __restrict__ out, int n) {
+              const double* __restrict__ in, double* __restrict__ out, int n,
+              const double* __restrict__ wn) {
   const int gid = first_thread<FL>();
   const int node = gid / LPN;
   const int sub = gid % LPN;
@@ -440,9 +476,11 @@ filter_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   const double sv = av.template reduce<LPN>();
   if (sub != 0) return;
   const double k = kappa[node];
+  double nx, ny;
+  const bool wall = wall_node(wn, node, nx, ny);  // the wall velocity is imposed
   out[node] = li + k * sl;
-  out[n + node] = ui + k * su;
-  out[n2 + node] = vi + k * sv;
+  out[n + node] = wall ? ui : ui + k * su;
+  out[n2 + node] = wall ? vi : vi + k * sv;
 }
 
 // --------------------------------------------------------------------------
@@ -486,7 +524,7 @@ rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
                       const typename P::W* __restrict__ w, const float* __restrict__ mom,
                       long long nnz, const double* Y,
                       const double* qin, double* qout, double* Yout, double dta, double dtb,
-                      Flow fl, int n) {
+                      Flow fl, int n, const double* __restrict__ wn) {
   extern __shared__ double lds[];
   double* sl = lds;
   double* su = lds + tl.hmax;
@@ -568,7 +606,7 @@ rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
         moment_fix(mom, node, n, Dv[2], Dv[3], Dv[4], Dv[5], Dv[6]);
         moment_fix(mom, node, n, Dv[7], Dv[8], Dv[9], Dv[10], Dv[11]);
       }
-      stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl);
+      stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl, wn);
     }
   }
 }
@@ -577,7 +615,8 @@ template <int LPN, int FL, class P>
 __global__ void __launch_bounds__(256)
 filter_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
                     const typename P::W* __restrict__ whyp, const double* __restrict__ kappa,
-                    const double* __restrict__ in, double* __restrict__ out, int n) {
+                    const double* __restrict__ in, double* __restrict__ out, int n,
+                    const double* __restrict__ wn) {
   extern __shared__ double lds[];
   double* sl = lds;
   double* su = lds + tl.hmax;
@@ -628,9 +667,11 @@ filter_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
     const double rv = av.template reduce<LPN>();
     if (sub == 0) {
       const double k = kappa[node];
+      double nx, ny;
+      const bool wall = wall_node(wn, node, nx, ny);
       out[node] = li + k * rl;
-      out[n + node] = ui + k * ru;
-      out[n2 + node] = vi + k * rv;
+      out[n + node] = wall ? ui : ui + k * ru;
+      out[n2 + node] = wall ? vi : vi + k * rv;
     }
   }
 }
@@ -774,14 +815,15 @@ hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename 
       hipLaunchKernelGGL((rk_stage_tiled_kernel<decltype(L)::value, decltype(F)::value, P>),
                          dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w,
                          o->mom32, static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb,
-                         fl, n);
+                         fl, n, o->wall_normal);
     });
   }
   const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((rk_stage_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
                        dim3(kThreads), 0, st, o->row_ptr, o->col, w, o->mom32,
-                       static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n);
+                       static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n,
+                       o->wall_normal);
   });
 }
 
@@ -796,13 +838,14 @@ hipError_t launch_filter(LaunchCfg cfg, const labfm_operators* o, const typename
     return with_cfg(cfg, [&](auto L, auto F) {
       hipLaunchKernelGGL((filter_tiled_kernel<decltype(L)::value, decltype(F)::value, P>),
                          dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, whyp,
-                         o->kappa, in, out, n);
+                         o->kappa, in, out, n, o->wall_normal);
     });
   }
   const unsigned grid = blocks_for(static_cast<long long>(n) * cfg.lpn, kThreads);
   return with_cfg(cfg, [&](auto L, auto F) {
     hipLaunchKernelGGL((filter_kernel<decltype(L)::value, decltype(F)::value, P>), dim3(grid),
-                       dim3(kThreads), 0, st, o->row_ptr, o->col, whyp, o->kappa, in, out, n);
+                       dim3(kThreads), 0, st, o->row_ptr, o->col, whyp, o->kappa, in, out, n,
+                       o->wall_normal);
   });
 }
 

@@ -52,7 +52,12 @@ class _Operators(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("w32", ctypes.c_void_p),
                 ("mom32", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
-                ("tiles", ctypes.POINTER(_Tiles))]
+                ("tiles", ctypes.POINTER(_Tiles)), ("wall_normal", ctypes.c_void_p)]
+
+
+class _Strips(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("column", ctypes.c_void_p),
+                ("normal", ctypes.c_void_p)]
 
 
 class _RKParams(ctypes.Structure):
@@ -109,6 +114,9 @@ _SIGNATURES = {
     "labfm_rk_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_Operators),
                                         ctypes.POINTER(_Transpose), ctypes.POINTER(_RKParams),
                                         ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "labfm_boundary_weights": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
+                                              ctypes.c_int64, ctypes.POINTER(_Strips), _P, _P,
+                                              _P, _P, _P, _P, _P]),
     "labfm_set_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_optimise_stencils": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
@@ -216,6 +224,9 @@ class Operators:
     use_tiles: bool = True
     # transposed stencils for the adjoint (labfm_build_transpose): tptr, tsrc, tw
     transpose: Optional[tuple] = None
+    # float64 (n, 2) inward normal at no-slip wall nodes, zero elsewhere
+    # (labfm_boundary_weights)
+    wall_normal: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
@@ -236,7 +247,8 @@ class Operators:
                           None if self.w is None else _ptr(self.w).value,
                           None if self.w32 is None else _ptr(self.w32).value,
                           None if self.mom32 is None else _ptr(self.mom32).value,
-                          _ptr(self.kappa).value, tp)
+                          _ptr(self.kappa).value, tp,
+                          None if self.wall_normal is None else _ptr(self.wall_normal).value)
 
 
 def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
@@ -267,6 +279,27 @@ def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
     ops = Operators(row_ptr, col, w, w32, kappa, mom32, rs, status)
     if tiles:
         build_tiles(ops)
+    return ops
+
+
+def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
+                     normal: torch.Tensor) -> Operators:
+    """Boundary operators of the strip columns (labfm_boundary_weights),
+    written over ops (built by build_weights on the same node set); sets
+    ops.wall_normal. column: int32 (count, 5) node indices of levels 0..4;
+    normal: float64 (count, 2) unit normals into the fluid."""
+    n = x.numel()
+    count = int(column.shape[0]) if column.numel() else 0
+    st = _Strips(count, _ptr(column).value if count else None,
+                 _ptr(normal).value if count else None)
+    if ops.status is None:
+        ops.status = torch.zeros(n, dtype=torch.int8, device=x.device)
+    wn = torch.empty((n, 2), dtype=torch.float64, device=x.device)
+    _check(lib().labfm_boundary_weights(
+        _ptr(x), _ptr(y), _ptr(h), _ptr(s), n, _box(box), _ptr(ops.row_ptr), _ptr(ops.col),
+        ops.nnz, ctypes.byref(st), _ptr(ops.w), _ptr(ops.w32), _ptr(ops.mom32), _ptr(ops.kappa),
+        _ptr(ops.status), _ptr(wn), _stream()))
+    ops.wall_normal = wn
     return ops
 
 
@@ -404,7 +437,8 @@ def rk_adjoint(q0: torch.Tensor, qbar_end: torch.Tensor, ops: Operators, flow, d
     if ops.transpose is None:
         build_transpose(ops)
     tptr, tsrc, tw = ops.transpose
-    tr = _Transpose(_ptr(tptr).value, _ptr(tsrc).value, _ptr(tw).value, _ptr(ops.rowsum).value)
+    tr = _Transpose(_ptr(tptr).value, _ptr(tsrc).value, _ptr(tw).value,
+                    None if ops.rowsum is None else _ptr(ops.rowsum).value)
     nbytes = lib().labfm_adjoint_workspace_bytes(ops.n, n_steps, ckpt_every)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=q0.device)
     prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
