@@ -63,6 +63,9 @@ def parse():
                     help="pin the gather kernels' launch shapes instead of tuning: JSON "
                          "{prec: {kernel: [lanes_per_node, flags]}} inline, or the path of a "
                          "JSON file holding it under 'launch_shapes' (a bench output line)")
+    ap.add_argument("--poiseuille", action="store_true",
+                    help="print the channel (no-slip walls) line instead: Poiseuille start-up\n"
+                         "throughput at 1.05M nodes, convergence at t* = 1, oracle baseline")
     ap.add_argument("--stencil-opt", action="store_true",
                     help="instead of the solver job: time the stencil optimisation on the "
                          "workload and on the 1.0M-node graded set (one JSON line)")
@@ -86,6 +89,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.stencil_opt:
         print(json.dumps(stencil_opt_bench(args, inputs, labfm, torch, np, dev)))
+        return
+    if args.poiseuille:
+        print(json.dumps(poiseuille_bench(args, inputs, labfm, torch, np, dev)))
         return
     wl = inputs.WORKLOADS[args.workload]
     rk_steps = wl.steps if args.rk_steps is None else args.rk_steps
@@ -281,8 +287,6 @@ def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
     includes its h0 stencil search), tests per node, the FP64 FLOP/s of the
     node systems it builds, neighbours before and after; and the oracle's
     per-node loop timed on a sample of the workload."""
-    from oracle import labfm_oracle as O
-
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     res = {"metric": "stencil optimisation: nodes/s and FP64 FLOP/s of the per-node systems",
            "runs": []}
@@ -290,7 +294,7 @@ def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
             ("holes1m", inputs.graded_holes(1_000_000, seed=3))]
     for name, nodes in sets:
         x, y, s, m = T(nodes.x), T(nodes.y), T(nodes.s), T(nodes.m)
-        h0 = (O.STENCIL_H0_OVER_S * s).contiguous()
+        h0 = (inputs.STENCIL_H0_OVER_S * s).contiguous()
         labfm.optimise_stencils(x, y, s, m, nodes.box, h0=h0)  # warm-up
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
@@ -317,6 +321,8 @@ def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
                                 "uniform_h_over_s": float(rpu[-1].item() / nodes.n),
                                 "optimised": float(rp1[-1].item() / nodes.n)}})
     # the oracle's loop on a sample of the workload (one core)
+    from oracle import labfm_oracle as O
+
     nodes = sets[0][1]
     sample = list(range(0, nodes.n, nodes.n // 24))
     t0 = time.perf_counter()
@@ -326,6 +332,136 @@ def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
     res["cpu_baseline"] = {"value": len(sample) / (t1 - t0), "unit": "nodes/s", "cores": 1,
                            "kind": "oracle", "sample": f"{len(sample)} nodes of {sets[0][0]}"}
     return res
+
+
+def poiseuille_bench(args, inputs, labfm, torch, np, dev, n_x=1024, rk_steps=400):
+    """Channel between no-slip walls (5-node strips, 1D LABFM rows, wall
+    equation) driven from rest by a body force at Re = 10, Ma = 0.05: the
+    whole job (stencils, weights, boundary weights, dt, RK steps with the
+    filter; node arrays resident on the device beforehand) at n_x = 1024
+    (1.05M nodes, m = 6 in the bulk), the stage kernel against the HBM
+    roofline (44 K + 120 bytes per node: the periodic stage's 44 K + 104 plus
+    the wall normal), the velocity error against the analytic start-up at the
+    final time, the convergence at t* = 1 for s = H/20, H/40, H/80, and the
+    oracle's steps timed on the 20 x 21 channel.
+
+    At n_x = 1024 the viscous term sets dt; the paper's coefficient 0.4 puts
+    the stiffest viscous mode outside the RK stability interval there (as for
+    the 2048^2 periodic case), so this job uses 0.25. The convergence runs are
+    convective-limited and use the paper's 0.4."""
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    P = inputs.POISEUILLE
+    flow = P.flow()
+
+    def resident(nodes, strips):
+        return tuple(T(a) for a in (nodes.x, nodes.y, nodes.h, nodes.s, nodes.m,
+                                    strips.column, strips.normal))
+
+    def setup(box, dev_arrays):
+        x, y, h, s, m, column, normal = dev_arrays
+        rp, col = labfm.build_neighbours(x, y, h, box)
+        ops = labfm.build_weights(x, y, h, s, m, box, rp, col)
+        labfm.boundary_weights(x, y, h, s, box, ops, column, normal)
+        return ops
+
+    def dt_for(q, s_dev, t_end, visc):
+        """dt = t_end / ceil(t_end / dt_max), dt_max from eq. dt on q."""
+        dt_max = labfm.time_step(q, s_dev, flow.c2, flow.mu, conv=1.0, visc=visc)
+        n = max(1, int(math.ceil(t_end / dt_max - 1e-9)))
+        return t_end / n, n
+
+    def vel_err(g, y, t):
+        ua = inputs.poiseuille_startup(y, t, P.H, P.mu / P.rho0, P.gx)
+        return float(math.sqrt(np.sum((g[1] - ua) ** 2 + g[2] ** 2) / np.sum(ua * ua)))
+
+    def run(nx, t_star):
+        nodes, st = inputs.channel(nx)
+        arr = resident(nodes, st)
+        ops = setup(nodes.box, arr)
+        q = torch.zeros(3 * nodes.n, dtype=torch.float64, device=dev)
+        dt, n = dt_for(q, arr[3], P.time(t_star), 0.4)
+        labfm.rk_step(q, ops, flow, dt, n, use_graph=True, check_finite=True)
+        return nodes, vel_err(q.cpu().numpy().reshape(3, -1), nodes.y, dt * n), dt * n
+
+    big, strips = inputs.channel(n_x)
+    N = big.n
+    arrays = resident(big, strips)
+    # launch shapes tuned on this node set, outside the timed region
+    ops = setup(big.box, arrays)
+    q = torch.zeros(3 * N, dtype=torch.float64, device=dev)
+    labfm.tune(ops, q, labfm.F64, reps=10)
+    torch.cuda.synchronize()
+
+    def job():
+        o = setup(big.box, arrays)
+        qq = torch.zeros(3 * N, dtype=torch.float64, device=dev)
+        dt = labfm.time_step(qq, arrays[3], flow.c2, flow.mu, conv=1.0, visc=0.25)
+        tm = labfm.rk_step(qq, o, flow, dt, rk_steps, timing=True)
+        return o, qq, dt, tm
+
+    job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tms = []
+    for _ in range(args.steps):
+        o, qq, dt, tm = job()
+        tms.append(tm)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    launches = sum(t["stage_launches"] for t in tms)
+    stage_ms = sum(t["stage_ms"] for t in tms) / launches
+    kbar = o.nnz / N
+    bytes_stage = (44.0 * kbar + 120.0) * N
+    achieved = bytes_stage / (stage_ms * 1e-3) / 1e9
+    g = qq.cpu().numpy().reshape(3, -1)
+    err_big = vel_err(g, big.y, dt * rk_steps)
+    conv = []
+    for nx in (20, 40, 80):
+        nn, err, t_end = run(nx, 1.0)
+        conv.append({"n_x": nx, "nodes": nn.n, "t_star": t_end * P.U0 / P.H, "vel_rel_err": err})
+    rates = [math.log(conv[k]["vel_rel_err"] / conv[k + 1]["vel_rel_err"]) / math.log(2.0)
+             for k in range(2)]
+    stage_name = stage_kernel_name(labfm.get_launch_config(labfm.KERNEL_STAGE, labfm.F64, N,
+                                                           o.nnz), True, "F64")
+    out = {
+        "metric": "Poiseuille channel: node-updates/s per RK stage + stage-kernel HBM roofline",
+        "value": N * 4 * rk_steps / sec, "unit": "node-updates/s", "dtype": "f64",
+        "config": {"workload": "channel1024_m6", "nodes": N, "order_bulk": 6, "order_walls": 4,
+                   "mean_neighbours": round(kbar, 2), "rk_steps_per_job": rk_steps,
+                   "dt_coefficients": {"conv": 1.0, "visc": 0.25},
+                   "flow": "Poiseuille start-up, Re=10, Ma=0.05, from rest",
+                   "domain": "[0,1) periodic x [0,1] walls, 5-node strips, +/-0.3s bulk jitter"},
+        "ms_per_job": sec * 1e3,
+        "roofline": {"bound": "hbm", "kernel": stage_name, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_node_stage": 44.0 * kbar + 120.0,
+                     "algorithmic_bytes_per_launch": bytes_stage, "mean_launch_ms": stage_ms,
+                     "launches": launches},
+        "final_time": dt * rk_steps, "vel_rel_err_at_final_time": err_big,
+        "final_state_finite": bool(np.all(np.isfinite(g))),
+        "convergence_t1": conv, "rates_t1": rates,
+    }
+    out["cpu_baseline"] = poiseuille_cpu_baseline(inputs, np)
+    return out
+
+
+def poiseuille_cpu_baseline(inputs, np, n_x=20, n_steps=60):
+    """The oracle's filtered RK steps of the 20 x 21 channel on one core."""
+    from oracle import boundaries_oracle as B
+
+    P = inputs.POISEUILLE
+    flow = P.flow()
+    small, strips = inputs.channel(n_x)
+    W = B.channel_weights(small, strips)
+    dt, _ = B.poiseuille_steps(small, P, flow, 1.0)
+    z = np.zeros(small.n)
+    c0 = time.perf_counter()
+    B.channel_run(z, z, z, W, flow, dt, n_steps)
+    c1 = time.perf_counter()
+    return {"value": small.n * 4 * n_steps / (c1 - c0), "unit": "node-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_steps} filtered RK steps of the {n_x} x {n_x + 1} channel "
+                      f"({small.n} nodes)"}
 
 
 def pinned_shapes(spec, precs, labfm):

@@ -47,6 +47,8 @@ import math
 
 import numpy as np
 
+from paper_2102_02019_amd.inputs import poiseuille_startup  # noqa: F401  (reference field)
+
 from . import labfm_oracle as O
 
 STRIP_DEPTH = 5
@@ -270,25 +272,9 @@ def channel_run(lnrho, u, v, W: dict, prm, dt: float, n_steps: int, filt: bool =
 
 
 # ---------------------------------------------------------------------------
-# Section "Poiseuille flow": the analytic start-up
+# Section "Poiseuille flow" (the analytic start-up itself is a reference field
+# of the inputs module, pinned in the tests)
 # ---------------------------------------------------------------------------
-
-def poiseuille_startup(y: np.ndarray, t: float, H: float, nu: float, g: float,
-                       n_terms: int = 400) -> np.ndarray:
-    """u(y, t) of flow between walls y = 0, H started from rest by a body
-    force g: the solution of u_t = nu u_yy + g, u(0) = u(H) = 0, u(y, 0) = 0,
-        u = g y (H - y) / (2 nu)
-            - sum_{k odd} 4 g H^2 / (nu pi^3 k^3) sin(k pi y / H) e^{-k^2 pi^2 nu t / H^2}
-    (the Fourier sine series of the steady parabola, each mode decaying at
-    its own rate). n_terms odd modes are summed."""
-    y = np.asarray(y, dtype=np.float64)
-    u = g * y * (H - y) / (2.0 * nu)
-    for j in range(n_terms):
-        k = 2 * j + 1
-        amp = 4.0 * g * H * H / (nu * math.pi ** 3 * k ** 3)
-        u = u - amp * np.sin(k * math.pi * y / H) * math.exp(-(k * math.pi) ** 2 * nu * t / (H * H))
-    return u
-
 
 def velocity_error(u, v, u_exact) -> float:
     """Relative L2 norm of the velocity error, sqrt(sum |u - u_a|^2 / sum |u_a|^2)."""

@@ -489,3 +489,27 @@ class Poiseuille:
 
 
 POISEUILLE = Poiseuille()
+
+
+def poiseuille_startup(y: np.ndarray, t: float, H: float, nu: float, g: float,
+                       n_terms: int = 400) -> np.ndarray:
+    """Analytic u(y, t) of flow between walls y = 0, H started from rest by a
+    body force g (the incompressible start-up, which the isothermal equations
+    also admit with uniform density): the solution of u_t = nu u_yy + g,
+    u(0) = u(H) = 0, u(y, 0) = 0,
+        u = g y (H - y) / (2 nu)
+            - sum_{k odd} 4 g H^2 / (nu pi^3 k^3) sin(k pi y / H) e^{-k^2 pi^2 nu t / H^2}
+    (the sine series of the steady parabola, each mode decaying at its own
+    rate); n_terms odd modes are summed."""
+    y = np.asarray(y, dtype=np.float64)
+    u = g * y * (H - y) / (2.0 * nu)
+    for j in range(n_terms):
+        k = 2 * j + 1
+        amp = 4.0 * g * H * H / (nu * math.pi ** 3 * k ** 3)
+        u = u - amp * np.sin(k * math.pi * y / H) * math.exp(-(k * math.pi) ** 2 * nu * t / (H * H))
+    return u
+
+
+# Initial stencil scale of the stencil optimisation (section "Stencil
+# optimisation"): h0 = 2.8 s.
+STENCIL_H0_OVER_S = 2.8

@@ -148,6 +148,32 @@ def kernel_stats_markdown(stats_csv: str, top: int = 12) -> str:
     return "\n".join(lines)
 
 
+def kernel_trace_markdown(trace_csv: str, min_grid: int = 0, top: int = 12) -> str:
+    """Markdown table of per-kernel durations from a rocprofv3 --kernel-trace
+    CSV, counting only dispatches with Grid_Size_X >= min_grid (to separate
+    the launches of one node set from those of smaller ones in the same run)."""
+    import re
+
+    rows = read_counter_csv(trace_csv)
+    acc = {}
+    for r in rows:
+        if int(r["Grid_Size_X"]) < min_grid:
+            continue
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        acc.setdefault(r["Kernel_Name"], []).append(d)
+    total = sum(sum(v) for v in acc.values()) or 1.0
+    order = sorted(acc.items(), key=lambda kv: -sum(kv[1]))
+    lines = ["| kernel | calls | mean us | min us | max us | share % |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for name, v in order[:top]:
+        name = re.sub(r"\(anonymous namespace\)::|labfm::", "", name)
+        name = re.sub(r"\((int|double|float|void|signed|long|labfm|at|std|Tiles|BuildArgs).*$", "",
+                      name)
+        lines.append(f"| `{name[:80]}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
+                     f"{max(v):.1f} | {100.0 * sum(v) / total:.2f} |")
+    return "\n".join(lines)
+
+
 def main(argv=None) -> None:
     """Command line: write a traffic summary (JSON) or a kernel-trace table
     (markdown) under profiles/ from rocprofv3 CSV output."""
@@ -167,6 +193,10 @@ def main(argv=None) -> None:
     k = sub.add_parser("stats", help="markdown table of a --stats kernel summary")
     k.add_argument("--csv", required=True, help="glob of the kernel_stats CSV file")
     k.add_argument("--top", type=int, default=14)
+    g = sub.add_parser("trace", help="markdown table of a --kernel-trace CSV, large grids only")
+    g.add_argument("--csv", required=True, help="glob of the kernel_trace CSV file")
+    g.add_argument("--min-grid", type=int, default=0, help="smallest Grid_Size_X counted")
+    g.add_argument("--top", type=int, default=14)
     a = ap.parse_args(argv)
     if a.what == "traffic":
         s = traffic_summary(a.tag, a.match, a.workload, a.fetch, a.write, a.command, a.last,
@@ -175,6 +205,8 @@ def main(argv=None) -> None:
         with open(path, "w") as f:
             json.dump(s, f, indent=1)
         print(path, s["hbm_bytes_per_dispatch"])
+    elif a.what == "trace":
+        print(kernel_trace_markdown(a.csv, a.min_grid, a.top))
     else:
         print(kernel_stats_markdown(a.csv, a.top))
 
