@@ -542,6 +542,53 @@ int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_rk_params* 
                   int32_t n_steps, labfm_prec prec, int32_t use_graph, void* workspace,
                   size_t workspace_bytes, labfm_timing* timing, void* stream);
 
+/*
+ * Lagrangian frame (section "Conclusions": node positions advanced by the
+ * same time integration as the flow, the consistency matrices of every node
+ * evaluated and solved at every step). The nodes move with the fluid,
+ * dr_i/dt = u_i, and (ln rho, u, v) follow eq. icns for the material
+ * derivative (no u . grad terms):
+ *   D ln rho/Dt = -(u_x + v_y),
+ *   Du/Dt = -c2 l_x + (mu/rho)(4/3 u_xx + u_yy + 1/3 v_xy) + gx,
+ *   Dv/Dt = -c2 l_y + (mu/rho)(4/3 v_yy + v_xx + 1/3 u_xy) + gy.
+ * The extended state (x, y, ln rho, u, v) takes n_steps steps of the
+ * RK3(2)4[2R+]C two-register scheme of labfm_rk_step. Every stage rebuilds
+ * the stencils and the six operators' weights at that stage's positions
+ * (labfm_build_neighbours and labfm_build_weights, with the node's h_i, s_i
+ * and order travelling with it); after each step the filter (prm->filter)
+ * uses weights built at the new positions, which also serve the next step's
+ * first stage: four builds per step, plus one before the first. Positions
+ * are folded into the box after every update.
+ *
+ *   x, y          float64[n] positions, updated in place (inside the box).
+ *   q             float64[3n] state [ln rho | u | v], updated in place.
+ *   h, s, order_m per-node stencil scale, spacing and order (fixed).
+ *   box           both axes periodic (LABFM_ERR_UNSUPPORTED otherwise).
+ *   prm           c2, mu, gx, gy, dt, filter, check_finite.
+ *   nnz_capacity  largest stencil count the workspace holds.
+ *   workspace     labfm_lagrangian_workspace_bytes(n, nnz_capacity) bytes:
+ *                 three 5n-double registers, the CSR and the weights.
+ *   stats         host, optional.
+ * Synchronises (every build does). Returns LABFM_ERR_CAPACITY when a stencil
+ * build needs more than nnz_capacity entries; x, y and q then hold the last
+ * completed step (stats->steps_done).
+ */
+typedef struct {
+  int32_t steps_done;  /* completed steps */
+  int64_t builds;      /* stencil + weight builds */
+  int64_t max_nnz;     /* largest stencil count built */
+  double build_ms;     /* host wall-clock time in the builds (they synchronise) */
+  double stage_ms;     /* stage and filter kernels (HIP events on the stream) */
+} labfm_lagrangian_stats;
+
+size_t labfm_lagrangian_workspace_bytes(int32_t n, int64_t nnz_capacity);
+
+int labfm_lagrangian_step(double* x, double* y, double* q, const double* h, const double* s,
+                          const int8_t* order_m, int32_t n, labfm_box box,
+                          const labfm_rk_params* prm, int32_t n_steps, int64_t nnz_capacity,
+                          void* workspace, size_t workspace_bytes,
+                          labfm_lagrangian_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

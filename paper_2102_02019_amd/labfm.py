@@ -55,6 +55,12 @@ class _Operators(ctypes.Structure):
                 ("tiles", ctypes.POINTER(_Tiles)), ("wall_normal", ctypes.c_void_p)]
 
 
+class _LagrangianStats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int32), ("builds", ctypes.c_int64),
+                ("max_nnz", ctypes.c_int64), ("build_ms", ctypes.c_double),
+                ("stage_ms", ctypes.c_double)]
+
+
 class _Strips(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("column", ctypes.c_void_p),
                 ("normal", ctypes.c_void_p)]
@@ -117,6 +123,11 @@ _SIGNATURES = {
     "labfm_boundary_weights": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                               ctypes.c_int64, ctypes.POINTER(_Strips), _P, _P,
                                               _P, _P, _P, _P, _P]),
+    "labfm_lagrangian_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "labfm_lagrangian_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_int32, _Box,
+                                             ctypes.POINTER(_RKParams), ctypes.c_int32,
+                                             ctypes.c_int64, _P, ctypes.c_size_t,
+                                             ctypes.POINTER(_LagrangianStats), _P]),
     "labfm_set_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_optimise_stencils": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
@@ -301,6 +312,40 @@ def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
         _ptr(ops.status), _ptr(wn), _stream()))
     ops.wall_normal = wn
     return ops
+
+
+def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, box, flow,
+                    dt: float, n_steps: int, filter: bool = True, check_finite: bool = False,
+                    nnz_capacity: Optional[int] = None,
+                    workspace: Optional[torch.Tensor] = None) -> dict:
+    """Advance positions (x, y) and q = [ln rho | u | v] in place by n_steps
+    Lagrangian RK steps (labfm_lagrangian_step). The stencil capacity
+    defaults to 1.5 times the current stencil count (queried from
+    labfm_build_neighbours). Returns the call's statistics."""
+    n = x.numel()
+    dev = x.device
+    if not torch.is_tensor(m):
+        m = torch.full((n,), int(m), dtype=torch.int8, device=dev)
+    if nnz_capacity is None:
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        nnz = ctypes.c_int64(0)
+        code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(rp),
+                                            None, 0, ctypes.byref(nnz), _stream())
+        if code != ERR_CAPACITY:
+            _check(code)
+        nnz_capacity = int(1.5 * nnz.value) + 1024
+    nbytes = lib().labfm_lagrangian_workspace_bytes(n, nnz_capacity)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
+                    float(getattr(flow, "gy", 0.0)), float(dt), int(filter), int(check_finite))
+    st = _LagrangianStats()
+    _check(lib().labfm_lagrangian_step(_ptr(x), _ptr(y), _ptr(q), _ptr(h), _ptr(s), _ptr(m), n,
+                                       _box(box), ctypes.byref(prm), int(n_steps),
+                                       int(nnz_capacity), _ptr(workspace), workspace.numel(),
+                                       ctypes.byref(st), _stream()))
+    return {"steps_done": st.steps_done, "builds": st.builds, "max_nnz": st.max_nnz,
+            "build_ms": st.build_ms, "stage_ms": st.stage_ms, "nnz_capacity": nnz_capacity}
 
 
 TILE_NODES = 64
