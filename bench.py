@@ -27,6 +27,13 @@ Launch shapes of the gather kernels are autotuned on the workload before the
 timed region. --profile-run runs a 1 GiB calibration copy, the tuner and one
 job per precision, for rocprofv3 counter passes.
 
+Other lines (each one JSON line of its own, same conventions):
+--poiseuille  the channel between no-slip walls (boundary strips, wall
+              equation) at 1.05M nodes, with the start-up's convergence;
+--lagrangian  the Lagrangian mode on the workload's nodes (stencils and
+              weights rebuilt at every RK stage);
+--stencil-opt the stencil optimisation on the workload and 1.0M graded nodes.
+
 Prints one JSON line.
 """
 import os
@@ -66,6 +73,9 @@ def parse():
     ap.add_argument("--poiseuille", action="store_true",
                     help="print the channel (no-slip walls) line instead: Poiseuille start-up\n"
                          "throughput at 1.05M nodes, convergence at t* = 1, oracle baseline")
+    ap.add_argument("--lagrangian", action="store_true",
+                    help="print the Lagrangian-mode line instead: nodes advected, stencils and\n"
+                         "weights rebuilt at every RK stage, on the workload's node set")
     ap.add_argument("--stencil-opt", action="store_true",
                     help="instead of the solver job: time the stencil optimisation on the "
                          "workload and on the 1.0M-node graded set (one JSON line)")
@@ -92,6 +102,9 @@ def main():
         return
     if args.poiseuille:
         print(json.dumps(poiseuille_bench(args, inputs, labfm, torch, np, dev)))
+        return
+    if args.lagrangian:
+        print(json.dumps(lagrangian_bench(args, inputs, labfm, torch, np, dev)))
         return
     wl = inputs.WORKLOADS[args.workload]
     rk_steps = wl.steps if args.rk_steps is None else args.rk_steps
@@ -462,6 +475,113 @@ def poiseuille_cpu_baseline(inputs, np, n_x=20, n_steps=60):
             "kind": "oracle",
             "sample": f"{n_steps} filtered RK steps of the {n_x} x {n_x + 1} channel "
                       f"({small.n} nodes)"}
+
+
+def lagrangian_bench(args, inputs, labfm, torch, np, dev, rk_steps=10):
+    """Lagrangian mode on the workload's nodes (Taylor-Green): each job
+    advances positions and fields by rk_steps RK steps with stencils and
+    weights rebuilt at every stage's positions (4 builds per step plus one),
+    inputs resident on the device. Reports node-updates/s per RK stage, the
+    share of the job in the builds, the weight build kernel against the FP64
+    peak (the dominant kernel: its algorithmic flops over the mean of HIP
+    events around labfm_build_weights on the moved nodes), the Eulerian job's
+    rate on the same nodes for comparison, and the oracle's Lagrangian step on
+    a 32 x 32 sample."""
+    wl = inputs.WORKLOADS[args.workload]
+    nodes = wl.nodes()
+    N = nodes.n
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    x0, y0, h, s, m = T(nodes.x), T(nodes.y), T(nodes.h), T(nodes.s), T(nodes.m)
+    q0 = T(np.concatenate([np.log(rho), u, v]))
+    x, y, q = torch.empty_like(x0), torch.empty_like(y0), torch.empty_like(q0)
+    dt = labfm.time_step(q0, s, prm.c2, prm.mu, visc=wl.visc_coef)
+    rp, _ = labfm.build_neighbours(x0, y0, h, nodes.box)
+    cap = int(1.5 * rp[-1].item()) + 1024
+    ws = torch.empty(labfm.lib().labfm_lagrangian_workspace_bytes(N, cap), dtype=torch.uint8,
+                     device=dev)
+
+    def job():
+        x.copy_(x0)
+        y.copy_(y0)
+        q.copy_(q0)
+        return labfm.lagrangian_step(x, y, q, h, s, m, nodes.box, prm, dt, rk_steps,
+                                     nnz_capacity=cap, workspace=ws)
+
+    job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        stats.append(job())
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    build_ms = sum(st["build_ms"] for st in stats) / len(stats)
+    stage_ms = sum(st["stage_ms"] for st in stats) / len(stats)
+    finite = bool(torch.isfinite(q).all().item())
+    # the build kernel on the moved nodes (final positions of the last job)
+    br = build_rate(labfm, torch, np, nodes_at(inputs, nodes, x, y), x, y, h, s, m)
+    # the Eulerian job on the same nodes (stencils and weights once)
+    x.copy_(x0)
+    y.copy_(y0)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(args.steps):
+        rp, col = labfm.build_neighbours(x0, y0, h, nodes.box)
+        ops = labfm.build_weights(x0, y0, h, s, m, nodes.box, rp, col)
+        q.copy_(q0)
+        labfm.rk_step(q, ops, prm, dt, rk_steps)
+    torch.cuda.synchronize()
+    e_sec = (time.perf_counter() - e0) / max(1, args.steps)
+    out = {
+        "metric": "Lagrangian LABFM: node-updates/s per RK stage with a stencil and weight "
+                  "rebuild at every stage",
+        "value": N * 4 * rk_steps / sec, "unit": "node-updates/s", "dtype": "f64",
+        "config": {"workload": wl.name + "_lagrangian", "nodes": N, "order_m": wl.m,
+                   "rk_steps_per_job": rk_steps, "builds_per_job": stats[-1]["builds"],
+                   "flow": "Taylor-Green, Re=100, Ma=0.1, nodes advected"},
+        "ms_per_job": sec * 1e3,
+        "build_share": build_ms / (sec * 1e3),
+        "build_ms_per_build": build_ms / stats[-1]["builds"],
+        "stage_and_filter_ms_per_job": stage_ms,
+        "max_nnz": stats[-1]["max_nnz"], "nnz_capacity": cap,
+        "final_state_finite": finite,
+        "roofline": {"bound": "mfma", "kernel": "build_block_kernel<%d>" % wl.m,
+                     "achieved": br["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": br["frac"], "traffic": None,
+                     "gflop_per_build": br["gflop"], "mean_build_ms": br["weights_ms"]},
+        "eulerian_same_nodes": {"value": N * 4 * rk_steps / e_sec, "ms_per_job": e_sec * 1e3,
+                                "lagrangian_slowdown": sec / e_sec},
+    }
+    out["cpu_baseline"] = lagrangian_cpu_baseline(inputs, np, wl)
+    return out
+
+
+def nodes_at(inputs, nodes, x, y):
+    """The node set with positions taken from device tensors x, y."""
+    return inputs.NodeSet(x.cpu().numpy(), y.cpu().numpy(), nodes.s, nodes.h, nodes.m, nodes.box,
+                          nodes.meta)
+
+
+def lagrangian_cpu_baseline(inputs, np, wl, n_side=32, n_steps=1):
+    """The oracle's Lagrangian step (5 stencil and weight builds, 4 stages, the
+    filter) on a 32 x 32 sample with the workload's order and h/s, one core."""
+    from oracle import labfm_oracle as O
+    from oracle import lagrangian_oracle as G
+
+    nodes = inputs.jittered_lattice(n_side, L=wl.L, seed=wl.seed, m=wl.m)
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm, visc_coef=wl.visc_coef)
+    c0 = time.perf_counter()
+    G.lagrangian_run(nodes.x, nodes.y, np.log(rho), u, v, nodes.h, nodes.s, nodes.m, nodes.box,
+                     prm, dt, n_steps)
+    c1 = time.perf_counter()
+    return {"value": nodes.n * 4 * n_steps / (c1 - c0), "unit": "node-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_steps} Lagrangian step of a {n_side}x{n_side} lattice (m={wl.m}): "
+                      f"5 builds, 4 stages, filter"}
 
 
 def pinned_shapes(spec, precs, labfm):
