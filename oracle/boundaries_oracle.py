@@ -130,11 +130,13 @@ def strip_maps(n: int, strips) -> tuple:
     return level, colidx, normal
 
 
-def boundary_weights(nodes, strips, row_ptr, col, W: dict) -> dict:
+def boundary_weights(nodes, strips, row_ptr, col, W: dict, columns=None) -> dict:
     """Weights of the strip nodes i0..i2 written over the two-dimensional
     ones in W (a dict with w (6, nnz), kappa, status as from
     labfm_oracle.weights). Returns a new dict; also 'wall_normal' (n, 2),
-    the inward normal at wall nodes and zero elsewhere."""
+    the inward normal at wall nodes and zero elsewhere. ``columns`` limits the
+    work to those strip columns (their rows must be in the CSR); the strip
+    levels of every column still decide the rows B_i."""
     x, y, h, s, box = nodes.x, nodes.y, nodes.h, nodes.s, nodes.box
     n = x.size
     level, colidx, normal = strip_maps(n, strips)
@@ -143,7 +145,7 @@ def boundary_weights(nodes, strips, row_ptr, col, W: dict) -> dict:
     status = W["status"].copy()
     wall_normal = np.zeros((n, 2))
     mp = O.filter_power(TANGENT_ORDER)
-    for k in range(strips.column.shape[0]):
+    for k in (range(strips.column.shape[0]) if columns is None else columns):
         nx_, ny_ = strips.normal[k]
         tx, ty = -ny_, nx_
         column = strips.column[k]

@@ -282,3 +282,45 @@ def test_poiseuille_steady_state(dev):
     rate = math.log(errs[0] / errs[1]) / math.log(2.0)
     print("poiseuille t*=20 errors", errs, "rate", rate)
     assert errs[1] < errs[0] / 8.0, errs
+
+
+def test_channel_full_size_sampled(dev):
+    """The benchmark's channel (n_x = 1024, 1,049,600 nodes, m = 6 in the bulk)
+    built on the GPU in the benchmark's configuration: sampled strip columns
+    (all five levels) and bulk nodes against the oracle's per-row stencils,
+    weights, kappa, status and right-hand side."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, strips = inputs.channel(1024)
+    ops = gpu_channel(nodes, strips, dev)
+    cols = [0, 311, 777, 1023, 1024, 1500, 2047]
+    rng = np.random.default_rng(17)
+    bulk = rng.choice(np.nonzero(strips.level < 0)[0], 24, replace=False)
+    rows = sorted(set(int(i) for i in strips.column[cols].ravel()) | set(int(i) for i in bulk))
+    rp, col = O.neighbours_rows(nodes.x, nodes.y, nodes.h, nodes.box, rows)
+    W2 = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, nodes.m, rp, col, nodes.box, nodes=rows)
+    W = B.boundary_weights(nodes, strips, rp, col, W2, columns=cols)
+    rp_g = ops.row_ptr.cpu().numpy()
+    kappa = ops.kappa.cpu().numpy()
+    status = ops.status.cpu().numpy()
+    wn = ops.wall_normal.cpu().numpy()
+    for i in rows:
+        a, b = rp[i], rp[i + 1]
+        ga, gb = int(rp_g[i]), int(rp_g[i + 1])
+        assert np.array_equal(ops.col[ga:gb].cpu().numpy(), col[a:b]), i
+        w = ops.w[:, ga:gb].cpu().numpy()
+        lvl = strips.level[i]
+        tol2d = max(1e-12, 100 * _cond2d(nodes, W, i) * 2.2e-16) if lvl != 0 else TOL
+        for d in range(6):
+            boundary = lvl == 0 or (lvl in (1, 2) and d in (O.OP_X, O.OP_Y))
+            assert rel(w[d], W["w"][d, a:b]) <= (TOL if boundary else tol2d), (i, lvl, d)
+        assert abs(kappa[i] - W["kappa"][i]) <= max(1e-9, tol2d) * abs(W["kappa"][i]), i
+        assert status[i] == W["status"][i], i
+        assert np.array_equal(wn[i], W["wall_normal"][i]), i
+    flow = inputs.FlowParams(c2=400.0, mu=0.1, gx=0.8, gy=-0.5)
+    l, u, v = _smooth_state(nodes)
+    got = labfm.ns_rhs(T(np.concatenate([l, u, v]), dev), ops, flow).cpu().numpy().reshape(3, -1)
+    ref = B.channel_rhs(l, u, v, W, flow)
+    for k in range(3):
+        scale = np.max(np.abs(ref[k][rows])) + 1e-300
+        assert np.max(np.abs(got[k][rows] - ref[k][rows])) <= 1e-11 * scale, k
