@@ -179,6 +179,23 @@ const char* labfm_last_error(void);
 const char* labfm_version(void);
 
 /*
+ * Morton (Z-order) permutation of a node set, the binning that keeps nodes
+ * close in space close in memory (the stencil is purely geometric: sorting
+ * the nodes changes no result, only the locality of the gathers). Node i's
+ * cell is (ix, iy) = (floor(x_i / cell), floor(y_i / cell)) clamped to
+ * 0..ceil(L/cell)-1; its key interleaves the bits of ix (even positions)
+ * and iy (odd positions); perm lists the node indices in ascending key order,
+ * nodes of equal key in ascending index (stable).
+ *
+ *   x, y   float64[n] positions.
+ *   cell   cell side, > 0, at most 2^21 cells per axis.
+ *   perm   int32[n] output.
+ * Synchronises; allocates temporaries (keys and the radix sort's storage).
+ */
+int labfm_morton_order(const double* x, const double* y, int32_t n, labfm_box box, double cell,
+                       int32_t* perm, void* stream);
+
+/*
  * Stencil search (stencil definition of the paper's LABFM section): node j
  * is a neighbour of node i iff j != i and |r_ji| <= 2 h_i, where
  * r_ji = r_j - r_i is taken to the nearest periodic image on periodic axes

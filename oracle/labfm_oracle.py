@@ -84,6 +84,22 @@ def min_image(d: np.ndarray, L: float, periodic: bool) -> np.ndarray:
     return np.where(d > half, d - L, np.where(d < -half, d + L, d))
 
 
+def morton_permutation(x, y, box, cell: float) -> np.ndarray:
+    """Z-order permutation of the nodes: cell (ix, iy) = floor(p / cell)
+    clamped to 0..ceil(L/cell)-1; the key carries bit b of ix at position 2b
+    and bit b of iy at 2b + 1; nodes in ascending key, equal keys in
+    ascending index."""
+    ncx = max(1, math.ceil(box.Lx / cell))
+    ncy = max(1, math.ceil(box.Ly / cell))
+    ix = np.clip(np.floor(x / cell), 0, ncx - 1).astype(np.int64)
+    iy = np.clip(np.floor(y / cell), 0, ncy - 1).astype(np.int64)
+    key = np.zeros(x.size, dtype=np.uint64)
+    for b in range(21):
+        key |= ((ix >> b) & 1).astype(np.uint64) << np.uint64(2 * b)
+        key |= ((iy >> b) & 1).astype(np.uint64) << np.uint64(2 * b + 1)
+    return np.argsort(key, kind="stable")
+
+
 def in_stencil(dx: np.ndarray, dy: np.ndarray, h_i) -> np.ndarray:
     """|r_ji| <= 2 h_i evaluated as dx*dx + dy*dy <= (2h)*(2h), each product
     and the sum rounded separately (no fused multiply-add)."""

@@ -23,7 +23,7 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-result",
 ]
 SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
-           "boundaries.hip", "lagrangian.hip"]
+           "boundaries.hip", "lagrangian.hip", "morton.hip"]
 
 
 def _compile(src: str) -> str:

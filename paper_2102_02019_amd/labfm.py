@@ -100,6 +100,7 @@ _P = ctypes.c_void_p
 _SIGNATURES = {
     "labfm_last_error": (ctypes.c_char_p, []),
     "labfm_version": (ctypes.c_char_p, []),
+    "labfm_morton_order": (ctypes.c_int, [_P, _P, ctypes.c_int32, _Box, ctypes.c_double, _P, _P]),
     "labfm_build_neighbours": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
@@ -201,6 +202,15 @@ def version() -> str:
 
 
 # ---------------------------------------------------------------------------
+
+def morton_order(x: torch.Tensor, y: torch.Tensor, box, cell: float) -> torch.Tensor:
+    """Z-order permutation (int32[n]) of the nodes' cells of side ``cell``."""
+    n = x.numel()
+    perm = torch.empty(n, dtype=torch.int32, device=x.device)
+    _check(lib().labfm_morton_order(_ptr(x), _ptr(y), n, _box(box), float(cell), _ptr(perm),
+                                    _stream()))
+    return perm
+
 
 def build_neighbours(x: torch.Tensor, y: torch.Tensor, h: torch.Tensor, box):
     """CSR stencils (row_ptr int32[n+1], col int32[nnz]) on the device."""

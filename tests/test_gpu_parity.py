@@ -86,6 +86,41 @@ def test_neighbours_bit_exact(dev, case):
     assert np.array_equal(col.cpu().numpy(), ocol)
 
 
+@pytest.mark.parametrize("case", ["lattice64", "cloud_coarse", "cloud_fine", "rect", "one"])
+def test_morton_order_bit_exact(dev, case):
+    """The GPU Z-order permutation equals the oracle's, ties (nodes in one
+    cell) in index order."""
+    from paper_2102_02019_amd import labfm
+
+    if case == "lattice64":
+        nodes = inputs.jittered_lattice(64, L=1.0, seed=3, m=4, morton=False)
+        x, y, box, cell = nodes.x, nodes.y, nodes.box, 1.0 / 64
+    elif case.startswith("cloud"):
+        x, y, box = inputs.random_cloud(20000, L=1.0, seed=8)
+        cell = 0.1 if case == "cloud_coarse" else 1e-4
+    elif case == "rect":
+        rng = np.random.default_rng(2)
+        x, y = rng.uniform(0, 3.0, 5000), rng.uniform(0, 0.5, 5000)
+        box, cell = inputs.Box(3.0, 0.5, False, False), 0.01
+    else:
+        x, y, box, cell = np.array([0.3]), np.array([0.6]), inputs.Box(1.0, 1.0), 0.25
+    perm = labfm.morton_order(T(x, dev), T(y, dev), box, cell).cpu().numpy()
+    assert np.array_equal(perm, O.morton_permutation(x, y, box, cell))
+
+
+def test_morton_order_full_size(dev):
+    """262,144 nodes of the benchmark workload, shuffled: the permutation
+    restores the oracle's order."""
+    from paper_2102_02019_amd import labfm
+
+    nodes = inputs.TG512_M8.nodes()
+    sh = np.random.default_rng(4).permutation(nodes.n)
+    x, y = nodes.x[sh], nodes.y[sh]
+    cell = nodes.meta["spacing"]
+    perm = labfm.morton_order(T(x, dev), T(y, dev), nodes.box, cell).cpu().numpy()
+    assert np.array_equal(perm, O.morton_permutation(x, y, nodes.box, cell))
+
+
 def test_neighbours_full_size_512(dev):
     """262,144 nodes, m = 8 (h/s = 2.68): every list identical."""
     from paper_2102_02019_amd import labfm

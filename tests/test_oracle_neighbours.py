@@ -1,5 +1,7 @@
 """Pins of the oracle's stencil search (the stencil definition of the paper's
 LABFM section: all j with |r_ji| <= 2 h_i) against a pure-Python pair loop."""
+import math
+
 import numpy as np
 
 from oracle import labfm_oracle as O
@@ -101,3 +103,54 @@ def test_rows_of_listed_nodes_match_full_search():
             assert np.array_equal(got, col[rp[i]:rp[i + 1]])
         else:
             assert got.size == 0
+
+
+# ---------------------------------------------------------------------------
+# Morton binning
+# ---------------------------------------------------------------------------
+
+def _z_less(p, q):
+    """Z-order comparison without interleaving (the dimension whose
+    coordinates differ in the highest bit decides; at equal bit levels y is
+    the more significant, as it sits above x in the interleaved key)."""
+    def less_msb(a, b):
+        return a < b and a < (a ^ b)
+
+    j, best = 1, 0
+    for d in (1, 0):
+        v = p[d] ^ q[d]
+        if less_msb(best, v):
+            j, best = d, v
+    return (p[j] > q[j]) - (p[j] < q[j])
+
+
+def test_morton_permutation_against_a_z_order_comparator():
+    import functools
+
+    from paper_2102_02019_amd import inputs as I
+
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        n = 300
+        x = rng.uniform(0.0, 1.0, n)
+        y = rng.uniform(0.0, 0.7, n)
+        box = I.Box(1.0, 0.7, True, True)
+        cell = [0.013, 0.05, 0.1, 0.33][trial]
+        perm = O.morton_permutation(x, y, box, cell)
+        ncx, ncy = math.ceil(1.0 / cell), math.ceil(0.7 / cell)
+        cells = [(min(int(math.floor(x[i] / cell)), ncx - 1), min(int(math.floor(y[i] / cell)), ncy - 1))
+                 for i in range(n)]
+        ref = sorted(range(n), key=functools.cmp_to_key(
+            lambda a, b: _z_less(cells[a], cells[b]) or (a > b) - (a < b)))
+        assert list(perm) == ref
+
+
+def test_morton_permutation_of_the_lattice_is_the_generators_order():
+    """The jittered lattice leaves its generator in the Z-order of its lattice
+    cells; re-binning the (unjittered) cell centres reproduces that order."""
+    from paper_2102_02019_amd import inputs as I
+
+    nodes = I.jittered_lattice(32, L=1.0, jitter=0.0, seed=1, m=4, morton=False)
+    perm = O.morton_permutation(nodes.x, nodes.y, nodes.box, 1.0 / 32)
+    ordered = I.jittered_lattice(32, L=1.0, jitter=0.0, seed=1, m=4, morton=True)
+    assert np.array_equal(nodes.x[perm], ordered.x) and np.array_equal(nodes.y[perm], ordered.y)
