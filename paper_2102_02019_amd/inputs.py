@@ -513,3 +513,50 @@ def poiseuille_startup(y: np.ndarray, t: float, H: float, nu: float, g: float,
 # Initial stencil scale of the stencil optimisation (section "Stencil
 # optimisation"): h0 = 2.8 s.
 STENCIL_H0_OVER_S = 2.8
+
+
+def cylinder(n_theta: int, R: float = 0.2, L: float = 1.0, m: int = 6, jitter: float = 0.3,
+             seed: int = 9) -> tuple:
+    """A no-slip circular wall of radius R centred in the periodic box
+    [0, L)^2 (the geometry of the paper's cylinder flows): n_theta wall nodes
+    at angles 2 pi k / n_theta, each with its strip column i1..i4 at radius
+    R + q s along the outward (into the fluid) normal, s = 2 pi R / n_theta;
+    the fluid beyond R + 4.5 s is a jittered lattice of spacing s. Orders and
+    stencil scales as in channel(). Returns (NodeSet, Strips) in Morton order
+    of a cell grid of side s."""
+    s = 2.0 * math.pi * R / n_theta
+    cx = cy = 0.5 * L
+    phi = 2.0 * math.pi * np.arange(n_theta) / n_theta
+    q = np.arange(STRIP_DEPTH)
+    rr = R + q[None, :] * s                                   # (1, 5)
+    sx = cx + rr * np.cos(phi)[:, None]                       # (n_theta, 5)
+    sy = cy + rr * np.sin(phi)[:, None]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    nl = int(round(L / s))
+    sl = L / nl
+    iy, ix = np.meshgrid(np.arange(nl), np.arange(nl), indexing="ij")
+    bx = (ix.ravel() + 0.5) * sl + rng.uniform(-jitter, jitter, nl * nl) * sl
+    by = (iy.ravel() + 0.5) * sl + rng.uniform(-jitter, jitter, nl * nl) * sl
+    keep = np.hypot(bx - cx, by - cy) > R + 4.5 * s
+    bx, by = np.mod(bx[keep], L), np.mod(by[keep], L)
+    x = np.concatenate([sx.ravel(), bx])
+    y = np.concatenate([sy.ravel(), by])
+    level = np.concatenate([np.tile(q, n_theta), np.full(bx.size, -1)]).astype(np.int8)
+    box = Box(L, L, True, True)
+    order = morton_order(x, y, box, s)
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    x, y, level = x[order], y[order], level[order]
+    column = np.ascontiguousarray(rank[: n_theta * STRIP_DEPTH].reshape(n_theta, STRIP_DEPTH),
+                                  dtype=np.int32)
+    normal = np.ascontiguousarray(np.stack([np.cos(phi), np.sin(phi)], axis=1))
+    n = x.size
+    mm = np.where((level >= 0) & (level <= 2), WALL_ORDER, m).astype(np.int8)
+    hs = np.where(level == 0, WALL_H_OVER_S,
+                  np.where(mm == WALL_ORDER, NEAR_WALL_H_OVER_S, H_OVER_S[m]))
+    nodes = NodeSet(
+        x=np.ascontiguousarray(x), y=np.ascontiguousarray(y), s=np.full(n, s),
+        h=np.ascontiguousarray(hs * s), m=np.ascontiguousarray(mm), box=box,
+        meta={"n_theta": n_theta, "R": R, "L": L, "m": m, "spacing": s},
+    )
+    return nodes, Strips(column=column, normal=normal, level=level)

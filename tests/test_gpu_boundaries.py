@@ -324,3 +324,36 @@ def test_channel_full_size_sampled(dev):
     for k in range(3):
         scale = np.max(np.abs(ref[k][rows])) + 1e-300
         assert np.max(np.abs(got[k][rows] - ref[k][rows])) <= 1e-11 * scale, k
+
+
+def test_cylinder_matches_oracle(dev):
+    """A curved no-slip wall (the paper's cylinder geometry): normals in every
+    direction, strip rows along arcs, a body force with g.n != 0 on the wall.
+    All weights, the right-hand side and 10 filtered steps against the
+    oracle."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, strips = inputs.cylinder(64)
+    ops = gpu_channel(nodes, strips, dev)
+    W = B.channel_weights(nodes, strips)
+    _check_channel_weights(nodes, strips, ops, W)
+    tp = 2.0 * math.pi
+    r = np.hypot(nodes.x - 0.5, nodes.y - 0.5)
+    wall = strips.column[:, 0]
+    l = 0.01 * np.cos(tp * nodes.x) * np.sin(tp * nodes.y)
+    u = 0.5 * (r - 0.2) * np.sin(tp * nodes.y)
+    v = 0.5 * (r - 0.2) * np.cos(tp * nodes.x)
+    u[wall] = 0.0
+    v[wall] = 0.0
+    flow = inputs.FlowParams(c2=400.0, mu=0.05, gx=0.3, gy=0.1)
+    got = labfm.ns_rhs(T(np.concatenate([l, u, v]), dev), ops, flow).cpu().numpy().reshape(3, -1)
+    ref = B.channel_rhs(l, u, v, W, flow)
+    for k in range(3):
+        assert rel(got[k], ref[k]) <= TOL, k
+    assert rel(got[0, wall], ref[0][wall]) <= TOL
+    dt = O.time_step(nodes.s, l, u, v, flow)
+    q = T(np.concatenate([l, u, v]), dev)
+    labfm.rk_step(q, ops, flow, dt, 10, check_finite=True)
+    refq = B.channel_run(l, u, v, W, flow, dt, 10)
+    errs = _compare_state(q.cpu().numpy(), refq)
+    assert max(errs) <= TOL, errs

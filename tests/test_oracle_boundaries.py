@@ -236,3 +236,32 @@ def test_poiseuille_converges_at_fourth_order():
     rate = math.log(errs[0] / errs[1]) / math.log(20 / 12)
     assert errs[1] < 5e-4
     assert 3.5 < rate < 6.5, (errs, rate)
+
+
+def test_wall_equation_on_a_curved_wall():
+    """On the cylinder (normals in every direction, g.n != 0) with u = v = 0
+    on the wall, the oracle's wall rate is c n.grad(ln rho) - d u_xi/dxi
+    - 2 g.n / c, with u_xi's normal derivative known in closed form, to the
+    accuracy of the 5-point differences."""
+    nodes, strips = inputs.cylinder(96, seed=4)
+    W = B.channel_weights(nodes, strips)
+    tp = 2.0 * math.pi
+    x, y = nodes.x, nodes.y
+    r = np.hypot(x - 0.5, y - 0.5)
+    l = 0.01 * np.cos(tp * x) * np.sin(tp * y)
+    u = 0.5 * (r - 0.2) * np.sin(tp * y)
+    v = 0.5 * (r - 0.2) * np.cos(tp * x)
+    wall = strips.column[:, 0]
+    u[wall] = 0.0
+    v[wall] = 0.0
+    flow = inputs.FlowParams(c2=400.0, mu=0.05, gx=0.3, gy=0.1)
+    r_l, r_u, r_v = B.channel_rhs(l, u, v, W, flow)
+    nx_, ny_ = strips.normal[:, 0], strips.normal[:, 1]
+    xw, yw = x[wall], y[wall]
+    lx = -0.01 * tp * np.sin(tp * xw) * np.sin(tp * yw)
+    ly = 0.01 * tp * np.cos(tp * xw) * np.cos(tp * yw)
+    duxi = 0.5 * (nx_ * np.sin(tp * yw) + ny_ * np.cos(tp * xw))
+    gn = flow.gx * nx_ + flow.gy * ny_
+    expect = 20.0 * (nx_ * lx + ny_ * ly) - duxi - 2.0 * gn / 20.0
+    np.testing.assert_allclose(r_l[wall], expect, atol=2e-3 * np.max(np.abs(expect)))
+    assert np.all(r_u[wall] == 0.0) and np.all(r_v[wall] == 0.0)
