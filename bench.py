@@ -167,7 +167,10 @@ def main():
         tuned = {key: tune(p) for key, p in precs.items()}
     # the stage kernels the jobs launch (names as a profiler shows them)
     use_tiles = True
-    names = {k: stage_kernel_name(v["stage"], use_tiles, PREC_TAG[k]) for k, v in tuned.items()}
+    rp0, _ = labfm.build_neighbours(x, y, h, nodes.box)
+    nnz0 = int(rp0[-1].item())
+    names = {k: stage_kernel_name(v["stage"], use_tiles, PREC_TAG[k], nnz0)
+             for k, v in tuned.items()}
 
     if args.profile_run:
         # the tuned shapes stay installed; the counters of the last dispatches
@@ -423,7 +426,7 @@ def poiseuille_bench(args, inputs, labfm, torch, np, dev, n_x=1024, rk_steps=400
         return {"profile_run": "done", "workload": "channel1024_m6", "nodes": N,
                 "rk_steps": args.rk_steps or 10,
                 "stage_kernel": stage_kernel_name(labfm.get_launch_config(
-                    labfm.KERNEL_STAGE, labfm.F64, N, ops.nnz), True, "F64")}
+                    labfm.KERNEL_STAGE, labfm.F64, N, ops.nnz), True, "F64", ops.nnz)}
 
     def job():
         o = setup(big.box, arrays)
@@ -455,7 +458,7 @@ def poiseuille_bench(args, inputs, labfm, torch, np, dev, n_x=1024, rk_steps=400
     rates = [math.log(conv[k]["vel_rel_err"] / conv[k + 1]["vel_rel_err"]) / math.log(2.0)
              for k in range(2)]
     stage_name = stage_kernel_name(labfm.get_launch_config(labfm.KERNEL_STAGE, labfm.F64, N,
-                                                           o.nnz), True, "F64")
+                                                           o.nnz), True, "F64", o.nnz)
     out = {
         "metric": "Poiseuille channel: node-updates/s per RK stage + stage-kernel HBM roofline",
         "value": N * 4 * rk_steps / sec, "unit": "node-updates/s", "dtype": "f64",
@@ -623,12 +626,21 @@ def pinned_shapes(spec, precs, labfm):
     return out
 
 
-def stage_kernel_name(shape, tiled, prec_tag):
+def stage_kernel_name(shape, tiled, prec_tag, nnz=None):
     """Name pattern of the fused RK stage kernel for a tuned launch shape
-    (lanes per node, flags); '*' joins the parts of a profiler's name."""
+    (lanes per node, flags); '*' joins the parts of a profiler's name. With
+    tiles the library launches the pair-loading variant for float64 and the
+    compensated float32 precision (its last template argument tells an odd
+    stencil count)."""
     lpn, flags = shape[0], shape[1]
-    kern = "rk_stage_tiled_kernel" if tiled else "rk_stage_kernel"
-    return f"{kern}<{lpn}, {flags}, *{prec_tag}>"
+    kern = "rk_stage_kernel"
+    tail = ""
+    if tiled:
+        packed = prec_tag in ("F64", "F32Comp")
+        kern = "rk_stage_tiled_packed_kernel" if packed else "rk_stage_tiled_kernel"
+        if packed and nnz is not None:
+            tail = ", " + ("true" if nnz % 2 else "false")
+    return f"{kern}<{lpn}, {flags}, *{prec_tag}{tail}>"
 
 
 def build_flops(m, K):

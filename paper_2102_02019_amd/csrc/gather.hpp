@@ -677,6 +677,241 @@ filter_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
 }
 
 // --------------------------------------------------------------------------
+// tiled kernels with packed edge loads
+// --------------------------------------------------------------------------
+
+// Each lane loads two consecutive edges of every weight array with one load
+// (16 bytes of float64 or 8 bytes of float32 weights) and their two halo
+// slots with one 4-byte load, halving the memory instructions per edge.
+// Pairs start at even edges; the edge of a pair outside the node's row
+// contributes nothing and reads no halo value. Needs a weight base aligned to
+// the pair size (checked by the launcher); with an odd nnz the stage kernel
+// loads the two misaligned arrays edge by edge and the filter (whose one
+// array is then misaligned) keeps its single-edge loads.
+template <class W>
+struct PairOf;
+template <>
+struct PairOf<double> {
+  using VT = double2;
+};
+template <>
+struct PairOf<float> {
+  using VT = float2;
+};
+// Pairs per lane in flight (measured on MI355X at K ~ 90: 3 for float64,
+// 2 for float32 weights in the stage; 3 in the filter). The components are
+// selected inline where they are used: through a helper taking the pair by
+// reference the compiler split some 16-byte loads into two. kUse: the
+// float32-weight, float64-sum policy runs faster with its single-edge loads
+// (143 against 150 us per stage at K ~ 90), the others with pairs (float64
+// 220 -> 204 us, Dot2 174 -> 157 us).
+template <class P>
+struct Packed {
+  static constexpr bool kUse = !std::is_same<P, F32W>::value;
+  static constexpr int V = 2;
+  static constexpr int kStageU = std::is_same<typename P::W, double>::value ? 3 : 2;
+  static constexpr int kFilterU = 3;
+  using VT = typename PairOf<typename P::W>::VT;
+  using IT = unsigned;
+  __device__ __forceinline__ static int slot(IT j, int h) {
+    return static_cast<int>(h ? (j >> 16) : (j & 0xFFFFu));
+  }
+};
+
+template <int LPN, int FL, class P, bool ODD>
+__global__ void __launch_bounds__(256)
+rk_stage_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                             const typename P::W* __restrict__ w, const float* __restrict__ mom,
+                             long long nnz, const double* Y, const double* qin, double* qout,
+                             double* Yout, double dta, double dtb, Flow fl, int n,
+                             const double* __restrict__ wn) {
+  using K = Packed<P>;
+  using W = typename P::W;
+  using D = typename P::D;
+  constexpr int V = K::V;
+  constexpr int U = K::kStageU;
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, Y, n, sl, su, sv);
+  // with an odd nnz the arrays of operators 1 and 3 (y, xx) start half a pair
+  // off alignment: their two edges are loaded one by one
+  const typename K::VT* wx = reinterpret_cast<const typename K::VT*>(w + 0 * nnz);
+  const typename K::VT* wy = reinterpret_cast<const typename K::VT*>(w + 1 * nnz);
+  const typename K::VT* wL = reinterpret_cast<const typename K::VT*>(w + 2 * nnz);
+  const typename K::VT* wxx = reinterpret_cast<const typename K::VT*>(w + 3 * nnz);
+  const typename K::VT* wxy = reinterpret_cast<const typename K::VT*>(w + 4 * nnz);
+  const W* wy1 = w + 1 * nnz;
+  const W* wxx1 = w + 3 * nnz;
+  const typename K::IT* lc = reinterpret_cast<const typename K::IT*>(tl.lcol);
+  constexpr int NPR = 256 / LPN;
+  const int sub = threadIdx.x % LPN;
+#pragma unroll 1
+  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
+    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+    if (node >= n) break;  // whole LPN groups stop together
+    const double li = Y[node], ui = Y[n + node], vi = Y[2 * static_cast<long long>(n) + node];
+    typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
+    lx.zero(); ly.zero();
+    ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
+    vx.zero(); vy.zero(); vL.zero(); vxx.zero(); vxy.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    const int g0 = e0 / V, g1 = (e1 + V - 1) / V;
+    for (int gb = g0 + sub; gb < g1; gb += U * LPN) {
+      int gg[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int g = gb + u * LPN;
+        ok[u] = g < g1;
+        gg[u] = ok[u] ? g : g1 - 1;
+      }
+      typename K::IT jj[U];
+      typename K::VT a[U], b[U], c[U], d[U], f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long e2 = 2LL * gg[u];
+        if constexpr (ODD) {
+          // the last pair of the array has no second slot
+          jj[u] = (e2 + 1 < nnz) ? lc[gg[u]] : static_cast<typename K::IT>(tl.lcol[e2]);
+          b[u].x = wy1[e2];
+          b[u].y = wy1[e2 + 1];
+          d[u].x = wxx1[e2];
+          d[u].y = wxx1[e2 + 1];
+        } else {
+          jj[u] = lc[gg[u]];
+          b[u] = wy[gg[u]];
+          d[u] = wxx[gg[u]];
+        }
+        a[u] = wx[gg[u]];
+        c[u] = wL[gg[u]];
+        f[u] = wxy[gg[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int h = 0; h < V; ++h) {
+          const int e = gg[u] * V + h;
+          const bool v = ok[u] && e >= e0 && e < e1;
+          const int j = v ? K::slot(jj[u], h) : 0;
+          const W z = W(0);
+          const W aw = v ? (h ? a[u].y : a[u].x) : z, bw = v ? (h ? b[u].y : b[u].x) : z;
+          const W cw = v ? (h ? c[u].y : c[u].x) : z, dw = v ? (h ? d[u].y : d[u].x) : z;
+          const W fw = v ? (h ? f[u].y : f[u].x) : z;
+          // edges outside the row read no halo value (slot 0 may be unset)
+          const D dl = P::diff(v ? sl[j] : li, li);
+          const D du = P::diff(v ? su[j] : ui, ui);
+          const D dv = P::diff(v ? sv[j] : vi, vi);
+          lx.add(aw, dl);
+          ly.add(bw, dl);
+          ux.add(aw, du);
+          uy.add(bw, du);
+          uL.add(cw, du);
+          uxx.add(dw, du);
+          uxy.add(fw, du);
+          vx.add(aw, dv);
+          vy.add(bw, dv);
+          vL.add(cw, dv);
+          vxx.add(dw, dv);
+          vxy.add(fw, dv);
+        }
+      }
+    }
+    double Dv[12] = {lx.template reduce<LPN>(),  ly.template reduce<LPN>(),
+                     ux.template reduce<LPN>(),  uy.template reduce<LPN>(),
+                     uL.template reduce<LPN>(),  uxx.template reduce<LPN>(),
+                     uxy.template reduce<LPN>(), vx.template reduce<LPN>(),
+                     vy.template reduce<LPN>(),  vL.template reduce<LPN>(),
+                     vxx.template reduce<LPN>(), vxy.template reduce<LPN>()};
+    if (sub == 0) {
+      if constexpr (P::kMomentFix) {
+        moment_fix(mom, node, n, Dv[2], Dv[3], Dv[4], Dv[5], Dv[6]);
+        moment_fix(mom, node, n, Dv[7], Dv[8], Dv[9], Dv[10], Dv[11]);
+      }
+      stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl, wn);
+    }
+  }
+}
+
+template <int LPN, int FL, class P>
+__global__ void __launch_bounds__(256)
+filter_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                           const typename P::W* __restrict__ whyp,
+                           const double* __restrict__ kappa, const double* __restrict__ in,
+                           double* __restrict__ out, int n, const double* __restrict__ wn) {
+  using K = Packed<P>;
+  using W = typename P::W;
+  constexpr int V = K::V;
+  constexpr int U = K::kFilterU;
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, in, n, sl, su, sv);
+  const typename K::VT* wh = reinterpret_cast<const typename K::VT*>(whyp);
+  const typename K::IT* lc = reinterpret_cast<const typename K::IT*>(tl.lcol);
+  constexpr int NPR = 256 / LPN;
+  const int sub = threadIdx.x % LPN;
+  const long long n2 = 2 * static_cast<long long>(n);
+#pragma unroll 1
+  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
+    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+    if (node >= n) break;
+    const double li = in[node], ui = in[n + node], vi = in[n2 + node];
+    typename P::Acc al, au, av;
+    al.zero();
+    au.zero();
+    av.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    const int g0 = e0 / V, g1 = (e1 + V - 1) / V;
+    for (int gb = g0 + sub; gb < g1; gb += U * LPN) {
+      int gg[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int g = gb + u * LPN;
+        ok[u] = g < g1;
+        gg[u] = ok[u] ? g : g1 - 1;
+      }
+      typename K::IT jj[U];
+      typename K::VT a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jj[u] = lc[gg[u]];
+        a[u] = wh[gg[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int h = 0; h < V; ++h) {
+          const int e = gg[u] * V + h;
+          const bool v = ok[u] && e >= e0 && e < e1;
+          const int j = v ? K::slot(jj[u], h) : 0;
+          const W aw = v ? (h ? a[u].y : a[u].x) : W(0);
+          al.add(aw, P::diff(v ? sl[j] : li, li));
+          au.add(aw, P::diff(v ? su[j] : ui, ui));
+          av.add(aw, P::diff(v ? sv[j] : vi, vi));
+        }
+      }
+    }
+    const double rl = al.template reduce<LPN>();
+    const double ru = au.template reduce<LPN>();
+    const double rv = av.template reduce<LPN>();
+    if (sub == 0) {
+      const double k = kappa[node];
+      double nx, ny;
+      const bool wall = wall_node(wn, node, nx, ny);  // the wall velocity is imposed
+      out[node] = li + k * rl;
+      out[n + node] = wall ? ui : ui + k * ru;
+      out[n2 + node] = wall ? vi : vi + k * rv;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // time step and finiteness check
 // --------------------------------------------------------------------------
 
@@ -803,11 +1038,40 @@ Tiles tiles_of(const labfm_operators* o) {
   return Tiles{t->halo_count, t->halo_idx, t->lcol, t->max_halo > 0 ? t->max_halo : 1};
 }
 
+// The packed tiled kernels apply when every weight array and the halo
+// slots are aligned for their pair loads: an even nnz and a weight base
+// aligned to two weights.
+template <class P>
+bool packable(const labfm_operators* o, const void* w, bool odd_ok) {
+  if (!Packed<P>::kUse) return false;
+  const uintptr_t wb = reinterpret_cast<uintptr_t>(w);
+  const uintptr_t lb = reinterpret_cast<uintptr_t>(o->tiles->lcol);
+  return (odd_ok || o->nnz % 2 == 0) && wb % (2 * sizeof(typename P::W)) == 0 && lb % 4 == 0;
+}
+
 template <class P>
 hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                         const double* Y, const double* qin, double* qout, double* Yout, double dta,
                         double dtb, const Flow& fl, hipStream_t st) {
   const int n = o->n;
+  if (o->tiles && packable<P>(o, w, true)) {
+    const Tiles tl = tiles_of(o);
+    const size_t shmem = 3 * sizeof(double) * tl.hmax;
+    const bool odd = (o->nnz % 2) != 0;
+    return with_cfg(cfg, [&](auto L, auto F) {
+      if (odd) {
+        hipLaunchKernelGGL(
+            (rk_stage_tiled_packed_kernel<decltype(L)::value, decltype(F)::value, P, true>),
+            dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w, o->mom32,
+            static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n, o->wall_normal);
+      } else {
+        hipLaunchKernelGGL(
+            (rk_stage_tiled_packed_kernel<decltype(L)::value, decltype(F)::value, P, false>),
+            dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w, o->mom32,
+            static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n, o->wall_normal);
+      }
+    });
+  }
   if (o->tiles) {
     const Tiles tl = tiles_of(o);
     const size_t shmem = 3 * sizeof(double) * tl.hmax;
@@ -832,6 +1096,15 @@ hipError_t launch_filter(LaunchCfg cfg, const labfm_operators* o, const typename
                          const double* in, double* out, hipStream_t st) {
   const int n = o->n;
   const typename P::W* whyp = w + LABFM_OP_HYP * o->nnz;
+  if (o->tiles && packable<P>(o, w, false)) {
+    const Tiles tl = tiles_of(o);
+    const size_t shmem = 3 * sizeof(double) * tl.hmax;
+    return with_cfg(cfg, [&](auto L, auto F) {
+      hipLaunchKernelGGL((filter_tiled_packed_kernel<decltype(L)::value, decltype(F)::value, P>),
+                         dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, whyp,
+                         o->kappa, in, out, n, o->wall_normal);
+    });
+  }
   if (o->tiles) {
     const Tiles tl = tiles_of(o);
     const size_t shmem = 3 * sizeof(double) * tl.hmax;

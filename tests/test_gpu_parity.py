@@ -646,26 +646,50 @@ def test_tiles_map_back_to_the_stencils(dev, tg64):
         assert np.array_equal(halo[lc[a:b]], col[a:b])
 
 
+def _odd_nnz_lattice():
+    """A 24 x 24 m = 4 lattice with stencil scales varied by +/-5% per node
+    (equal scales make the stencil relation symmetric and the count even),
+    the first seed whose stencil count is odd."""
+    for seed in range(1, 200):
+        nodes = inputs.jittered_lattice(24, seed=seed, m=4)
+        nodes.h = nodes.h * np.random.default_rng(seed).uniform(0.95, 1.05, nodes.n)
+        rp, _ = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+        if rp[-1] % 2 == 1:
+            return nodes
+    raise AssertionError("no odd stencil count found")
+
+
 @pytest.mark.parametrize("prec_name", ["F64", "F32W", "F32_COMP"])
-def test_tiled_kernels_bitwise_equal_untiled(dev, tg64, prec_name):
-    """Staging the halo in LDS changes where values are read from, not the
-    order of any sum: results are bitwise identical."""
+def test_tiled_kernels_match_untiled(dev, tg64, prec_name):
+    """Tiles change where neighbour values are read from. The float64 and
+    Dot2 tiled stage kernels load edges in pairs (for an odd stencil count
+    two of the weight arrays edge by edge), which changes the lanes'
+    summation order: results agree with the untiled kernels to rounding. The
+    float32-weight, float64-sum kernels walk the rows as the untiled kernels
+    do: results are bitwise identical. Both an even and an odd stencil count
+    are run."""
     from paper_2102_02019_amd import labfm
 
-    nodes, ops, _ = tg64
     prec = getattr(labfm, prec_name)
     prm = inputs.taylor_green_params()
-    l, u, v = _tg_state(nodes)
-    q0 = np.concatenate([l, u, v])
-    outs = []
-    for use in (True, False):
-        ops.use_tiles = use
-        q = T(q0, dev)
-        labfm.rk_step(q, ops, prm, 0.008, 4, prec=prec)
-        r = labfm.ns_rhs(q, ops, prm, prec)
-        outs.append((q.cpu().numpy(), r.cpu().numpy()))
-    ops.use_tiles = True
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    odd = _odd_nnz_lattice()
+    for nodes, ops in ((tg64[0], tg64[1]), (odd, gpu_setup(odd, dev, f32=True))):
+        l, u, v = _tg_state(nodes)
+        q0 = np.concatenate([l, u, v])
+        outs = []
+        for use in (True, False):
+            ops.use_tiles = use
+            q = T(q0, dev)
+            labfm.rk_step(q, ops, prm, 0.008, 4, prec=prec)
+            r = labfm.ns_rhs(q, ops, prm, prec)
+            outs.append((q.cpu().numpy(), r.cpu().numpy()))
+        ops.use_tiles = True
+        if prec_name == "F32W":
+            assert np.array_equal(outs[0][0], outs[1][0])
+            assert np.array_equal(outs[0][1], outs[1][1])
+        else:
+            assert rel(outs[0][0], outs[1][0]) <= 1e-14
+            assert rel(outs[0][1], outs[1][1]) <= 1e-12
 
 
 # ------------------------------------------------ build modes, graded nodes
