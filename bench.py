@@ -32,6 +32,7 @@ Other lines (each one JSON line of its own, same conventions):
               equation) at 1.05M nodes, with the start-up's convergence;
 --lagrangian  the Lagrangian mode on the workload's nodes (stencils and
               weights rebuilt at every RK stage);
+--adjoint     the adjoint of the filtered RK loop (65,536 nodes, 200 steps);
 --stencil-opt the stencil optimisation on the workload and 1.0M graded nodes.
 
 Prints one JSON line.
@@ -73,6 +74,9 @@ def parse():
     ap.add_argument("--poiseuille", action="store_true",
                     help="print the channel (no-slip walls) line instead: Poiseuille start-up\n"
                          "throughput at 1.05M nodes, convergence at t* = 1, oracle baseline")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="print the adjoint line instead: the gradient of a loss of the state\n"
+                         "after 200 steps (tg256_m6) with respect to the initial state")
     ap.add_argument("--lagrangian", action="store_true",
                     help="print the Lagrangian-mode line instead: nodes advected, stencils and\n"
                          "weights rebuilt at every RK stage, on the workload's node set")
@@ -105,6 +109,9 @@ def main():
         return
     if args.lagrangian:
         print(json.dumps(lagrangian_bench(args, inputs, labfm, torch, np, dev)))
+        return
+    if args.adjoint:
+        print(json.dumps(adjoint_bench(args, inputs, labfm, torch, np, dev)))
         return
     wl = inputs.WORKLOADS[args.workload]
     rk_steps = wl.steps if args.rk_steps is None else args.rk_steps
@@ -581,6 +588,103 @@ def lagrangian_bench(args, inputs, labfm, torch, np, dev, rk_steps=10):
     }
     out["cpu_baseline"] = lagrangian_cpu_baseline(inputs, np, wl)
     return out
+
+
+def adjoint_bench(args, inputs, labfm, torch, np, dev, ckpt_every=20):
+    """The adjoint of the filtered RK loop on tg256_m6 (65,536 nodes, m = 6,
+    200 steps, a checkpoint every 20 steps): forward run, then the gradient
+    of a scalar loss of the final state with respect to the initial state
+    (labfm_rk_adjoint: each checkpoint segment recomputed once, then per step
+    the filter adjoint and four stage adjoints, each a forward gather and a
+    transposed gather). Inputs resident on the device. Reports the adjoint's
+    node-updates/s (N x 4 stages x steps / its time), its cost relative to the
+    forward run, and the pass's algorithmic bytes per second. At this size a
+    stage's data (~180 MB) stays in the 256 MB last-level cache, so the rate is
+    a cache-resident one, not an HBM roofline (per-kernel times:
+    profiles/adjoint_tg256_m6_kernel_trace.md)."""
+    wl = inputs.TG256_M6
+    nodes = wl.nodes()
+    N = nodes.n
+    steps = wl.steps
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    x, y, h, s, m = T(nodes.x), T(nodes.y), T(nodes.h), T(nodes.s), T(nodes.m)
+    q0 = T(np.concatenate([np.log(rho), u, v]))
+    rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+    ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, rowsum=True)
+    labfm.build_transpose(ops)
+    dt = labfm.time_step(q0, s, prm.c2, prm.mu, visc=wl.visc_coef)
+    qbar = T(np.random.default_rng(5).standard_normal(3 * N))
+    q = torch.empty_like(q0)
+    ws = labfm.rk_workspace(N, dev)
+
+    def forward():
+        q.copy_(q0)
+        labfm.rk_step(q, ops, prm, dt, steps, workspace=ws)
+
+    def adjoint():
+        return labfm.rk_adjoint(q0, qbar, ops, prm, dt, steps, ckpt_every)
+
+    forward()
+    g = adjoint()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd_ms, adj_ms = [], []
+    for _ in range(max(1, args.steps)):
+        ev[0].record()
+        forward()
+        ev[1].record()
+        g = adjoint()
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        adj_ms.append(ev[1].elapsed_time(ev[2]))
+    fwd, adj = sum(fwd_ms) / len(fwd_ms), sum(adj_ms) / len(adj_ms)
+    kbar = ops.nnz / N
+    # algorithmic bytes per node and step: the recomputed forward step
+    # (4 stages of 44K + 104 and a filter of 12K + 56), four forward gathers
+    # (44K + 216) and four transposed gathers (44K + 240), and the filter
+    # adjoint (12K + 80)
+    per_node_step = (4 * (44 * kbar + 104) + 12 * kbar + 56 + 4 * (44 * kbar + 216)
+                     + 4 * (44 * kbar + 240) + 12 * kbar + 80)
+    achieved = per_node_step * N * steps / (adj * 1e-3) / 1e9
+    return {
+        "metric": "adjoint of the filtered RK loop: node-updates/s (N x 4 stages x steps / time)",
+        "value": N * 4 * steps / (adj * 1e-3), "unit": "node-updates/s", "dtype": "f64",
+        "config": {"workload": wl.name + "_adjoint", "nodes": N, "order_m": wl.m,
+                   "mean_neighbours": round(kbar, 2), "rk_steps": steps,
+                   "checkpoint_every": ckpt_every, "filter": "every step"},
+        "forward_ms": fwd, "adjoint_ms": adj, "adjoint_over_forward": adj / fwd,
+        "gradient_finite": bool(torch.isfinite(g).all().item()),
+        "pass_bytes": {"bound": "cache-resident gathers", "achieved_GBs": achieved,
+                       "bytes_per_node_step": per_node_step,
+                       "note": "about 180 MB per stage at this size: last-level cache"},
+        "cpu_baseline": adjoint_cpu_baseline(inputs, np, wl),
+    }
+
+
+def adjoint_cpu_baseline(inputs, np, wl, n_side=32, n_steps=10):
+    """The oracle's adjoint (explicit sparse operator matrices, every forward
+    state stored) on a 32 x 32 sample with the workload's order and h/s, one
+    core, scaled per node-update."""
+    from oracle import labfm_oracle as O
+
+    nodes = inputs.jittered_lattice(n_side, L=wl.L, seed=wl.seed, m=wl.m)
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, wl.m, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm, visc_coef=wl.visc_coef)
+    qbar = tuple(np.random.default_rng(5).standard_normal((3, nodes.n)))
+    c0 = time.perf_counter()
+    O.rk_adjoint(np.log(rho), u, v, W, prm, dt, n_steps, qbar)
+    c1 = time.perf_counter()
+    return {"value": nodes.n * 4 * n_steps / (c1 - c0), "unit": "node-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"adjoint of {n_steps} filtered steps on a {n_side}x{n_side} lattice "
+                      f"(m={wl.m})"}
 
 
 def nodes_at(inputs, nodes, x, y):

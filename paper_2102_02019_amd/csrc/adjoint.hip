@@ -106,8 +106,10 @@ __global__ void tweights_kernel(const double* __restrict__ w, const int* __restr
 
 // Forward operator sums at Y and the pointwise part of J_R^T: with
 // Rbar = dtb P + dta Ynext (Ynext may be null), writes the twelve operator-sum
-// adjoints g[k][node] (l_x, l_y, u_x, u_y, Lu, u_xx, u_xy, v_x, v_y, Lv,
-// v_xx, v_xy) and the pointwise adjoints loc[f][node] of (ln rho, u, v).
+// adjoints g[node][k] (l_x, l_y, u_x, u_y, Lu, u_xx, u_xy, v_x, v_y, Lv,
+// v_xx, v_xy; node-major, so the transposed gather reads a source node's
+// twelve values from one or two cache lines) and the pointwise adjoints
+// loc[f][node] of (ln rho, u, v).
 template <int LPN>
 __global__ void __launch_bounds__(256)
 adj_forward_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
@@ -154,21 +156,22 @@ adj_forward_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   }
   const double nu = fl.mu / exp(li);
   const double third = 1.0 / 3.0;
+  double* gn = g + 12LL * node;
   // R_l = -(u l_x + v l_y) - (u_x + v_y)
   // R_u = -(u u_x + v u_y) - c2 l_x + nu (Lu + (u_xx + v_xy)/3) + gx
   // R_v = -(u v_x + v v_y) - c2 l_y + nu (4/3 Lv - v_xx/3 + u_xy/3) + gy
-  g[0 * n + node] = -ui * rl - fl.c2 * ru;
-  g[1 * n + node] = -vi * rl - fl.c2 * rv;
-  g[2 * n + node] = -rl - ui * ru;
-  g[3 * n + node] = -vi * ru;
-  g[4 * n + node] = nu * ru;
-  g[5 * n + node] = nu * ru * third;
-  g[6 * n + node] = nu * rv * third;
-  g[7 * n + node] = -ui * rv;
-  g[8 * n + node] = -rl - vi * rv;
-  g[9 * n + node] = 4.0 * third * nu * rv;
-  g[10 * n + node] = -nu * rv * third;
-  g[11 * n + node] = nu * ru * third;
+  gn[0] = -ui * rl - fl.c2 * ru;
+  gn[1] = -vi * rl - fl.c2 * rv;
+  gn[2] = -rl - ui * ru;
+  gn[3] = -vi * ru;
+  gn[4] = nu * ru;
+  gn[5] = nu * ru * third;
+  gn[6] = nu * rv * third;
+  gn[7] = -ui * rv;
+  gn[8] = -rl - vi * rv;
+  gn[9] = 4.0 * third * nu * rv;
+  gn[10] = -nu * rv * third;
+  gn[11] = nu * ru * third;
   // d nu / d ln rho = -nu
   loc[node] = -nu * (ru * (uL + third * (uxx + vxy)) + rv * (vL + third * ((vL - vxx) + uxy)));
   loc[n + node] = -rl * lx - ru * ux - rv * vx;
@@ -176,7 +179,7 @@ adj_forward_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
 }
 
 // Transposed gather of g: Ybar_j = loc_j + sum_{i -> j} w^d_ij g_d(i) - S^d_j g_d(j),
-// then P_j += Pupd_j when Pupd is set.
+// then P_j += Pupd_j when Pupd is set (g node-major, g[i][d]).
 template <int LPN>
 __global__ void __launch_bounds__(256)
 adj_transpose_kernel(const int* __restrict__ tptr, const int* __restrict__ tsrc,
@@ -193,18 +196,19 @@ adj_transpose_kernel(const int* __restrict__ tptr, const int* __restrict__ tsrc,
     const int i = tsrc[e];
     const double a = tw[e], b = tw[nnz + e], c = tw[2 * nnz + e], d = tw[3 * nnz + e],
                  f = tw[4 * nnz + e];
-    sl = fma(a, g[0 * n + i], sl);
-    sl = fma(b, g[1 * n + i], sl);
-    su = fma(a, g[2 * n + i], su);
-    su = fma(b, g[3 * n + i], su);
-    su = fma(c, g[4 * n + i], su);
-    su = fma(d, g[5 * n + i], su);
-    su = fma(f, g[6 * n + i], su);
-    sv = fma(a, g[7 * n + i], sv);
-    sv = fma(b, g[8 * n + i], sv);
-    sv = fma(c, g[9 * n + i], sv);
-    sv = fma(d, g[10 * n + i], sv);
-    sv = fma(f, g[11 * n + i], sv);
+    const double* gi = g + 12LL * i;
+    sl = fma(a, gi[0], sl);
+    sl = fma(b, gi[1], sl);
+    su = fma(a, gi[2], su);
+    su = fma(b, gi[3], su);
+    su = fma(c, gi[4], su);
+    su = fma(d, gi[5], su);
+    su = fma(f, gi[6], su);
+    sv = fma(a, gi[7], sv);
+    sv = fma(b, gi[8], sv);
+    sv = fma(c, gi[9], sv);
+    sv = fma(d, gi[10], sv);
+    sv = fma(f, gi[11], sv);
   }
   sl = group_sum<LPN>(sl);
   su = group_sum<LPN>(su);
@@ -212,13 +216,12 @@ adj_transpose_kernel(const int* __restrict__ tptr, const int* __restrict__ tsrc,
   if (sub != 0) return;
   const long long n2 = 2 * static_cast<long long>(n);
   const double* S = rowsum;  // S[d * n + node]
-  const double dl = S[node] * g[node] + S[n + node] * g[n + node];
-  const double du = S[node] * g[2 * n + node] + S[n + node] * g[3 * n + node] +
-                    S[2 * n + node] * g[4 * n + node] + S[3 * n + node] * g[5 * n + node] +
-                    S[4 * n + node] * g[6 * n + node];
-  const double dv = S[node] * g[7 * n + node] + S[n + node] * g[8 * n + node] +
-                    S[2 * n + node] * g[9 * n + node] + S[3 * n + node] * g[10 * n + node] +
-                    S[4 * n + node] * g[11 * n + node];
+  const double* gj = g + 12LL * node;
+  const double dl = S[node] * gj[0] + S[n + node] * gj[1];
+  const double du = S[node] * gj[2] + S[n + node] * gj[3] + S[2 * n + node] * gj[4] +
+                    S[3 * n + node] * gj[5] + S[4 * n + node] * gj[6];
+  const double dv = S[node] * gj[7] + S[n + node] * gj[8] + S[2 * n + node] * gj[9] +
+                    S[3 * n + node] * gj[10] + S[4 * n + node] * gj[11];
   Ybar[node] = loc[node] + (sl - dl);
   Ybar[n + node] = loc[n + node] + (su - du);
   Ybar[n2 + node] = loc[n2 + node] + (sv - dv);
