@@ -18,6 +18,9 @@ roofline: the fused RK stage kernel, algorithmic bytes per launch
 graph_replayed_steps: the same RK steps replayed from a HIP graph;
 build: stencil search and weight build of the workload (HIP events) and
          the build's algorithmic FP64 FLOP/s against the FP64 peak;
+stream_copy: measured bandwidth of plain streaming kernels on 1 GiB (a
+         device copy, read + write, and a read-only sum; best of 5 each), the
+         measured ceiling the stage kernel's bandwidth is also compared with;
 f32w, f32_comp: the same job with float32 weights (float64 sums, or
          float32 compensated Dot2 sums), speedup and per-field error against
          the float64 run;
@@ -220,6 +223,7 @@ def main():
     graph_equal = bool(torch.equal(q, q64))
 
     build = build_rate(labfm, torch, np, nodes, x, y, h, s, m)
+    stream = stream_copy_rate(torch, dev)
 
     out = {
         "metric": METRIC,
@@ -243,7 +247,9 @@ def main():
                      "traffic": traffic,
                      "bytes_per_node_stage": 44.0 * kbar + 104.0,
                      "algorithmic_bytes_per_launch": bytes_stage,
-                     "mean_launch_ms": stage_ms, "launches": launches},
+                     "mean_launch_ms": stage_ms, "launches": launches,
+                     "frac_of_stream_copy": achieved / stream["GBs"]},
+        "stream_copy": stream,
         "stage_kernel_node_updates_per_s": N / (stage_ms * 1e-3),
         "graph_replayed_steps": {"node_updates_per_s": N * 4 * rk_steps / graph_s,
                                  "ms_per_rk_step": graph_s * 1e3 / rk_steps,
@@ -745,6 +751,40 @@ def stage_kernel_name(shape, tiled, prec_tag, nnz=None):
         if packed and nnz is not None:
             tail = ", " + ("true" if nnz % 2 else "false")
     return f"{kern}<{lpn}, {flags}, *{prec_tag}{tail}>"
+
+
+def stream_copy_rate(torch, dev, reps=5):
+    """Measured bandwidth ceilings of plain streaming kernels on 1 GiB of
+    float64 (torch's own): a device copy (read + write, 2 GiB moved) and a
+    sum (read only, 1 GiB), each the best of reps, timed with events on
+    torch's stream (the one both run on). GBs is the larger of the two."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    r = a.sum()
+
+    def best_ms(fn):
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    nb = float(a.numel() * a.element_size())
+    t_copy = best_ms(lambda: b.copy_(a))
+    t_sum = best_ms(lambda: torch.sum(a, 0, out=r))
+    del a, b, r
+    copy_gbs = 2.0 * nb / (t_copy * 1e-3) / 1e9
+    read_gbs = nb / (t_sum * 1e-3) / 1e9
+    best = max(copy_gbs, read_gbs)
+    return {"GBs": best, "copy_GBs": copy_gbs, "copy_ms": t_copy, "read_GBs": read_gbs,
+            "read_ms": t_sum, "bytes": nb, "frac_of_hbm_peak": best / HBM_PEAK_GBS}
 
 
 def build_flops(m, K):
