@@ -22,13 +22,18 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+# weights.hip: LDS atomics are issued as they are written. The compiler's
+# atomic optimizer would otherwise turn each pivot proposal (an LDS max from a
+# few lanes) into a loop over the active lanes, a dozen instructions per lane,
+# on the LU's critical path.
+FILE_FLAGS = {"weights.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
            "boundaries.hip", "lagrangian.hip", "morton.hip"]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *HIP_FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

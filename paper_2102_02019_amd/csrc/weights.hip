@@ -709,10 +709,28 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
       const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
       const double ucj = sm.A[c * S::LDA + jj];
       unsigned long long best = 0ull;
-#pragma unroll 4
-      for (int r = c + 1 + rg; r < n; r += groups) {
-        const double l = sm.A[r * S::LDA + c] * inv;
-        const double v = fma(-l, ucj, sm.A[r * S::LDA + jj]);
+      // two rows per trip, their four LDS reads issued together (column c
+      // is only read in this step, and each A[r][jj] belongs to one
+      // thread); a loop that is not unrolled further needs no trip count,
+      // whose integer division cost more than the rows it served
+      int r = c + 1 + rg;
+#pragma unroll 1
+      for (; r + groups < n; r += 2 * groups) {
+        const int r1 = r + groups;
+        const double a0 = sm.A[r * S::LDA + c], b0 = sm.A[r * S::LDA + jj];
+        const double a1 = sm.A[r1 * S::LDA + c], b1 = sm.A[r1 * S::LDA + jj];
+        const double v0 = fma(-(a0 * inv), ucj, b0);
+        const double v1 = fma(-(a1 * inv), ucj, b1);
+        sm.A[r * S::LDA + jj] = v0;
+        sm.A[r1 * S::LDA + jj] = v1;
+        if (t == 0) {
+          const unsigned long long k0 = pivot_key(v0, r), k1 = pivot_key(v1, r1);
+          const unsigned long long k = k0 > k1 ? k0 : k1;
+          best = k > best ? k : best;
+        }
+      }
+      if (r < n) {
+        const double v = fma(-(sm.A[r * S::LDA + c] * inv), ucj, sm.A[r * S::LDA + jj]);
         sm.A[r * S::LDA + jj] = v;
         if (t == 0) {
           const unsigned long long kv = pivot_key(v, r);
