@@ -672,15 +672,31 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
   using S = Shape<MMAX>;
   bool singular = false;
   // ---- LU with partial pivoting on [M~ | C~] --------------------------------
-  // One barrier per column (two when rows are swapped): the threads that
-  // update column c+1 in step c also propose its pivot (LDS atomic max of the
-  // keys), so there is no separate pivot search. The multipliers are not
-  // kept (the right-hand sides are eliminated along).
+  // Columns are eliminated in pairs (c, c+1), with the arithmetic of two
+  // single-column steps in their order:
+  //   A: the pivot of column c is known (its key); rows c and bi swap, and
+  //      wavefront 0 applies step c to column c+1 alone (one row per lane),
+  //      proposing the pivot of column c+1 (LDS atomic max of the keys);
+  //   B: rows c+1 and bi1 swap, and every thread applies steps c and c+1 to
+  //      its column of the rest (columns c+2.. and the right-hand sides):
+  //      a <- a - l_c u_c, then a <- a - l_{c+1} u_{c+1}, with u_{c+1} the
+  //      pivot row after step c, which each thread forms for its column.
+  //      The threads updating column c+2 propose its pivot.
+  // Each half ends with a barrier (and a swap adds one), so the barriers are
+  // as many as with single columns while the bulk update, and its fixed
+  // cost, runs once per pair. Row c+1 after step c is written to a staging
+  // row (sm.psi, unused until the solution is copied out) and moved into A
+  // during the next pair, since its old values are read throughout B. The
+  // multipliers are not kept (the right-hand sides are eliminated along).
+  // Key slots: the sub-step for column s reads key[s % 3], clears
+  // key[(s + 2) % 3] and proposes into key[(s + 1) % 3].
   if (tid < 3) sm.key[tid] = 0ull;
   lds_barrier();
   for (int r = tid; r < n; r += kBlock) atomicMax(&sm.key[0], pivot_key(sm.A[r * S::LDA], r));
   lds_barrier();
-  for (int c = 0; c < n; ++c) {
+  double* stage = sm.psi;
+  int staged = -1;  // row whose step-c values wait in the staging row, or -1
+  for (int c = 0; c < n; c += 2) {
     const unsigned long long kc = uniform64(sm.key[c % 3]);
     const unsigned long long vb = kc & ~0x7Full;
     if (vb == 0ull || vb >= 0x7FF0000000000000ull) {  // zero or non-finite column
@@ -688,8 +704,16 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
       break;
     }
     const int bi = 127 - static_cast<int>(kc & 0x7Full);
-    // the key of column c+2 is next written in step c+1, after a barrier
     if (tid == 0) sm.key[(c + 2) % 3] = 0ull;
+    // the previous pair's row c-1 (columns c.. and the right-hand sides) by
+    // wavefronts 1-3; rows >= c are all that this pair touches
+    if (staged >= 0 && tid >= 64) {
+      const int w1 = (n - c) + LABFM_NUM_OPS;
+      for (int t = tid - 64; t < w1; t += kBlock - 64) {
+        const int jj = (t < n - c) ? (c + t) : (S::NMAX + t - (n - c));
+        sm.A[staged * S::LDA + jj] = stage[t];
+      }
+    }
     const int width = (n - c) + LABFM_NUM_OPS;  // columns c..n-1 and the RHS
     if (bi != c) {
       for (int t = tid; t < width; t += kBlock) {
@@ -700,27 +724,65 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
       }
       lds_barrier();
     }
-    const double inv = 1.0 / sm.A[c * S::LDA + c];
-    const int W = width - 1;  // columns right of c
+    const double inv0 = 1.0 / sm.A[c * S::LDA + c];
+    if (c + 1 == n) {  // last column alone: nothing below it
+      staged = -1;
+      lds_barrier();
+      break;
+    }
+    // ---- A: column c+1 (rows c+1..n-1, at most 64: one per lane of wave 0)
+    {
+      const int r = c + 1 + tid;
+      if (r < n) {
+        const double v = fma(-(sm.A[r * S::LDA + c] * inv0), sm.A[c * S::LDA + c + 1],
+                             sm.A[r * S::LDA + c + 1]);
+        sm.A[r * S::LDA + c + 1] = v;
+        atomicMax(&sm.key[(c + 1) % 3], pivot_key(v, r));
+      }
+    }
+    lds_barrier();
+    // ---- B: pivot of column c+1, then both steps on the rest
+    const int c1 = c + 1;
+    const unsigned long long kc1 = uniform64(sm.key[c1 % 3]);
+    const unsigned long long vb1 = kc1 & ~0x7Full;
+    if (vb1 == 0ull || vb1 >= 0x7FF0000000000000ull) {
+      singular = true;
+      break;
+    }
+    const int bi1 = 127 - static_cast<int>(kc1 & 0x7Full);
+    if (tid == 0) sm.key[(c1 + 2) % 3] = 0ull;
+    if (bi1 != c1) {
+      for (int t = tid; t < width; t += kBlock) {
+        const int jj = (t < n - c) ? (c + t) : (S::NMAX + t - (n - c));
+        const double t0 = sm.A[c1 * S::LDA + jj];
+        sm.A[c1 * S::LDA + jj] = sm.A[bi1 * S::LDA + jj];
+        sm.A[bi1 * S::LDA + jj] = t0;
+      }
+      lds_barrier();
+    }
+    const double inv1 = 1.0 / sm.A[c1 * S::LDA + c1];
+    const double l01 = sm.A[c1 * S::LDA + c] * inv0;  // row c+1's multiplier in step c
+    const int nc = n - c - 2;                          // matrix columns right of c+1
+    const int W = nc + LABFM_NUM_OPS;
     const int groups = small_div(kBlock, W);
     const int rg = small_div(tid, W);
     if (rg < groups) {
       const int t = tid - rg * W;
-      const int jj = (t < n - c - 1) ? (c + 1 + t) : (S::NMAX + t - (n - c - 1));
-      const double ucj = sm.A[c * S::LDA + jj];
+      const int jj = (t < nc) ? (c + 2 + t) : (S::NMAX + t - nc);
+      const double u0 = sm.A[c * S::LDA + jj];
+      const double u1 = fma(-l01, u0, sm.A[c1 * S::LDA + jj]);
+      if (rg == 0) stage[t] = u1;
       unsigned long long best = 0ull;
-      // two rows per trip, their four LDS reads issued together (column c
-      // is only read in this step, and each A[r][jj] belongs to one
-      // thread); a loop that is not unrolled further needs no trip count,
-      // whose integer division cost more than the rows it served
-      int r = c + 1 + rg;
+      int r = c + 2 + rg;
 #pragma unroll 1
       for (; r + groups < n; r += 2 * groups) {
         const int r1 = r + groups;
-        const double a0 = sm.A[r * S::LDA + c], b0 = sm.A[r * S::LDA + jj];
-        const double a1 = sm.A[r1 * S::LDA + c], b1 = sm.A[r1 * S::LDA + jj];
-        const double v0 = fma(-(a0 * inv), ucj, b0);
-        const double v1 = fma(-(a1 * inv), ucj, b1);
+        const double a0 = sm.A[r * S::LDA + c], b0 = sm.A[r * S::LDA + c1];
+        const double x0 = sm.A[r * S::LDA + jj];
+        const double a1 = sm.A[r1 * S::LDA + c], b1 = sm.A[r1 * S::LDA + c1];
+        const double x1 = sm.A[r1 * S::LDA + jj];
+        const double v0 = fma(-(b0 * inv1), u1, fma(-(a0 * inv0), u0, x0));
+        const double v1 = fma(-(b1 * inv1), u1, fma(-(a1 * inv0), u0, x1));
         sm.A[r * S::LDA + jj] = v0;
         sm.A[r1 * S::LDA + jj] = v1;
         if (t == 0) {
@@ -730,14 +792,26 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
         }
       }
       if (r < n) {
-        const double v = fma(-(sm.A[r * S::LDA + c] * inv), ucj, sm.A[r * S::LDA + jj]);
+        const double x = fma(-(sm.A[r * S::LDA + c] * inv0), u0, sm.A[r * S::LDA + jj]);
+        const double v = fma(-(sm.A[r * S::LDA + c1] * inv1), u1, x);
         sm.A[r * S::LDA + jj] = v;
         if (t == 0) {
           const unsigned long long kv = pivot_key(v, r);
           best = kv > best ? kv : best;
         }
       }
-      if (t == 0 && best != 0ull) atomicMax(&sm.key[(c + 1) % 3], best);
+      if (t == 0 && best != 0ull) atomicMax(&sm.key[(c1 + 1) % 3], best);
+    }
+    staged = c1;
+    lds_barrier();
+  }
+  if (!singular && staged >= 0) {
+    // the last pair's row c+1 (columns from n and the right-hand sides)
+    const int c = staged + 1;
+    const int w1 = (n - c) + LABFM_NUM_OPS;
+    for (int t = tid; t < w1; t += kBlock) {
+      const int jj = (t < n - c) ? (c + t) : (S::NMAX + t - (n - c));
+      sm.A[staged * S::LDA + jj] = stage[t];
     }
     lds_barrier();
   }
