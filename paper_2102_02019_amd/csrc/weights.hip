@@ -817,16 +817,28 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
   }
   if (!singular) {
   // ---- back substitution ----------------------------------------------------
-  for (int c = n - 1; c >= 0; --c) {
+  // Rows c and c-1 per pass: six threads solve row c, apply it to row c-1
+  // and solve that; then the rows above take both updates, in the order of
+  // two single-row passes (half the barriers).
+  for (int c = n - 1; c >= 0; c -= 2) {
     if (tid < LABFM_NUM_OPS) {
       const int jj = S::NMAX + tid;
-      sm.A[c * S::LDA + jj] = sm.A[c * S::LDA + jj] / sm.A[c * S::LDA + c];
+      const double p = sm.A[c * S::LDA + jj] / sm.A[c * S::LDA + c];
+      sm.A[c * S::LDA + jj] = p;
+      if (c >= 1) {
+        double x = sm.A[(c - 1) * S::LDA + jj];
+        x -= sm.A[(c - 1) * S::LDA + c] * p;
+        sm.A[(c - 1) * S::LDA + jj] = x / sm.A[(c - 1) * S::LDA + c - 1];
+      }
     }
     lds_barrier();
-    for (int t = tid; t < c * LABFM_NUM_OPS; t += kBlock) {
+    for (int t = tid; t < (c - 1) * LABFM_NUM_OPS; t += kBlock) {
       const int r = t / LABFM_NUM_OPS, d = t - r * LABFM_NUM_OPS;
       const int jj = S::NMAX + d;
-      sm.A[r * S::LDA + jj] -= sm.A[r * S::LDA + c] * sm.A[c * S::LDA + jj];
+      double v = sm.A[r * S::LDA + jj];
+      v -= sm.A[r * S::LDA + c] * sm.A[c * S::LDA + jj];
+      v -= sm.A[r * S::LDA + c - 1] * sm.A[(c - 1) * S::LDA + jj];
+      sm.A[r * S::LDA + jj] = v;
     }
     lds_barrier();
   }
