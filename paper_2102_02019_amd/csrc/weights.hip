@@ -567,11 +567,15 @@ __device__ void assemble_system(const BuildArgs& g, int i, int m, int n, int e0,
   double4_t acc[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) acc[k] = double4_t{0.0, 0.0, 0.0, 0.0};
+  // table lanes: lanes 0..31 of wavefronts 0 and 1, two per neighbour (x and
+  // y); wavefront 0 writes the Hermite tables, wavefront 1 the monomial ones,
+  // so the two kinds are computed side by side rather than one after the other
+  const bool tab_lane = tid < 128 && lane < 32;
   NbrPrefetch pf;
-  if (tid < 64) pf.init(g, e0, K, lane >> 2);
+  if (tab_lane) pf.init(g, e0, K, lane >> 1);
   for (int k0 = 0; k0 < K; k0 += kChunk) {
-    if (tid < 64) {
-      const int kk = lane >> 2, t = lane & 3;
+    if (tab_lane) {
+      const int kk = lane >> 1, t = (lane & 1) + (wave == 0 ? 2 : 0);
       double xj, yj;
       const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
       double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
@@ -879,13 +883,14 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   const double kf = 2.0 * M_PI / (3.0 * s);
   double rs = 0.0, f0 = 0.0, mx = 0.0, my = 0.0;
   double* nbx = sm.nb();  // [0, 16): dx, [16, 32): dy, [32, 48): cos(kf dx), [48, 64): cos(kf dy)
+  // table lanes as in the assembly: wavefront 0 writes the psi He_a and He_b
+  // tables, wavefront 1 each neighbour's offsets and filter cosines
+  const bool tab_lane = tid < 128 && lane < 32;
   NbrPrefetch pf;
-  if (tid < 64) pf.init(g, e0, K, lane >> 2);
+  if (tab_lane) pf.init(g, e0, K, lane >> 1);
   for (int k0 = 0; k0 < K; k0 += kChunk) {
-    if (tid < 64) {
-      // basis tables of 16 neighbours (the psi He_a and He_b ones are used);
-      // lanes t = 0, 1 keep each neighbour's offset and filter cosine
-      const int kk = lane >> 2, t = lane & 3;
+    if (tab_lane) {
+      const int kk = lane >> 1, t = (lane & 1) + (tid < 64 ? 2 : 0);
       double xj, yj;
       const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
       double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
