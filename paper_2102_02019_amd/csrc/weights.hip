@@ -997,12 +997,14 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
 }
 
 // one workgroup per node of the list (or per node when list is null)
-// Waves per SIMD for the workgroup-per-node kernel: up to m = 8 the LDS of
-// seven workgroups fits a CU and the register allocator fits seven without
-// spilling; m = 10 is bounded by its LDS (four workgroups).
+// Waves per SIMD for the workgroup-per-node kernel (measured): m = 8 runs
+// eight workgroups per CU (its LDS just fits eight; 64 VGPRs, a few values
+// spilled at the phase boundaries), m = 4 and 6 seven (at eight their spills
+// cost more than the extra workgroup brings), m = 10 is bounded by its LDS
+// (four workgroups).
 template <int MMAX>
 constexpr int block_waves() {
-  return MMAX <= 8 ? 7 : 4;
+  return MMAX == 8 ? 8 : (MMAX < 8 ? 7 : 4);
 }
 
 template <int MMAX>
