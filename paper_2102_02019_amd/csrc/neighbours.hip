@@ -10,8 +10,12 @@
 // separate sort. The distance test rounds every product and sum separately
 // (no fused multiply-add), so the lists are reproducible bit for bit by any
 // IEEE-754 double implementation of the same test.
+#include <algorithm>
 #include <climits>
 #include <cmath>
+#include <rocprim/device/device_reduce.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "common.hpp"
 
@@ -59,18 +63,13 @@ __device__ __forceinline__ bool within(double xi, double yi, double xj, double y
   return d2 <= r2;
 }
 
-__global__ void max_reduce_kernel(const double* __restrict__ v, int n, double* out) {
-  __shared__ double sh[1024];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sh[0];
-}
+// max over h ignoring NaN (fmax), from 0
+struct FMax {
+  __host__ __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct ToI64 {
+  __host__ __device__ long long operator()(int v) const { return static_cast<long long>(v); }
+};
 
 __global__ void bin_count_kernel(const double* __restrict__ x, const double* __restrict__ y, int n,
                                  Grid g, int* __restrict__ cell_of, int* __restrict__ cell_count) {
@@ -81,37 +80,6 @@ __global__ void bin_count_kernel(const double* __restrict__ x, const double* __r
   const int c = cy * g.ncx + cx;
   cell_of[i] = c;
   atomicAdd(&cell_count[c], 1);
-}
-
-// Exclusive scan of int32 counts into int32 offsets (out has n+1 entries),
-// one block walking the array in tiles; the running total is kept in int64
-// and reported through total (so overflow of int32 can be detected).
-constexpr int kScanThreads = 1024;
-__global__ void __launch_bounds__(kScanThreads)
-scan_kernel(const int* __restrict__ in, int* __restrict__ out, int n, long long* total) {
-  __shared__ long long sh[kScanThreads];
-  long long carry = 0;
-  for (int base = 0; base < n; base += kScanThreads) {
-    const int i = base + threadIdx.x;
-    const long long v = (i < n) ? static_cast<long long>(in[i]) : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the tile
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      long long t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += t;
-      __syncthreads();
-    }
-    const long long incl = carry + sh[threadIdx.x];
-    if (i < n) out[i] = static_cast<int>(incl - v);
-    carry += sh[kScanThreads - 1];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[n] = static_cast<int>(carry);
-    *total = carry;
-  }
 }
 
 __global__ void bin_scatter_kernel(const int* __restrict__ cell_of, int n,
@@ -248,13 +216,29 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
       if (p) (void)hipFree(p);
     }
   };
+  // device-wide reductions and scans (rocPRIM): their temporary storage is
+  // sized once for the largest of them (the cell table has at most 4n + 65
+  // entries, see below)
+  const size_t nscan = 4 * static_cast<size_t>(n) + 65;
+  size_t tb_max = 0, tb_sum = 0, tb_scan = 0;
+  LABFM_HIP(rocprim::reduce(nullptr, tb_max, h, static_cast<double*>(nullptr), 0.0,
+                            static_cast<size_t>(n), FMax(), st));
+  LABFM_HIP(rocprim::reduce(nullptr, tb_sum,
+                            rocprim::make_transform_iterator(static_cast<const int*>(nullptr), ToI64()),
+                            static_cast<long long*>(nullptr), 0LL, static_cast<size_t>(n),
+                            rocprim::plus<long long>(), st));
+  LABFM_HIP(rocprim::exclusive_scan(nullptr, tb_scan, static_cast<const int*>(nullptr),
+                                    static_cast<int*>(nullptr), 0, nscan, rocprim::plus<int>(),
+                                    st));
+  size_t tbytes = std::max(tb_max, std::max(tb_sum, tb_scan));
+  tbytes = (tbytes + 255) & ~static_cast<size_t>(255);
   Temp t_small;
-  LABFM_HIP(hipMalloc(&t_small.p, 64));
+  LABFM_HIP(hipMalloc(&t_small.p, 256 + tbytes));
   double* d_hmax = static_cast<double*>(t_small.p);
   long long* d_total = reinterpret_cast<long long*>(static_cast<char*>(t_small.p) + 16);
+  void* d_temp = static_cast<char*>(t_small.p) + 256;
 
-  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(1024), 0, st, h, n, d_hmax);
-  LABFM_LAUNCHED();
+  LABFM_HIP(rocprim::reduce(d_temp, tbytes, h, d_hmax, 0.0, static_cast<size_t>(n), FMax(), st));
   double hmax = 0.0;
   LABFM_HIP(hipMemcpyAsync(&hmax, d_hmax, sizeof(double), hipMemcpyDeviceToHost, st));
   LABFM_HIP(hipStreamSynchronize(st));
@@ -283,12 +267,12 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   const int ncell = g.ncx * g.ncy;
 
   Temp t_big;
-  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 3 + 2 * (ncell + 1));
+  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 3 + 1 + 2 * (ncell + 1));
   LABFM_HIP(hipMalloc(&t_big.p, bytes));
   int* cell_of = static_cast<int*>(t_big.p);
   int* cell_nodes = cell_of + n;
-  int* counts = cell_nodes + n;
-  int* cell_count = counts + n;            // ncell + 1
+  int* counts = cell_nodes + n;              // n + 1 (the last stays 0)
+  int* cell_count = counts + n + 1;          // ncell + 1 (the last stays 0)
   int* cell_start = cell_count + ncell + 1;  // ncell + 1
 
   const int T = 256;
@@ -296,9 +280,8 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   hipLaunchKernelGGL(bin_count_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, n, g,
                      cell_of, cell_count);
   LABFM_LAUNCHED();
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, cell_count, cell_start,
-                     ncell, d_total);
-  LABFM_LAUNCHED();
+  LABFM_HIP(rocprim::exclusive_scan(d_temp, tbytes, cell_count, cell_start, 0,
+                                    static_cast<size_t>(ncell) + 1, rocprim::plus<int>(), st));
   LABFM_HIP(hipMemsetAsync(cell_count, 0, sizeof(int) * (ncell + 1), st));  // now cursors
   hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, cell_of, n,
                      cell_start, cell_count, cell_nodes);
@@ -309,9 +292,13 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   hipLaunchKernelGGL(count_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, h, n, g, cell_of,
                      cell_start, cell_nodes, counts);
   LABFM_LAUNCHED();
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, counts, row_ptr, n,
-                     d_total);
-  LABFM_LAUNCHED();
+  LABFM_HIP(hipMemsetAsync(counts + n, 0, sizeof(int), st));
+  // the total in 64 bits (an int32 offset past INT_MAX is reported below)
+  LABFM_HIP(rocprim::reduce(d_temp, tbytes, rocprim::make_transform_iterator(
+                                static_cast<const int*>(counts), ToI64()),
+                            d_total, 0LL, static_cast<size_t>(n), rocprim::plus<long long>(), st));
+  LABFM_HIP(rocprim::exclusive_scan(d_temp, tbytes, counts, row_ptr, 0,
+                                    static_cast<size_t>(n) + 1, rocprim::plus<int>(), st));
   long long total = 0;
   LABFM_HIP(hipMemcpyAsync(&total, d_total, sizeof(long long), hipMemcpyDeviceToHost, st));
   LABFM_HIP(hipStreamSynchronize(st));
