@@ -524,7 +524,7 @@ __device__ __forceinline__ int small_div(int a, int b) {
 // relative, the first row. Rows are < 128 (n <= 65).
 __device__ __forceinline__ unsigned long long pivot_key(double a, int r) {
   const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(fabs(a)));
-  return (b & ~0x7Full) | static_cast<unsigned long long>(127 - r);
+  return (b & ~0x7Full) | static_cast<unsigned long long>(static_cast<unsigned>(127 - r));
 }
 
 // Assembles [M~ | C~] of node i (order m, n moments, K neighbours from e0,
@@ -685,7 +685,8 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
   //      its column of the rest (columns c+2.. and the right-hand sides):
   //      a <- a - l_c u_c, then a <- a - l_{c+1} u_{c+1}, with u_{c+1} the
   //      pivot row after step c, which each thread forms for its column.
-  //      The threads updating column c+2 propose its pivot.
+  //      Column c+2 (the next pivot column) is done by wavefront 0, one row
+  //      per lane, which also proposes its pivot.
   // Each half ends with a barrier (and a swap adds one), so the barriers are
   // as many as with single columns while the bulk update, and its fixed
   // cost, runs once per pair. Row c+1 after step c is written to a staging
@@ -767,16 +768,33 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
     const double inv1 = 1.0 / sm.A[c1 * S::LDA + c1];
     const double l01 = sm.A[c1 * S::LDA + c] * inv0;  // row c+1's multiplier in step c
     const int nc = n - c - 2;                          // matrix columns right of c+1
-    const int W = nc + LABFM_NUM_OPS;
+    // column c+2, the next pivot column, by wavefront 0 (one row per lane,
+    // at most 63), with the pivot proposals; the rest of the pass has none
+    if (nc > 0) {
+      const int r = c + 2 + tid;
+      if (r < n) {
+        const int j = c + 2;
+        const double u0 = sm.A[c * S::LDA + j];
+        const double u1 = fma(-l01, u0, sm.A[c1 * S::LDA + j]);
+        if (tid == 0) stage[0] = u1;
+        const double x = fma(-(sm.A[r * S::LDA + c] * inv0), u0, sm.A[r * S::LDA + j]);
+        const double v = fma(-(sm.A[r * S::LDA + c1] * inv1), u1, x);
+        sm.A[r * S::LDA + j] = v;
+        atomicMax(&sm.key[(c1 + 1) % 3], pivot_key(v, r));
+      }
+    }
+    // columns c+3.. and the right-hand sides: slot t of the pair's columns
+    // (t < nc: column c+2+t, else right-hand side t-nc), t from off
+    const int off = nc > 0 ? 1 : 0;
+    const int W = nc + LABFM_NUM_OPS - off;
     const int groups = small_div(kBlock, W);
     const int rg = small_div(tid, W);
     if (rg < groups) {
-      const int t = tid - rg * W;
+      const int t = tid - rg * W + off;
       const int jj = (t < nc) ? (c + 2 + t) : (S::NMAX + t - nc);
       const double u0 = sm.A[c * S::LDA + jj];
       const double u1 = fma(-l01, u0, sm.A[c1 * S::LDA + jj]);
       if (rg == 0) stage[t] = u1;
-      unsigned long long best = 0ull;
       int r = c + 2 + rg;
 #pragma unroll 1
       for (; r + groups < n; r += 2 * groups) {
@@ -785,26 +803,13 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
         const double x0 = sm.A[r * S::LDA + jj];
         const double a1 = sm.A[r1 * S::LDA + c], b1 = sm.A[r1 * S::LDA + c1];
         const double x1 = sm.A[r1 * S::LDA + jj];
-        const double v0 = fma(-(b0 * inv1), u1, fma(-(a0 * inv0), u0, x0));
-        const double v1 = fma(-(b1 * inv1), u1, fma(-(a1 * inv0), u0, x1));
-        sm.A[r * S::LDA + jj] = v0;
-        sm.A[r1 * S::LDA + jj] = v1;
-        if (t == 0) {
-          const unsigned long long k0 = pivot_key(v0, r), k1 = pivot_key(v1, r1);
-          const unsigned long long k = k0 > k1 ? k0 : k1;
-          best = k > best ? k : best;
-        }
+        sm.A[r * S::LDA + jj] = fma(-(b0 * inv1), u1, fma(-(a0 * inv0), u0, x0));
+        sm.A[r1 * S::LDA + jj] = fma(-(b1 * inv1), u1, fma(-(a1 * inv0), u0, x1));
       }
       if (r < n) {
         const double x = fma(-(sm.A[r * S::LDA + c] * inv0), u0, sm.A[r * S::LDA + jj]);
-        const double v = fma(-(sm.A[r * S::LDA + c1] * inv1), u1, x);
-        sm.A[r * S::LDA + jj] = v;
-        if (t == 0) {
-          const unsigned long long kv = pivot_key(v, r);
-          best = kv > best ? kv : best;
-        }
+        sm.A[r * S::LDA + jj] = fma(-(sm.A[r * S::LDA + c1] * inv1), u1, x);
       }
-      if (t == 0 && best != 0ull) atomicMax(&sm.key[(c1 + 1) % 3], best);
     }
     staged = c1;
     lds_barrier();
