@@ -87,7 +87,7 @@ typedef struct {
 /* Node tiles for the LDS-staged gather kernels (labfm_build_tiles): tile t
  * holds nodes [t*LABFM_TILE_NODES, (t+1)*LABFM_TILE_NODES); its halo is the
  * ascending list of distinct neighbour indices of its rows. */
-#define LABFM_TILE_NODES 64
+#define LABFM_TILE_NODES 32
 #define LABFM_TILE_HALO_MAX 1024
 typedef struct {
   int32_t ntiles;             /* labfm_tile_count(n) */

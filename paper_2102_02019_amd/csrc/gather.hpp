@@ -542,8 +542,10 @@ rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
   using D = typename P::D;
   const int sub = threadIdx.x % LPN;
 #pragma unroll 1
-  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
-    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
     if (node >= n) break;  // whole LPN groups stop together
     const double li = Y[node], ui = Y[n + node], vi = Y[2 * static_cast<long long>(n) + node];
     typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
@@ -628,8 +630,10 @@ filter_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
   const int sub = threadIdx.x % LPN;
   const long long n2 = 2 * static_cast<long long>(n);
 #pragma unroll 1
-  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
-    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
     if (node >= n) break;
     const double li = in[node], ui = in[n + node], vi = in[n2 + node];
     typename P::Acc al, au, av;
@@ -749,8 +753,10 @@ rk_stage_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
   constexpr int NPR = 256 / LPN;
   const int sub = threadIdx.x % LPN;
 #pragma unroll 1
-  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
-    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
     if (node >= n) break;  // whole LPN groups stop together
     const double li = Y[node], ui = Y[n + node], vi = Y[2 * static_cast<long long>(n) + node];
     typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
@@ -857,8 +863,10 @@ filter_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
   const int sub = threadIdx.x % LPN;
   const long long n2 = 2 * static_cast<long long>(n);
 #pragma unroll 1
-  for (int r = 0; r < LABFM_TILE_NODES / NPR; ++r) {
-    const int node = t * LABFM_TILE_NODES + r * NPR + threadIdx.x / LPN;
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
     if (node >= n) break;
     const double li = in[node], ui = in[n + node], vi = in[n2 + node];
     typename P::Acc al, au, av;
@@ -1005,10 +1013,12 @@ bool valid_cfg(const labfm_launch_config& c) {
 // overridden per kernel and precision by labfm_set_launch_config or
 // labfm_tune.
 LaunchCfg default_cfg(int kernel, labfm_prec prec, int n, long long nnz) {
-  (void)prec;
   const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
   int lpn = k > 48.0 ? 16 : (k > 12.0 ? 8 : 4);
   if (kernel == LABFM_KERNEL_FILTER && k > 48.0) lpn = 8;
+  // float64 stage on 32-node tiles: 8 lanes per node (two passes of 32 nodes
+  // per workgroup) measured 197 us against 200 us for 16 at 262,144 nodes, K = 90
+  if (kernel == LABFM_KERNEL_STAGE && prec == LABFM_F64 && k > 48.0) lpn = 8;
   return LaunchCfg{lpn, 0};
 }
 

@@ -166,6 +166,10 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        # the tile size is compiled into the library (LABFM_TILE_NODES)
+        if L.labfm_tile_count(TILE_NODES) != 1 or L.labfm_tile_count(TILE_NODES + 1) != 2:
+            raise RuntimeError(f"{LIB_PATH} was built for another tile size than "
+                               f"TILE_NODES = {TILE_NODES}")
         _lib = L
     return _lib
 
@@ -358,7 +362,7 @@ def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, 
             "build_ms": st.build_ms, "stage_ms": st.stage_ms, "nnz_capacity": nnz_capacity}
 
 
-TILE_NODES = 64
+TILE_NODES = 32
 TILE_HALO_MAX = 1024
 
 

@@ -65,11 +65,21 @@ def counter_per_dispatch(rows: list, kernel_substr: str, counter: str) -> list:
 GATHER_SOURCES = ("gather.hpp", "operators.hip", "common.hpp")
 
 
+def tile_nodes() -> int:
+    """LABFM_TILE_NODES as the public header defines it."""
+    import re
+
+    with open(os.path.join(ROOT, "include", "labfm.h")) as f:
+        return int(re.search(r"#define LABFM_TILE_NODES (\d+)", f.read()).group(1))
+
+
 def sources_hash(names=GATHER_SOURCES) -> str:
+    """Hash of the gather kernels' sources and of the tile size they run on."""
     h = hashlib.sha256()
     for name in names:
         with open(kernel_source(name), "rb") as f:
             h.update(f.read())
+    h.update(b"tile_nodes=%d" % tile_nodes())
     return h.hexdigest()[:16]
 
 
