@@ -2,9 +2,9 @@
 // the paper's LABFM section), as CSR with ascending j per row.
 //
 // Nodes are binned into a uniform cell grid whose cells are at least
-// 2 max(h) wide (a stable counting sort: count, scan, scatter, per-cell
-// ordering), so every neighbour of a node lies in the 3x3 block of cells
-// around it. A count pass sizes each row, a scan turns counts into row
+// 2 max(h) wide (cell counts and their scan give each cell's start; a stable
+// radix sort of the cell indices lists each cell's nodes in ascending order),
+// so every neighbour of a node lies in the 3x3 block of cells around it. A count pass sizes each row, a scan turns counts into row
 // offsets, and a fill pass walks the candidate cells as a k-way merge of
 // their (ascending) node lists so that each row comes out sorted without a
 // separate sort. The distance test rounds every product and sum separately
@@ -13,8 +13,10 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_reduce.hpp>
 #include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
 
 #include "common.hpp"
@@ -80,34 +82,6 @@ __global__ void bin_count_kernel(const double* __restrict__ x, const double* __r
   const int c = cy * g.ncx + cx;
   cell_of[i] = c;
   atomicAdd(&cell_count[c], 1);
-}
-
-__global__ void bin_scatter_kernel(const int* __restrict__ cell_of, int n,
-                                   const int* __restrict__ cell_start, int* __restrict__ cursor,
-                                   int* __restrict__ cell_nodes) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cell_of[i];
-  const int slot = atomicAdd(&cursor[c], 1);
-  cell_nodes[cell_start[c] + slot] = i;
-}
-
-// Orders each cell's node list ascending (insertion sort: cells hold a few
-// tens of nodes), which makes the binning a stable sort.
-__global__ void cell_sort_kernel(const int* __restrict__ cell_start, int ncell,
-                                 int* __restrict__ cell_nodes) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int b = cell_start[c], e = cell_start[c + 1];
-  for (int k = b + 1; k < e; ++k) {
-    const int v = cell_nodes[k];
-    int p = k - 1;
-    while (p >= b && cell_nodes[p] > v) {
-      cell_nodes[p + 1] = cell_nodes[p];
-      --p;
-    }
-    cell_nodes[p + 1] = v;
-  }
 }
 
 struct Candidates {
@@ -230,7 +204,12 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   LABFM_HIP(rocprim::exclusive_scan(nullptr, tb_scan, static_cast<const int*>(nullptr),
                                     static_cast<int*>(nullptr), 0, nscan, rocprim::plus<int>(),
                                     st));
-  size_t tbytes = std::max(tb_max, std::max(tb_sum, tb_scan));
+  size_t tb_sort = 0;
+  LABFM_HIP(rocprim::radix_sort_pairs(nullptr, tb_sort, static_cast<const int*>(nullptr),
+                                      static_cast<int*>(nullptr), rocprim::counting_iterator<int>(0),
+                                      static_cast<int*>(nullptr), static_cast<size_t>(n), 0u, 31u,
+                                      st));
+  size_t tbytes = std::max(std::max(tb_max, tb_sort), std::max(tb_sum, tb_scan));
   tbytes = (tbytes + 255) & ~static_cast<size_t>(255);
   Temp t_small;
   LABFM_HIP(hipMalloc(&t_small.p, 256 + tbytes));
@@ -267,13 +246,14 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   const int ncell = g.ncx * g.ncy;
 
   Temp t_big;
-  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 3 + 1 + 2 * (ncell + 1));
+  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 4 + 1 + 2 * (ncell + 1));
   LABFM_HIP(hipMalloc(&t_big.p, bytes));
   int* cell_of = static_cast<int*>(t_big.p);
   int* cell_nodes = cell_of + n;
   int* counts = cell_nodes + n;              // n + 1 (the last stays 0)
   int* cell_count = counts + n + 1;          // ncell + 1 (the last stays 0)
   int* cell_start = cell_count + ncell + 1;  // ncell + 1
+  int* sorted_cell = cell_start + ncell + 1;  // n (the radix sort's keys out)
 
   const int T = 256;
   LABFM_HIP(hipMemsetAsync(cell_count, 0, sizeof(int) * (ncell + 1), st));
@@ -282,13 +262,12 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   LABFM_LAUNCHED();
   LABFM_HIP(rocprim::exclusive_scan(d_temp, tbytes, cell_count, cell_start, 0,
                                     static_cast<size_t>(ncell) + 1, rocprim::plus<int>(), st));
-  LABFM_HIP(hipMemsetAsync(cell_count, 0, sizeof(int) * (ncell + 1), st));  // now cursors
-  hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, cell_of, n,
-                     cell_start, cell_count, cell_nodes);
-  LABFM_LAUNCHED();
-  hipLaunchKernelGGL(cell_sort_kernel, dim3(blocks_for(ncell, T)), dim3(T), 0, st, cell_start,
-                     ncell, cell_nodes);
-  LABFM_LAUNCHED();
+  // node indices ordered by cell, ascending within a cell (stable sort)
+  unsigned end_bit = 1;
+  while (end_bit < 31 && (1LL << end_bit) < ncell) ++end_bit;
+  LABFM_HIP(rocprim::radix_sort_pairs(d_temp, tbytes, static_cast<const int*>(cell_of), sorted_cell,
+                                      rocprim::counting_iterator<int>(0), cell_nodes,
+                                      static_cast<size_t>(n), 0u, end_bit, st));
   hipLaunchKernelGGL(count_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, h, n, g, cell_of,
                      cell_start, cell_nodes, counts);
   LABFM_LAUNCHED();
