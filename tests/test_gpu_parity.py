@@ -607,6 +607,30 @@ def test_every_launch_shape_agrees(dev, tg64, lpn, flags):
     assert rel(a, b) <= 1e-13
 
 
+@pytest.mark.parametrize("lpn", [4, 8, 16, 32])
+@pytest.mark.parametrize("flags", [0, 1, 3])
+def test_every_filter_shape_agrees(dev, tg64, lpn, flags):
+    """Each launch shape of the filter (tiled; with 4 lanes per node a pass
+    covers 64 nodes, more than a tile holds) gives one filtered RK step
+    equal, to rounding, to the default's."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    q0 = T(np.concatenate([l, u, v]), dev)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    ref = q0.clone()
+    labfm.rk_step(ref, ops, prm, dt, 1)
+    got = q0.clone()
+    try:
+        labfm.set_launch_config(labfm.KERNEL_FILTER, labfm.F64, lpn, flags)
+        labfm.rk_step(got, ops, prm, dt, 1)
+    finally:
+        labfm.set_launch_config(labfm.KERNEL_FILTER, labfm.F64, 0, 0)
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) <= 1e-13
+
+
 def test_tuner_installs_a_valid_shape(dev, tg64):
     from paper_2102_02019_amd import labfm
 
