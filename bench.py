@@ -17,7 +17,8 @@ roofline: the fused RK stage kernel, algorithmic bytes per launch
          on the current source;
 graph_replayed_steps: the same RK steps replayed from a HIP graph;
 build: stencil search and weight build of the workload (HIP events) and
-         the build's algorithmic FP64 FLOP/s against the FP64 peak;
+         the build's algorithmic FP64 FLOP/s against the FP64 peak and the
+         FP64 MFMA rate measured on the device (labfm_mfma_f64_rate);
 stream_copy: measured bandwidth of plain streaming kernels on 1 GiB (a
          device copy, read + write, and a read-only sum; best of 5 each), the
          measured ceiling the stage kernel's bandwidth is also compared with;
@@ -811,10 +812,13 @@ def build_rate(labfm, torch, np, nodes, x, y, h, s, m):
     K = np.diff(rp.cpu().numpy()).astype(np.float64)
     fl = float(np.sum(build_flops(nodes.m.astype(np.float64), K)))
     mode = labfm.get_build_config()
+    measured = labfm.mfma_f64_rate()
     return {"neighbours_ms": best[0], "weights_ms": best[1], "gflop": fl / 1e9,
             "achieved_TFLOPs": fl / (best[1] * 1e-3) / 1e12,
             "peak_TFLOPs": FP64_PEAK_TFLOPS,
             "frac": fl / (best[1] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "measured_mfma_f64_TFLOPs": measured,
+            "frac_of_measured_mfma": fl / (best[1] * 1e-3) / 1e12 / measured,
             "distribution": {1: "wavefront-per-node", 2: "workgroup-per-node",
                              3: "persistent", 4: "per-order-class"}.get(mode[0], str(mode[0]))}
 

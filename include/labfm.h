@@ -606,6 +606,26 @@ int labfm_lagrangian_step(double* x, double* y, double* q, const double* h, cons
                           void* workspace, size_t workspace_bytes,
                           labfm_lagrangian_stats* stats, void* stream);
 
+/*
+ * Measured FP64 matrix-core rate (a measurement aid, not part of the method):
+ * the rate that v_mfma_f64_16x16x4f64 reaches on this device with every SIMD
+ * fed four independent accumulators, the ceiling the weight build's assembly
+ * is compared with next to the data-sheet FP64 peak.
+ *
+ *   iters          MFMA rounds per wavefront (each four instructions of 2048
+ *                  flops); the grid is eight workgroups of four wavefronts
+ *                  per CU.
+ *   scratch        device buffer of at least
+ *                  labfm_mfma_f64_rate_scratch_bytes() bytes (the kernel's
+ *                  per-lane results, written and not read back).
+ *   tflops         host: receives the measured TFLOP/s.
+ * Runs the kernel twice (the second timed with HIP events on the stream) and
+ * synchronises. Returns LABFM_ERR_ARG for iters <= 0 or a short scratch.
+ */
+size_t labfm_mfma_f64_rate_scratch_bytes(void);
+int labfm_mfma_f64_rate(int32_t iters, double* scratch, size_t scratch_bytes, double* tflops,
+                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,7 @@ HIP_FLAGS = [
 # on the LU's critical path.
 FILE_FLAGS = {"weights.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
-           "boundaries.hip", "lagrangian.hip", "morton.hip"]
+           "boundaries.hip", "lagrangian.hip", "morton.hip", "probe.hip"]
 
 
 def _compile(src: str) -> str:

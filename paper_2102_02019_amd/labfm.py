@@ -113,6 +113,9 @@ _SIGNATURES = {
     "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
                                     ctypes.c_int, _P]),
     "labfm_tile_count": (ctypes.c_int32, [ctypes.c_int32]),
+    "labfm_mfma_f64_rate_scratch_bytes": (ctypes.c_size_t, []),
+    "labfm_mfma_f64_rate": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_size_t,
+                                           ctypes.POINTER(ctypes.c_double), _P]),
     "labfm_build_tiles": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
                                          ctypes.POINTER(ctypes.c_int32), _P]),
     "labfm_build_transpose": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, _P, _P, _P]),
@@ -539,6 +542,18 @@ class RKSolve(torch.autograd.Function):
         g0 = rk_adjoint(q0, qbar, ops, flow, dt, n_steps, ckpt_every, filter)
         rho0 = torch.exp(q0[:n])
         return (g0[:n] / rho0, g0[n:2 * n], g0[2 * n:], None, None, None, None, None, None)
+
+
+def mfma_f64_rate(iters: int = 4096, device=None) -> float:
+    """Measured FP64 MFMA rate of the device in TFLOP/s (a measurement aid:
+    the ceiling the weight build's assembly is compared with)."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    nbytes = int(lib().labfm_mfma_f64_rate_scratch_bytes())
+    scratch = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+    out = ctypes.c_double(0.0)
+    _check(lib().labfm_mfma_f64_rate(int(iters), _ptr(scratch), nbytes, ctypes.byref(out),
+                                     _stream()))
+    return float(out.value)
 
 
 def set_build_config(mode: int = 0, workgroups_per_cu: int = 0) -> None:
