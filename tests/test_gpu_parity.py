@@ -215,6 +215,26 @@ def test_weights_mixed_orders(dev):
     _check_weights(nodes, ops, W, sample)
 
 
+def test_weights_orders_1_3_7_9(dev):
+    """Orders 1, 3, 7 and 9 (n = 2, 9, 35, 54: the smallest system, and odd
+    and even n for the paired column elimination) in one launch; order 1 has
+    no filter operator, so its nodes carry the bad-filter status with the
+    oracle's."""
+    nodes = inputs.jittered_lattice(36, seed=11, m=8)
+    rng = np.random.default_rng(17)
+    nodes.m = rng.choice(np.array([1, 3, 7, 9], dtype=np.int8), nodes.n)
+    nodes.h = np.where(nodes.m >= 7, 3.0, 2.2) * nodes.s
+    ops = gpu_setup(nodes, dev)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    sample = list(range(0, nodes.n, 23))
+    W = O.weights(nodes.x, nodes.y, nodes.h, nodes.s, nodes.m, rp, col, nodes.box, nodes=sample)
+    W.update(row_ptr=rp, col=col)
+    _check_weights(nodes, ops, W, sample)
+    st = ops.status.cpu().numpy()
+    for i in sample:
+        assert st[i] == W["status"][i]
+
+
 def test_weights_degenerate_nodes(dev):
     """Orders outside 1..10 and nodes with too few neighbours get a status."""
     nodes = inputs.jittered_lattice(16, seed=4, m=4)
