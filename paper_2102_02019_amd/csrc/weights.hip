@@ -57,7 +57,8 @@ struct Shape {
   static constexpr int NB = (NMAX + 15) / 16;   // 16-wide MFMA tiles per side
   static constexpr int LDA = (NMAX + 6) | 1;     // row stride of [M | C] (odd)
   static constexpr int TW = MMAX + 1;            // one basis table's length
-  static constexpr int TABLE = 4 * TW;           // four tables per neighbour
+  static constexpr int TABLE = 4 * TW + 1;       // four tables per neighbour and a zero
+  static constexpr int ZERO = 4 * TW;            // the zero entry of a neighbour's tables
   static constexpr int HW = 2 * TW + 1;          // per-lane Hermite row (odd)
 };
 
@@ -543,12 +544,15 @@ __device__ void assemble_system(const BuildArgs& g, int i, int m, int n, int e0,
   const double xi = g.x[i], yi = g.y[i];
   const int px = g.box.periodic_x, py = g.box.periodic_y;
   for (int p = tid; p < n; p += kBlock) exponents_of(p, sm.qa[p], sm.qb[p]);
+  // the zero entries (operands of moment indices beyond n); the tables
+  // written below stop short of them
+  for (int k = tid; k < kChunk; k += kBlock) sm.T()[k * S::TABLE + S::ZERO] = 0.0;
   lds_barrier();
 
   // ---- basis tables and MFMA assembly --------------------------------------
   int tP[TPW], tQ[TPW];
   // LDS offsets of this lane's A and B operands in a neighbour's tables
-  // (-1: moment index beyond n, operand 0)
+  // (the zero entry for a moment index beyond n: the operand is 0 * 0)
   int oa[TPW], ob[TPW], oc[TPW], od[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
@@ -558,10 +562,10 @@ __device__ void assemble_system(const BuildArgs& g, int i, int m, int n, int e0,
     const int p = tP[k] * 16 + (lane & 15);
     const int q = tQ[k] * 16 + (lane & 15);
     const bool pok = tP[k] >= 0 && p < n, qok = tQ[k] >= 0 && q < n;
-    oa[k] = pok ? sm.qa[p] : -1;
-    ob[k] = pok ? S::TW + sm.qb[p] : -1;
-    oc[k] = qok ? 2 * S::TW + sm.qa[q] : -1;
-    od[k] = qok ? 3 * S::TW + sm.qb[q] : -1;
+    oa[k] = pok ? sm.qa[p] : S::ZERO;
+    ob[k] = pok ? S::TW + sm.qb[p] : S::ZERO;
+    oc[k] = qok ? 2 * S::TW + sm.qa[q] : S::ZERO;
+    od[k] = qok ? 3 * S::TW + sm.qb[q] : S::ZERO;
   }
   const double hinv = 1.0 / h;
   double4_t acc[TPW];
@@ -617,8 +621,8 @@ __device__ void assemble_system(const BuildArgs& g, int i, int m, int n, int e0,
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
         if (tP[k] >= 0) {  // wave-uniform
-          const double av = (oa[k] >= 0) ? tk[oa[k]] * tk[ob[k]] : 0.0;
-          const double bv = (oc[k] >= 0) ? tk[oc[k]] * tk[od[k]] : 0.0;
+          const double av = tk[oa[k]] * tk[ob[k]];
+          const double bv = tk[oc[k]] * tk[od[k]];
           acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
         }
       }
