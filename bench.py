@@ -877,7 +877,20 @@ def cpu_baseline_all_cores(wl, rk_steps, N_full):
         "sample": (f"{cores} processes x {n_tot // cores} nodes (64x64, m={wl.m}), stencils + "
                    f"weights and {k} RK steps each, {wall:.1f} s wall; scaled per node to "
                    f"{N_full} nodes and {rk_steps} steps"),
+        "cpu_model": cpu_model(),
     }
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU baselines."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(wl, rk_steps, N_full):
@@ -914,6 +927,7 @@ def cpu_baseline(wl, rk_steps, N_full):
                    f"{k} RK steps {t2 - t1:.1f} s; scaled per node to {N_full} nodes "
                    f"and {rk_steps} steps"),
         "rk_stage_only_node_updates_per_s": 4 * n * k / (t2 - t1),
+        "cpu_model": cpu_model(),
     }
 
 
