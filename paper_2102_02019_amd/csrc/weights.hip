@@ -453,6 +453,7 @@ struct BlockSmem {
   double psi[S::NMAX * LABFM_NUM_OPS];  // the solution, copied out of A
   int qa[S::NMAX], qb[S::NMAX];
   unsigned long long key[3];  // pivot keys of three consecutive columns
+  double rinv;                 // 1 / pivot of the pair's first column (LU)
   int next;
   __device__ double* T() { return A; }
   __device__ double* part() { return A + kChunk * S::TABLE; }
@@ -733,23 +734,26 @@ __device__ bool factor_solve(int n, BlockSmem<MMAX>& sm, int tid) {
       }
       lds_barrier();
     }
-    const double inv0 = 1.0 / sm.A[c * S::LDA + c];
     if (c + 1 == n) {  // last column alone: nothing below it
       staged = -1;
       lds_barrier();
       break;
     }
-    // ---- A: column c+1 (rows c+1..n-1, at most 64: one per lane of wave 0)
-    {
+    // ---- A: column c+1 (rows c+1..n-1, at most 64: one per lane of wave 0);
+    // wavefront 0 also forms 1 / pivot for the other wavefronts
+    if (tid < 64) {
+      const double inv = 1.0 / sm.A[c * S::LDA + c];
+      if (tid == 0) sm.rinv = inv;
       const int r = c + 1 + tid;
       if (r < n) {
-        const double v = fma(-(sm.A[r * S::LDA + c] * inv0), sm.A[c * S::LDA + c + 1],
+        const double v = fma(-(sm.A[r * S::LDA + c] * inv), sm.A[c * S::LDA + c + 1],
                              sm.A[r * S::LDA + c + 1]);
         sm.A[r * S::LDA + c + 1] = v;
         atomicMax(&sm.key[(c + 1) % 3], pivot_key(v, r));
       }
     }
     lds_barrier();
+    const double inv0 = sm.rinv;
     // ---- B: pivot of column c+1, then both steps on the rest
     const int c1 = c + 1;
     const unsigned long long kc1 = uniform64(sm.key[c1 % 3]);
