@@ -47,8 +47,6 @@ import math
 
 import numpy as np
 
-from paper_2102_02019_amd.inputs import poiseuille_startup  # noqa: F401  (reference field)
-
 from . import labfm_oracle as O
 
 STRIP_DEPTH = 5
@@ -294,3 +292,30 @@ def poiseuille_steps(nodes, prm, flow, t_star: float, conv_coef: float = 1.0,
     t_end = prm.time(t_star)
     n_steps = max(1, int(math.ceil(t_end / dt_max - 1e-9)))
     return t_end / n_steps, n_steps
+
+
+# ---------------------------------------------------------------------------
+# Section "Poiseuille flow": the analytic start-up solution
+# ---------------------------------------------------------------------------
+
+def poiseuille_startup(y, t: float, H: float, nu: float, g: float,
+                       n_modes: int = 400) -> np.ndarray:
+    """u(y, t) of the flow between no-slip walls at y = 0 and y = H driven
+    from rest by a uniform body force g: the solution of u_t = nu u_yy + g
+    with u(0, t) = u(H, t) = 0 and u(y, 0) = 0 (uniform density, so the
+    isothermal equations reduce to this diffusion problem).
+
+    Separation of variables: the steady state is the parabola
+    U(y) = g y (H - y) / (2 nu); the transient U - u solves the homogeneous
+    heat equation with initial value U, whose sine coefficients on (0, H),
+    (2/H) int_0^H U sin(k pi y/H) dy, are 4 g H^2 / (nu pi^3 k^3) for odd k
+    (zero for even k), each decaying as exp(-nu (k pi / H)^2 t). The first n_modes odd modes are kept."""
+    y = np.asarray(y, dtype=np.float64)
+    steady = g / (2.0 * nu) * y * (H - y)
+    transient = np.zeros_like(y)
+    for j in range(n_modes):
+        k = 2.0 * j + 1.0
+        lam = nu * (k * math.pi / H) ** 2
+        coef = 4.0 * g * H * H / (nu * math.pi ** 3 * k ** 3)
+        transient += coef * math.exp(-lam * t) * np.sin(k * math.pi * y / H)
+    return steady - transient

@@ -284,17 +284,20 @@ def node_weights(dx: np.ndarray, dy: np.ndarray, h: float, s: float, m: int) -> 
     return {"w": w, "kappa": kappa, "status": status, "M": M, "C": C, "Psi": Psi}
 
 
-def filter_coefficient(dx, dy, s: float, w_hyp: np.ndarray) -> tuple:
+def filter_coefficient(dx, dy, s: float, w_hyp: np.ndarray, k: float = None) -> tuple:
     """F_0 = sum_j [1 - cos(k x_ji) cos(k y_ji)] w^hyp_ji and kappa = 2/(3 F_0),
     so that the filter leaves 1/3 of that mode, with k two-thirds of the
-    Nyquist wavenumber pi/s, i.e. k = 2 pi / (3 s).
+    Nyquist wavenumber pi/s, i.e. k = 2 pi / (3 s) (the default).
 
     The paper's printed phase 3 pi x / (2 s) is 1.5 times the Nyquist
-    wavenumber; on a near-lattice it aliases to a low wavenumber, F_0 gets
-    small at some nodes and the filter then amplifies the highest modes. Its
-    text also names "two-thirds the Nyquist wavenumber", which is the reading
-    taken here."""
-    a = 2.0 * math.pi / (3.0 * s)
+    wavenumber (the wavelength 4s/3, two-thirds of the Nyquist wavelength 2s,
+    which is what the sentence after the kappa equation names); on a
+    near-lattice it aliases to a low wavenumber, F_0 gets small or changes
+    sign at some nodes and the filter then amplifies instead of damping. The
+    next paragraph names "two-thirds the Nyquist wavenumber", which is the
+    reading taken here. ``k`` overrides the wavenumber (the tests use it to
+    show what the printed phase does)."""
+    a = 2.0 * math.pi / (3.0 * s) if k is None else float(k)
     phi = 1.0 - np.cos(a * dx) * np.cos(a * dy)
     F0 = float(np.sum(phi * w_hyp))
     if not np.isfinite(F0) or F0 == 0.0:

@@ -61,3 +61,23 @@ def test_argument_errors_return_codes_without_gpu(lib):
     assert code == labfm.ERR_ARG
     assert lib.labfm_rk_workspace_bytes(0) == 0
     assert lib.labfm_rk_workspace_bytes(1000) >= 6 * 1000 * 8
+
+
+def test_oracle_and_product_are_separate():
+    """The oracle imports nothing from the product package, and the product
+    package (Python binding and sources) neither imports nor loads anything
+    under oracle/."""
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if f.endswith(".py"):
+            text = open(os.path.join(odir, f)).read()
+            assert "paper_2102_02019_amd" not in text, f
+    pdir = os.path.join(ROOT, "paper_2102_02019_amd")
+    for base, _, files in os.walk(pdir):
+        if "_build" in base or "__pycache__" in base:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".c", ".h")):
+                text = open(os.path.join(base, f)).read()
+                assert not re.search(r"(import\s+oracle|from\s+oracle|oracle/|oracle\.)", text), \
+                    os.path.join(base, f)

@@ -217,6 +217,16 @@ def test_startup_solution_solves_its_problem():
     assert abs(u(np.array([0.5]), 1e-3)[0] - g * 1e-3) < 1e-6
 
 
+def test_startup_series_agrees_with_the_benchmark_copy():
+    """The benchmark keeps its own coding of the same series (the product
+    package never calls the oracle); the two agree to rounding."""
+    y = np.linspace(0.0, 1.0, 41)
+    for t in (0.0, 0.05, 1.0, 30.0):
+        a = B.poiseuille_startup(y, t, 1.0, 0.1, 0.8)
+        b = inputs.poiseuille_startup(y, t, 1.0, 0.1, 0.8)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * 0.8 / (8 * 0.1))
+
+
 @pytest.mark.slow
 def test_poiseuille_converges_at_fourth_order():
     """Start-up to t* = 1 at Re = 10, Ma = 0.05 (the paper's case): the

@@ -250,3 +250,107 @@ def test_filtered_run_is_stable_and_decays(m):
     with np.errstate(all="ignore"):
         l2, u2, v2 = O.rk_run(np.log(rho), u, v, W, prm, dt, n, filt=False)
     assert not np.all(np.abs(u2) < 2.0)
+
+
+# ------------------------------------- filter calibration wavenumber (pin)
+
+def _kappa_at(nodes, W, k_of_s):
+    """kappa_i of the oracle's calibration rule at wavenumber k_of_s(s_i)."""
+    rp, col = W["row_ptr"], W["col"]
+    out = np.empty(nodes.n)
+    for i in range(nodes.n):
+        dx, dy = O.stencil_offsets(nodes.x, nodes.y, nodes.box, rp, col, i)
+        s = float(nodes.s[i])
+        out[i], _ = O.filter_coefficient(dx, dy, s, W["w"][O.OP_HYP, rp[i]:rp[i + 1]],
+                                         k=k_of_s(s))
+    return out
+
+
+def _peak_history(nodes, W, kappa, n_steps):
+    """Peak |u| after each filtered Taylor-Green step, stopping at the first
+    step where it exceeds 2 (the initial peak is 1) or stops being finite."""
+    prm = inputs.taylor_green_params()
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    dt = O.time_step(nodes.s, np.log(rho), u, v, prm)
+    Wk = dict(W, kappa=kappa)
+    q = (np.log(rho), u, v)
+    peaks = []
+    with np.errstate(all="ignore"):
+        for _ in range(n_steps):
+            q = O.rk_run(*q, Wk, prm, dt, 1)
+            peaks.append(float(np.max(np.abs(q[1]))))
+            if not np.isfinite(peaks[-1]) or peaks[-1] > 2.0:
+                break
+    return peaks, prm, dt
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m,nside,seed", [(4, 32, 4), (6, 32, 4), (8, 32, 4), (4, 64, 1)])
+def test_calibration_wavenumber_reading(m, nside, seed):
+    """Section "Spatial filtering" prints the calibration mode with phase
+    3 pi x/(2s) (wavenumber 1.5 k_Ny, wavelength two-thirds of the Nyquist
+    wavelength), and its next paragraph names two-thirds of the Nyquist
+    wavenumber (2 pi/(3s)). On jittered lattices (the 64^2 case is the small
+    Taylor-Green workload) the two readings differ qualitatively:
+
+    * 2 pi/(3s): kappa has the damping sign (-1)^(m/2+1) at every node and
+      varies by less than 2x about its median; the filtered run stays bounded
+      for 100 steps and its peak velocity follows exp(-2 mu t) within 3%.
+    * 3 pi/(2s): the mode lies above Nyquist and aliases, F_0 nearly vanishes
+      at some nodes, kappa spreads by more than 20x (and changes sign at some
+      nodes for m >= 6) and the filtered run diverges within 20 steps.
+
+    This is what fixes the oracle's reading (and the kernel's)."""
+    nodes, W = _setup(nside, m, seed=seed)
+    damp = (-1) ** (m // 2 + 1)
+    k_read = _kappa_at(nodes, W, lambda s: 2.0 * math.pi / (3.0 * s))
+    k_print = _kappa_at(nodes, W, lambda s: 3.0 * math.pi / (2.0 * s))
+    # the oracle's own kappa is the 2 pi/(3s) one
+    np.testing.assert_allclose(k_read, W["kappa"], rtol=1e-12)
+
+    med = np.median(np.abs(k_read))
+    assert np.all(np.sign(k_read) == damp)
+    assert np.abs(k_read).max() / med < 2.0 and np.abs(k_read).min() / med > 0.5
+    spread_p = np.abs(k_print).max() / np.median(np.abs(k_print))
+    flips = int(np.sum(np.sign(k_print) != damp))
+    assert spread_p > 20.0, spread_p
+    if m >= 6:
+        assert flips > 0
+
+    peaks, prm, dt = _peak_history(nodes, W, k_read, 100)
+    assert len(peaks) == 100 and np.all(np.isfinite(peaks))
+    assert peaks[-1] == pytest.approx(math.exp(-2 * prm.mu * dt * 100), rel=0.03)
+    peaks_p, _, _ = _peak_history(nodes, W, k_print, 20)
+    assert len(peaks_p) < 20 and not (peaks_p[-1] <= 2.0), peaks_p
+
+
+# ----------------------------------------- per-node right-hand side (pin)
+
+def test_rhs_at_nodes_equals_full_rhs():
+    """ns_rhs_at (each sampled node from its own freshly built weights, with
+    numpy's pairwise sums) equals ns_rhs (all nodes' weights, sums in
+    ascending j) at sampled nodes, for a state with density variation and a
+    body force: the two are separate codings of eq. icns that agree to
+    rounding."""
+    nodes, W = _setup(32, 6, seed=2)
+    prm = inputs.FlowParams(c2=100.0, mu=math.pi / 100, gx=0.3, gy=-0.1)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    l = np.log(rho) + 0.05 * np.sin(nodes.x + 2 * nodes.y)
+    full = np.array(O.ns_rhs(l, u, v, W, prm))
+    sample = list(range(3, nodes.n, 17))
+    rp, col = O.neighbours_rows(nodes.x, nodes.y, nodes.h, nodes.box, sample)
+    at = O.ns_rhs_at(l, u, v, nodes.x, nodes.y, nodes.h, nodes.s, 6, rp, col, nodes.box, prm,
+                     sample)
+    # R_l of the divergence-free Taylor-Green velocity is a cancellation
+    # (u_x + v_y ~ 0), so it is measured against the size of its terms
+    A = lambda d, f: O.apply_op(W["row_ptr"], W["col"], W["w"][d], f)[sample]  # noqa: E731
+    terms_l = (np.abs(u[sample] * A(O.OP_X, l)) + np.abs(v[sample] * A(O.OP_Y, l))
+               + np.abs(A(O.OP_X, u)) + np.abs(A(O.OP_Y, v)))
+    assert np.linalg.norm(at[0] - full[0, sample]) <= 1e-13 * np.linalg.norm(terms_l)
+    for k in (1, 2):
+        ref = full[k, sample]
+        assert np.linalg.norm(at[k] - ref) <= 1e-13 * np.linalg.norm(ref), k
+    # and the sampled rows of the stencil search equal the full search's
+    rp_f, col_f = W["row_ptr"], W["col"]
+    for i in sample:
+        assert np.array_equal(col[rp[i]:rp[i + 1]], col_f[rp_f[i]:rp_f[i + 1]])
