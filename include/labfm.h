@@ -584,11 +584,13 @@ int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_rk_params* 
  *   prm           c2, mu, gx, gy, dt, filter, check_finite.
  *   nnz_capacity  largest stencil count the workspace holds.
  *   workspace     labfm_lagrangian_workspace_bytes(n, nnz_capacity) bytes:
- *                 three 5n-double registers, the CSR and the weights.
+ *                 three 5n-double registers, the CSR, the weights and the
+ *                 status counters.
  *   stats         host, optional.
  * Synchronises (every build does). Returns LABFM_ERR_CAPACITY when a stencil
  * build needs more than nnz_capacity entries; x, y and q then hold the last
- * completed step (stats->steps_done).
+ * completed step (stats->steps_done), and stats->node_status counts the
+ * builds done before the failure.
  */
 typedef struct {
   int32_t steps_done;  /* completed steps */
@@ -596,6 +598,15 @@ typedef struct {
   int64_t max_nnz;     /* largest stencil count built */
   double build_ms;     /* host wall-clock time in the builds (they synchronise) */
   double stage_ms;     /* stage and filter kernels (HIP events on the stream) */
+  int64_t node_status[5]; /* node builds per LABFM_NODE_* status, summed over
+                             the call's builds (counted on the device after
+                             each build). Nodes that cluster or thin out as
+                             they move can reach LABFM_NODE_SINGULAR,
+                             _FEW_NEIGHBOURS or _BAD_FILTER: their weights and
+                             kappa are then zero for that stage, so their
+                             fields do not change there. A caller checks
+                             node_status[1..4]; the call itself still
+                             returns LABFM_OK. */
 } labfm_lagrangian_stats;
 
 size_t labfm_lagrangian_workspace_bytes(int32_t n, int64_t nnz_capacity);

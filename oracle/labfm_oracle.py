@@ -336,11 +336,14 @@ def weights(x, y, h, s, m, row_ptr, col, box, nodes=None) -> dict:
     return {"w": w, "kappa": kappa, "rowsum": rowsum, "status": status}
 
 
-def weights_batched(x, y, h, s, m: int, row_ptr, col, box, chunk: int = 4096) -> dict:
+def weights_batched(x, y, h, s, m: int, row_ptr, col, box, chunk: int = 4096,
+                    start: int = 0, stop: int = None) -> dict:
     """Same steps as ``weights`` for a uniform order m, run over a stack of
     nodes at once. Rows are padded to the longest row of the stack and padded
-    entries are masked out of every sum."""
+    entries are masked out of every sum. Only nodes start..stop-1 are built
+    (all by default); the entries of the others are left unset."""
     N = x.size
+    stop = N if stop is None else stop
     nnz = int(row_ptr[-1])
     n = n_moments(m)
     K = np.diff(row_ptr)
@@ -348,8 +351,8 @@ def weights_batched(x, y, h, s, m: int, row_ptr, col, box, chunk: int = 4096) ->
     kappa = np.empty(N)
     rowsum = np.empty((6, N))
     status = np.zeros(N, dtype=np.int8)
-    for lo in range(0, N, chunk):
-        hi = min(N, lo + chunk)
+    for lo in range(start, stop, chunk):
+        hi = min(stop, lo + chunk)
         Kmax = int(K[lo:hi].max()) if hi > lo else 0
         B = hi - lo
         idx = np.arange(Kmax)[None, :]

@@ -16,6 +16,7 @@
 //   filter:  weights at Ya's positions; Ya -> Q
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -23,6 +24,8 @@
 
 namespace labfm {
 namespace {
+
+constexpr int kStatusKinds = 5;  // LABFM_NODE_OK .. LABFM_NODE_BAD_ORDER
 
 struct Reg {
   double* x;
@@ -124,11 +127,27 @@ hipError_t launch_lagr_stage(int lpn, const int* row_ptr, const int* col, const 
   return hipGetLastError();
 }
 
+// Adds the per-node statuses of one build to counts[LABFM_NODE_*] (statuses
+// outside 0..4 are not written by the build).
+__global__ void __launch_bounds__(256)
+count_status_kernel(const int8_t* __restrict__ status, int n, unsigned long long* counts) {
+  __shared__ unsigned int c[kStatusKinds];
+  if (threadIdx.x < kStatusKinds) c[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int v = status[i];
+    if (v >= 0 && v < kStatusKinds) atomicAdd(&c[v], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatusKinds && c[threadIdx.x] != 0u)
+    atomicAdd(&counts[threadIdx.x], static_cast<unsigned long long>(c[threadIdx.x]));
+}
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t reg, rowptr, col, w, kappa, status, total;
+  size_t reg, rowptr, col, w, kappa, status, counts, total;
 };
 
 Layout layout_of(int32_t n, int64_t cap) {
@@ -139,7 +158,8 @@ Layout layout_of(int32_t n, int64_t cap) {
   L.w = align_up(sizeof(double) * 6 * static_cast<size_t>(cap));
   L.kappa = align_up(sizeof(double) * static_cast<size_t>(n));
   L.status = align_up(static_cast<size_t>(n));
-  L.total = 3 * L.reg + L.rowptr + L.col + L.w + L.kappa + L.status;
+  L.counts = align_up(sizeof(unsigned long long) * kStatusKinds);
+  L.total = 3 * L.reg + L.rowptr + L.col + L.w + L.kappa + L.status + L.counts;
   return L;
 }
 
@@ -190,6 +210,11 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
   double* kappa = reinterpret_cast<double*>(base + off);
   off += L.kappa;
   int8_t* status = reinterpret_cast<int8_t*>(base + off);
+  off += L.status;
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(base + off);
+  LABFM_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned long long) * kStatusKinds, st));
+  const unsigned count_grid =
+      static_cast<unsigned>(std::min<long long>(1024, (static_cast<long long>(n) + 255) / 256));
 
   labfm_lagrangian_stats local{};
   labfm_lagrangian_stats& sx = stats ? *stats : local;
@@ -211,11 +236,27 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
     r = labfm_build_weights(R.x, R.y, h, s, order_m, n, box, row_ptr, col, nnz, w, nullptr,
                             nullptr, kappa, nullptr, status, stream_);
     if (r != LABFM_OK) return r;
+    hipLaunchKernelGGL(count_status_kernel, dim3(count_grid), dim3(256), 0, st, status, n,
+                       counts);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("lagrangian_step: status count launch failed");
+      return LABFM_ERR_HIP;
+    }
     const auto t1 = std::chrono::steady_clock::now();
     sx.builds += 1;
     sx.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (got > sx.max_nnz) sx.max_nnz = got;
     return LABFM_OK;
+  };
+  // node builds per status, summed over the call's builds, into the stats
+  auto read_counts = [&]() -> hipError_t {
+    unsigned long long hc[kStatusKinds];
+    const hipError_t e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (e2 != hipSuccess) return e2;
+    for (int k = 0; k < kStatusKinds; ++k) sx.node_status[k] = static_cast<int64_t>(hc[k]);
+    return hipSuccess;
   };
   hipEvent_t ev[2];
   LABFM_HIP(hipEventCreate(&ev[0]));
@@ -251,42 +292,50 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
   const Reg Qin[4] = {Q, Ya, Ya, Ya};
   const Reg Yo[4] = {Yb, Yc, Yb, none};
   const size_t field_bytes = sizeof(double) * static_cast<size_t>(n);
-  if (n_steps > 0) {
-    if (int r = build(Q)) return r;
-  }
-  for (int step = 0; step < n_steps; ++step) {
-    for (int k = 0; k < 4; ++k) {
-      if (k > 0) {
-        if (int r = build(G[k])) return r;
+  // the steps; every early exit (a capacity error) still reports the
+  // statuses of the builds done so far
+  auto advance = [&]() -> int {
+    if (n_steps > 0) {
+      if (int r = build(Q)) return r;
+    }
+    for (int step = 0; step < n_steps; ++step) {
+      for (int k = 0; k < 4; ++k) {
+        if (k > 0) {
+          if (int r = build(G[k])) return r;
+        }
+        const double K = static_cast<double>(nnz) / n;
+        const int lpn = K > 48.0 ? 16 : (K > 12.0 ? 8 : 4);
+        const double dta = (k < 3) ? dt * kA[k] : 0.0;
+        LABFM_HIP(timed([&] {
+          return launch_lagr_stage(lpn, row_ptr, col, w, nnz, G[k], Qin[k], Ya, Yo[k], dta,
+                                   dt * kB[k], fl, box.Lx, box.Ly, n, st);
+        }));
       }
-      const double K = static_cast<double>(nnz) / n;
-      const int lpn = K > 48.0 ? 16 : (K > 12.0 ? 8 : 4);
-      const double dta = (k < 3) ? dt * kA[k] : 0.0;
-      LABFM_HIP(timed([&] {
-        return launch_lagr_stage(lpn, row_ptr, col, w, nnz, G[k], Qin[k], Ya, Yo[k], dta,
-                                 dt * kB[k], fl, box.Lx, box.Ly, n, st);
-      }));
+      // weights at the new positions: the filter's, and the next first stage's
+      if (int r = build(Ya)) return r;
+      LABFM_HIP(hipMemcpyAsync(Q.x, Ya.x, field_bytes, hipMemcpyDeviceToDevice, st));
+      LABFM_HIP(hipMemcpyAsync(Q.y, Ya.y, field_bytes, hipMemcpyDeviceToDevice, st));
+      if (prm->filter) {
+        labfm_operators ops{};
+        ops.n = n;
+        ops.nnz = nnz;
+        ops.row_ptr = row_ptr;
+        ops.col = col;
+        ops.w = w;
+        ops.kappa = kappa;
+        const LaunchCfg fc = cfg_for(LABFM_KERNEL_FILTER, LABFM_F64, n, nnz);
+        LABFM_HIP(timed([&] { return launch_filter<F64>(fc, &ops, w, Ya.f, Q.f, st); }));
+      } else {
+        LABFM_HIP(hipMemcpyAsync(Q.f, Ya.f, 3 * field_bytes, hipMemcpyDeviceToDevice, st));
+      }
+      sx.steps_done = step + 1;
     }
-    // weights at the new positions: the filter's, and the next first stage's
-    if (int r = build(Ya)) return r;
-    LABFM_HIP(hipMemcpyAsync(Q.x, Ya.x, field_bytes, hipMemcpyDeviceToDevice, st));
-    LABFM_HIP(hipMemcpyAsync(Q.y, Ya.y, field_bytes, hipMemcpyDeviceToDevice, st));
-    if (prm->filter) {
-      labfm_operators ops{};
-      ops.n = n;
-      ops.nnz = nnz;
-      ops.row_ptr = row_ptr;
-      ops.col = col;
-      ops.w = w;
-      ops.kappa = kappa;
-      const LaunchCfg fc = cfg_for(LABFM_KERNEL_FILTER, LABFM_F64, n, nnz);
-      LABFM_HIP(timed([&] { return launch_filter<F64>(fc, &ops, w, Ya.f, Q.f, st); }));
-    } else {
-      LABFM_HIP(hipMemcpyAsync(Q.f, Ya.f, 3 * field_bytes, hipMemcpyDeviceToDevice, st));
-    }
-    sx.steps_done = step + 1;
-  }
-  LABFM_HIP(hipStreamSynchronize(st));
+    return LABFM_OK;
+  };
+  const int adv = advance();
+  const hipError_t cerr = read_counts();
+  if (adv != LABFM_OK) return adv;
+  LABFM_HIP(cerr);
   if (n_steps > 0 && prm->check_finite) {
     std::vector<double> hq(3 * static_cast<size_t>(n));
     LABFM_HIP(hipMemcpy(hq.data(), q, 3 * field_bytes, hipMemcpyDeviceToHost));

@@ -36,6 +36,17 @@ class LabfmError(RuntimeError):
         self.code = code
 
 
+class NodeStatusError(RuntimeError):
+    """Weight builds left nodes with a failure status (LABFM_NODE_SINGULAR,
+    _FEW_NEIGHBOURS, _BAD_FILTER or _BAD_ORDER); ``counts`` holds the node
+    builds per status, LABFM_NODE_OK first."""
+
+    def __init__(self, counts):
+        super().__init__("node builds with a failure status (singular, few neighbours, "
+                         f"bad filter, bad order): {list(counts[1:])}")
+        self.counts = list(counts)
+
+
 class _Box(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
                 ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32)]
@@ -58,7 +69,7 @@ class _Operators(ctypes.Structure):
 class _LagrangianStats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int32), ("builds", ctypes.c_int64),
                 ("max_nnz", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("stage_ms", ctypes.c_double)]
+                ("stage_ms", ctypes.c_double), ("node_status", ctypes.c_int64 * 5)]
 
 
 class _Strips(ctypes.Structure):
@@ -334,11 +345,14 @@ def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
 def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, box, flow,
                     dt: float, n_steps: int, filter: bool = True, check_finite: bool = False,
                     nnz_capacity: Optional[int] = None,
-                    workspace: Optional[torch.Tensor] = None) -> dict:
+                    workspace: Optional[torch.Tensor] = None, strict: bool = False) -> dict:
     """Advance positions (x, y) and q = [ln rho | u | v] in place by n_steps
     Lagrangian RK steps (labfm_lagrangian_step). The stencil capacity
     defaults to 1.5 times the current stencil count (queried from
-    labfm_build_neighbours). Returns the call's statistics."""
+    labfm_build_neighbours). Returns the call's statistics, with
+    ``node_status`` the node builds per LABFM_NODE_* status; with
+    ``strict`` a build that left any node with a failure status raises
+    LabfmError after the call."""
     n = x.numel()
     dev = x.device
     if not torch.is_tensor(m):
@@ -361,8 +375,13 @@ def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, 
                                        _box(box), ctypes.byref(prm), int(n_steps),
                                        int(nnz_capacity), _ptr(workspace), workspace.numel(),
                                        ctypes.byref(st), _stream()))
-    return {"steps_done": st.steps_done, "builds": st.builds, "max_nnz": st.max_nnz,
-            "build_ms": st.build_ms, "stage_ms": st.stage_ms, "nnz_capacity": nnz_capacity}
+    status = [int(v) for v in st.node_status]
+    out = {"steps_done": st.steps_done, "builds": st.builds, "max_nnz": st.max_nnz,
+           "build_ms": st.build_ms, "stage_ms": st.stage_ms, "nnz_capacity": nnz_capacity,
+           "node_status": status}
+    if strict and sum(status[1:]) > 0:
+        raise NodeStatusError(status)
+    return out
 
 
 TILE_NODES = 32

@@ -22,3 +22,9 @@ def square_wave(x, y, H=1.0, terms=8):
         py += c * ky * cy * sx
         lap -= c * sy * sx * (kx * kx + ky * ky)
     return phi, px, py, lap
+
+
+def smooth_fields(x, y):
+    """Two smooth periodic fields on [0, 2 pi)^2 for operator parity tests."""
+    return {"sin_cos": np.sin(x) * np.cos(2 * y),
+            "mixed": np.cos(3 * x + y) + 0.3 * np.sin(x - 2 * y) + 2.0}

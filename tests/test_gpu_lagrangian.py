@@ -73,6 +73,7 @@ def test_lagrangian_taylor_green_matches_oracle(dev, filt):
     assert pos <= 1e-12, pos
     assert max(fields) <= 1e-11, fields
     assert st["steps_done"] == 4 and st["builds"] == 17
+    assert st["node_status"] == [17 * nodes.n, 0, 0, 0, 0]
     # the nodes did move: by about |u| dt per step
     disp = np.hypot(O.min_image(x - nodes.x, nodes.box.Lx, True),
                     O.min_image(y - nodes.y, nodes.box.Ly, True))
@@ -155,3 +156,33 @@ def test_lagrangian_taylor_green_256(dev):
     print("lagrangian 256^2 errors", e_lag, "eulerian", e_eul, st)
     assert e_lag < 2.0 * e_eul + 1e-7, (e_lag, e_eul)
     assert st["builds"] == 4 * steps + 1
+
+
+def test_lagrangian_reports_starved_stencils(dev):
+    """A node whose stencil holds no neighbour (h = 0.01 s; the jittered
+    lattice keeps other nodes at least 0.4 s away, and two steps move them by
+    far less) has a zero moment matrix: every build marks it singular and
+    gives it zero weights and kappa. The call still completes, counts the
+    failure once per build in node_status, and raises with strict=True; the
+    node's fields hold (its material rates are zero) while it moves."""
+    from paper_2102_02019_amd import labfm
+
+    nodes = inputs.jittered_lattice(16, seed=4, m=4)
+    nodes.h = nodes.h.copy()
+    starved = 7
+    nodes.h[starved] = 0.01 * nodes.s[starved]
+    prm = inputs.taylor_green_params()
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    l = np.log(rho)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    x, y, g, st = gpu_run(nodes, l, u, v, prm, dt, 2, dev, filter=True)
+    builds = 1 + 4 * 2
+    assert st["builds"] == builds
+    cnt = st["node_status"]
+    assert cnt == [builds * (nodes.n - 1), builds, 0, 0, 0], cnt
+    assert g[0][starved] == l[starved]
+    assert g[1][starved] == u[starved] and g[2][starved] == v[starved]
+    assert x[starved] != nodes.x[starved]
+    with pytest.raises(labfm.NodeStatusError) as ei:
+        gpu_run(nodes, l, u, v, prm, dt, 1, dev, filter=True, strict=True)
+    assert ei.value.counts == [5 * (nodes.n - 1), 5, 0, 0, 0]

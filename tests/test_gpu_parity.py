@@ -2,9 +2,12 @@
 
 Gates: neighbour lists bit-exact; operator outputs, right-hand sides and RK
 states within 1e-12 relative (l2 over the field) in float64; weights per node
-within max(1e-12, 100 cond(M~) eps) relative l2.
+within max(1e-12, 100 cond(M~) eps) relative l2. At orders 9 and 10, where
+cond(M~) eps is far above 1e-12, the gates are set by the oracle's own error
+against 40-digit solves (see the section header below).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -518,6 +521,160 @@ def test_full_size_rk_stable_and_decays(dev, tg512):
     decay = math.exp(-2 * prm.mu * dt * 100)
     assert np.max(np.abs(g[1])) == pytest.approx(np.max(np.abs(u)) * decay, rel=2e-3)
     assert np.max(np.abs(g[0])) < 0.02
+
+
+def test_full_size_rk_state_matches_oracle(dev, tg512):
+    """The whole 262,144-node state after 5 filtered RK steps at m = 8 (the
+    benchmark workload, eager and graph-replayed) against the oracle's
+    weights and time loop, run over node chunks in worker processes (each
+    running the oracle's own routines on its rows, bit-identical to the
+    serial oracle)."""
+    import time
+
+    from oracle_pool import OraclePool
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops = tg512
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    got = []
+    for graph in (False, True):
+        q = T(np.concatenate([l, u, v]), dev)
+        labfm.rk_step(q, ops, prm, dt, 5, use_graph=graph, check_finite=True)
+        got.append(q.cpu().numpy())
+    assert np.array_equal(got[0], got[1])
+    t0 = time.perf_counter()
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    assert np.array_equal(ops.row_ptr.cpu().numpy(), rp)
+    with OraclePool(nodes, rp, col, prm, workers=16) as pool:
+        assert np.array_equal(ops.status.cpu().numpy(), pool.status)
+        np.testing.assert_allclose(ops.kappa.cpu().numpy(), pool.kappa, rtol=1e-9)
+        ref = pool.rk_run(l, u, v, dt, 5)
+    errs = _compare_state(got[0], ref)
+    print(f"full-size state vs oracle: rel errors {errs}, oracle {time.perf_counter() - t0:.1f} s")
+    assert max(errs) <= TOL, errs
+
+
+# --------------------------------------------- orders 9 and 10 (k up to 10)
+#
+# At m = 9 and 10 the node systems have cond(M~) ~ 3e12 and ~1e14, and any
+# float64 solve (LAPACK's included) is accurate only to ~1e-11..1e-9 in the
+# operator outputs: 1e-12 agreement between two correct float64 solvers is
+# below the rounding floor there. The gates are therefore derived from the
+# arithmetic: tests/golden/high_order_exact.txt holds the exact outputs
+# (40-digit solves of the same systems, oracle/exact.py) at sampled nodes;
+# the GPU must be as close to them as the float64 oracle is (within 10x),
+# and the whole-field GPU-oracle difference is gated at 10x the oracle's own
+# error against the exact result (never below 1e-12).
+
+GOLD_HIGH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "high_order_exact.txt")
+
+
+def _gold_high(m):
+    rows = {}
+    for ln in open(GOLD_HIGH):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        mm, i, f, d, ex, _ = ln.split()
+        if int(mm) == m:
+            rows[(int(i), f, int(d))] = float(ex)
+    return rows
+
+
+def _exact_errors(m, nodes, outputs):
+    """Relative l2 error of outputs[field] (6, N) against the exact outputs
+    at the sampled nodes: {field: array of 6 (one per operator)}."""
+    gold = _gold_high(m)
+    nodes_s = sorted({k[0] for k in gold})
+    errs = {}
+    for f in outputs:
+        e = []
+        for d in range(6):
+            ex = np.array([gold[(i, f, d)] for i in nodes_s])
+            got = np.array([outputs[f][d][i] for i in nodes_s])
+            e.append(np.linalg.norm(got - ex) / np.linalg.norm(ex))
+        errs[f] = np.array(e)
+    return errs
+
+
+@pytest.fixture(scope="module", params=[(10, 3.2), (9, 3.0)], ids=["m10", "m9"])
+def high_order(dev, request):
+    """40 x 40 jittered lattice (seed 6) at m = 10 (h/s = 3.2, ~128
+    neighbours, 65 moments) or the odd order m = 9 (h/s = 3.0, 54 moments;
+    its filter is nabla^8): GPU operators, the oracle's for every node, and
+    the oracle's error against the exact outputs (per operator)."""
+    from fields import smooth_fields
+
+    m, hs = request.param
+    nodes = inputs.jittered_lattice(40, seed=6, m=m, h_over_s=hs)
+    ops = gpu_setup(nodes, dev)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    assert np.array_equal(ops.col.cpu().numpy(), col)
+    fields = smooth_fields(nodes.x, nodes.y)
+    orc = {k: np.array([O.apply_op(rp, col, W["w"][d], f) for d in range(6)])
+           for k, f in fields.items()}
+    e_oracle = _exact_errors(m, nodes, orc)
+    return m, nodes, ops, W, fields, orc, e_oracle
+
+
+def _gate(e_oracle, fields=None, ops=range(5)):
+    """10x the oracle's error against the exact outputs (the largest over the
+    given fields and operators), never below 1e-12."""
+    fs = list(e_oracle) if fields is None else fields
+    return max(TOL, 10.0 * max(float(np.max(e_oracle[f][list(ops)])) for f in fs))
+
+
+def test_high_order_apply_parity(dev, high_order):
+    from paper_2102_02019_amd import labfm
+
+    m, nodes, ops, W, fields, orc, e_or = high_order
+    assert np.array_equal(ops.status.cpu().numpy(), W["status"])
+    assert np.all(W["status"] == 0)
+    gpu = {k: labfm.apply_operators(ops, T(f, dev), 0x3F).cpu().numpy()
+           for k, f in fields.items()}
+    e_gpu = _exact_errors(m, nodes, gpu)
+    for k in fields:
+        print(f"m={m} {k}: error vs exact, oracle {e_or[k]}, gpu {e_gpu[k]}")
+        # the GPU's solve is as accurate as LAPACK's, within 10x
+        assert np.all(e_gpu[k] <= 10.0 * e_or[k] + 1e-13), (k, e_gpu[k], e_or[k])
+        for d in range(6):
+            r = rel(gpu[k][d], orc[k][d])
+            assert r <= _gate(e_or, [k], [d]), (m, k, d, r, e_or[k][d])
+
+
+def test_high_order_rhs_parity(dev, high_order):
+    from paper_2102_02019_amd import labfm
+
+    m, nodes, ops, W, _, _, e_or = high_order
+    prm = inputs.FlowParams(c2=100.0, mu=math.pi / 100, gx=0.3, gy=-0.1)
+    l, u, v = _tg_state(nodes)
+    got = labfm.ns_rhs(T(np.concatenate([l, u, v]), dev), ops, prm).cpu().numpy().reshape(3, -1)
+    ref = O.ns_rhs(l, u, v, W, prm)
+    errs = [rel(got[k], ref[k]) for k in range(3)]
+    print(f"m={m} RHS vs oracle {errs}, gate {_gate(e_or):.2e}")
+    assert max(errs) <= _gate(e_or), (m, errs)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_high_order_rk_parity_20_steps(dev, high_order, graph):
+    """Taylor-Green, 20 RK steps with the filter after every step."""
+    from paper_2102_02019_amd import labfm
+
+    m, nodes, ops, W, _, _, e_or = high_order
+    prm = inputs.taylor_green_params()
+    l, u, v = _tg_state(nodes)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    q = T(np.concatenate([l, u, v]), dev)
+    labfm.rk_step(q, ops, prm, dt, 20, use_graph=graph, check_finite=True)
+    ref = O.rk_run(l, u, v, W, prm, dt, 20)
+    errs = _compare_state(q.cpu().numpy(), ref)
+    print(f"m={m} RK state vs oracle {errs}, gate {_gate(e_or):.2e}")
+    assert max(errs) <= _gate(e_or), (m, errs)
+    np.testing.assert_allclose(ops.kappa.cpu().numpy(), W["kappa"], rtol=1e-8)
 
 
 # ------------------------------------------------------- float32 weight paths

@@ -354,3 +354,31 @@ def test_rhs_at_nodes_equals_full_rhs():
     rp_f, col_f = W["row_ptr"], W["col"]
     for i in sample:
         assert np.array_equal(col[rp[i]:rp[i + 1]], col_f[rp_f[i]:rp_f[i + 1]])
+
+
+# ------------------------------------------- the oracle over node chunks
+
+def test_chunked_oracle_equals_serial_oracle():
+    """The worker-process oracle used by the full-size GPU tests (each worker
+    running the oracle's routines on its node range) reproduces the serial
+    oracle's weights, right-hand side and filtered RK run bit for bit."""
+    from oracle_pool import OraclePool
+
+    nodes = inputs.jittered_lattice(24, seed=5, m=6)
+    rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
+    W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, 6, rp, col, nodes.box)
+    W.update(row_ptr=rp, col=col)
+    prm = inputs.FlowParams(c2=100.0, mu=math.pi / 100, gx=0.3, gy=-0.1)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y)
+    l = np.log(rho) + 0.05 * np.sin(nodes.x + 2 * nodes.y)
+    dt = O.time_step(nodes.s, l, u, v, prm)
+    ref = O.rk_run(l, u, v, W, prm, dt, 3)
+    with OraclePool(nodes, rp, col, prm, workers=3) as pool:
+        assert np.array_equal(pool.kappa, W["kappa"])
+        assert np.array_equal(pool.status, W["status"])
+        r = pool.ns_rhs(l, u, v)
+        for a, b in zip(r, O.ns_rhs(l, u, v, W, prm)):
+            assert np.array_equal(a, b)
+        got = pool.rk_run(l, u, v, dt, 3)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)

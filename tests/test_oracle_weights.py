@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import sympy
 
+from oracle import exact as X
 from oracle import labfm_oracle as O
 from paper_2102_02019_amd import inputs
 
@@ -61,33 +62,7 @@ def test_polynomial_reproduction(m):
 
 
 def _exact_weights(dx, dy, h, m, digits=40):
-    """Weights from a 40-digit solve with mpmath's own Hermite polynomials."""
-    with mpmath.workdps(digits):
-        ex = O.monomial_exponents(m)
-        n = len(ex)
-        hm = mpmath.mpf(h)
-        K = dx.size
-        Xt = mpmath.matrix(K, n)
-        Wm = mpmath.matrix(K, n)
-        for k in range(K):
-            xs = mpmath.mpf(dx[k]) / hm
-            ys = mpmath.mpf(dy[k]) / hm
-            q = mpmath.sqrt(xs * xs + ys * ys)
-            psi = (1 - q / 2) ** 4 * (1 + 2 * q) if q < 2 else mpmath.mpf(0)
-            for c, (a, b) in enumerate(ex):
-                Xt[k, c] = xs ** a * ys ** b / (mpmath.factorial(a) * mpmath.factorial(b))
-                Wm[k, c] = (psi * mpmath.hermite(a, xs / mpmath.sqrt(2))
-                            * mpmath.hermite(b, ys / mpmath.sqrt(2)) / mpmath.sqrt(2) ** (a + b))
-        M = Xt.T * Wm
-        C = O.target_vectors(m, 1.0)
-        out = np.zeros((6, K))
-        for d in range(6):
-            c = mpmath.matrix([mpmath.mpf(C[p, d]) / hm ** sum(ex[p]) for p in range(n)])
-            psi_d = mpmath.lu_solve(M, c)
-            wd = Wm * psi_d
-            out[d] = [float(wd[k]) for k in range(K)]
-        Mf = np.array([[float(M[r, c]) for c in range(n)] for r in range(n)])
-    return out, np.linalg.cond(Mf)
+    return X.exact_node_weights(dx, dy, h, m, digits)
 
 
 @pytest.mark.slow
