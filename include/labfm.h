@@ -259,6 +259,29 @@ int labfm_build_weights(const double* x, const double* y, const double* h, const
                         int8_t* status, void* stream);
 
 /*
+ * labfm_build_weights for callers that cannot allocate device memory (tight
+ * serving or time-stepping loops, harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results, with the work list held in a static
+ * device array of the library instead of a temporary allocation. The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *
+ *   n  at most LABFM_NOALLOC_MAX_NODES; larger sets return LABFM_ERR_ARG
+ *      (use labfm_build_weights).
+ * The array, (64 + LABFM_NOALLOC_MAX_NODES) int32 = 16 MiB, is held by every
+ * GPU the library runs on until the process ends, and is shared by all calls
+ * on that GPU: calls that overlap on one GPU (from several host threads or
+ * streams) race and must be serialised by the caller. Each call clears what
+ * it uses; nothing is kept between calls. Synchronises, like
+ * labfm_build_weights.
+ */
+#define LABFM_NOALLOC_MAX_NODES 4194304
+int labfm_build_weights_noalloc(const double* x, const double* y, const double* h,
+                                const double* s, const int8_t* order_m, int32_t n, labfm_box box,
+                                const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                                double* w, float* w32, float* mom32, double* kappa,
+                                double* rowsum, int8_t* status, void* stream);
+
+/*
  * Stencil optimisation (section "Stencil optimisation"): for every node, the
  * stencil scale h_i shrinks from h0_i by the factor `shrink` while the
  * stencil passes two tests, and the last scale that passed is kept (h0_i

@@ -1334,6 +1334,13 @@ order_scatter_kernel(const int8_t* __restrict__ m, int n, int* __restrict__ hist
   if (i < n) list[base[b] + rank] = i;
 }
 
+// Zeroes count ints: the clears of the build's work area are kernels, not
+// memset nodes.
+__global__ void zero_ints_kernel(int* __restrict__ p, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 __global__ void max_order_kernel(const int8_t* __restrict__ m, int n, int* out) {
   __shared__ int sh[256];
   int v = 0;
@@ -1381,7 +1388,8 @@ hipError_t launch_persistent(const BuildArgs& g, const int* list, int count, int
   blocks = std::max(1, blocks);
   if (per_cu > 0) blocks = std::min(blocks, per_cu);
   const int grid = std::max(1, std::min(count, cus * blocks));
-  e = hipMemsetAsync(counter, 0, sizeof(int), st);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, counter, 1);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(build_persistent_kernel<MMAX>, dim3(grid), dim3(kBlock), 0, st, g, list,
                      count, counter);
@@ -1426,35 +1434,29 @@ extern "C" int labfm_get_build_config(labfm_build_config* cfg) {
   return LABFM_OK;
 }
 
-extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
-                                   const double* s, const int8_t* order_m, int32_t n,
-                                   labfm_box box, const int32_t* row_ptr, const int32_t* col,
-                                   int64_t nnz, double* w, float* w32, float* mom32,
-                                   double* kappa, double* rowsum, int8_t* status,
-                                   void* stream_) {
-  clear_error();
-  LABFM_REQUIRE(n > 0, "build_weights: n must be positive (got %d)", n);
-  LABFM_REQUIRE(x && y && h && s && order_m && row_ptr && w && kappa && status,
-                "build_weights: null pointer argument");
-  LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "build_weights: bad CSR arguments");
-  hipStream_t st = as_stream(stream_);
+namespace labfm {
+namespace {
+
+// Body of labfm_build_weights over a work area of kBuildWorkInts + n ints:
+// [0, 16) bucket cursors, [16, 33) bucket starts and their total, [40] the
+// persistent distribution's work counter, [64, 64 + n) the node list ordered
+// by decreasing order. The area is cleared here; nothing else is kept.
+constexpr int kBuildWorkInts = 64;
+
+int build_weights_with(const double* x, const double* y, const double* h, const double* s,
+                       const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
+                       const int32_t* col, int64_t nnz, double* w, float* w32, float* mom32,
+                       double* kappa, double* rowsum, int8_t* status, int* work,
+                       hipStream_t st) {
   labfm_build_config cfg;
   {
     std::lock_guard<std::mutex> lock(g_build_mutex);
     cfg = g_build_cfg;
   }
-  // work list grouped by order (highest first) and the bucket sizes
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  } tmp;
-  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (64 + static_cast<size_t>(n))));
-  int* hist = static_cast<int*>(tmp.p);  // [0,16) cursors, [16,32) starts, [32] total
+  int* hist = work;  // [0,16) cursors, [16,32) starts, [32] total
   int* counter = hist + 40;
-  int* list = hist + 64;
-  LABFM_HIP(hipMemsetAsync(hist, 0, sizeof(int) * 64, st));
+  int* list = hist + kBuildWorkInts;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, hist, kBuildWorkInts);
   hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
                      n, hist);
   hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(64), 0, st, hist);
@@ -1516,9 +1518,97 @@ extern "C" int labfm_build_weights(const double* x, const double* y, const doubl
       e = hipErrorInvalidValue;
   }
   LABFM_HIP(e);
-  // the work list is freed on return
+  // the work area may be released or reused once the call returns
   LABFM_HIP(hipStreamSynchronize(st));
   return LABFM_OK;
+}
+
+int check_build_args(const double* x, const double* y, const double* h, const double* s,
+                     const int8_t* order_m, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                     int64_t nnz, const double* w, const double* kappa, const int8_t* status,
+                     const char* who) {
+  LABFM_REQUIRE(n > 0, "%s: n must be positive (got %d)", who, n);
+  LABFM_REQUIRE(x && y && h && s && order_m && row_ptr && w && kappa && status,
+                "%s: null pointer argument", who);
+  LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "%s: bad CSR arguments", who);
+  return LABFM_OK;
+}
+
+// Scratch of labfm_build_weights_noalloc: the work area of the largest node
+// set it accepts. Each GPU the library runs on holds its own copy until the
+// process ends. Host code never uses this name as an address: it takes the
+// device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) int scratch[kBuildWorkInts + LABFM_NOALLOC_MAX_NODES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+int* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first use).
+int scratch_of_current_device(int** out) {
+  int dev = 0;
+  LABFM_HIP(hipGetDevice(&dev));
+  LABFM_REQUIRE(dev >= 0 && dev < kMaxDevices, "build_weights_noalloc: device %d out of range",
+                dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("build_weights_noalloc: hipGetSymbolAddress(scratch) failed: %s",
+                hipGetErrorString(e));
+      return LABFM_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = static_cast<int*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LABFM_OK;
+}
+
+}  // namespace
+}  // namespace labfm
+
+extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
+                                   const double* s, const int8_t* order_m, int32_t n,
+                                   labfm_box box, const int32_t* row_ptr, const int32_t* col,
+                                   int64_t nnz, double* w, float* w32, float* mom32,
+                                   double* kappa, double* rowsum, int8_t* status,
+                                   void* stream_) {
+  clear_error();
+  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, w, kappa, status,
+                               "build_weights"))
+    return r;
+  hipStream_t st = as_stream(stream_);
+  struct Temp {
+    void* p = nullptr;
+    ~Temp() {
+      if (p) (void)hipFree(p);
+    }
+  } tmp;
+  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (kBuildWorkInts + static_cast<size_t>(n))));
+  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
+                            rowsum, status, static_cast<int*>(tmp.p), st);
+}
+
+extern "C" int labfm_build_weights_noalloc(const double* x, const double* y, const double* h,
+                                           const double* s, const int8_t* order_m, int32_t n,
+                                           labfm_box box, const int32_t* row_ptr,
+                                           const int32_t* col, int64_t nnz, double* w,
+                                           float* w32, float* mom32, double* kappa,
+                                           double* rowsum, int8_t* status, void* stream_) {
+  clear_error();
+  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, w, kappa, status,
+                               "build_weights_noalloc"))
+    return r;
+  LABFM_REQUIRE(n <= LABFM_NOALLOC_MAX_NODES,
+                "build_weights_noalloc: %d nodes exceed the scratch's maximum of %d nodes "
+                "(use labfm_build_weights)",
+                n, LABFM_NOALLOC_MAX_NODES);
+  int* work = nullptr;
+  if (int r = scratch_of_current_device(&work)) return r;
+  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
+                            rowsum, status, work, as_stream(stream_));
 }
 
 extern "C" int labfm_tune_build(const double* x, const double* y, const double* h,
@@ -1596,7 +1686,7 @@ extern "C" int labfm_optimise_stencils(const double* x, const double* y, const d
   LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (64 + static_cast<size_t>(n))));
   int* hist = static_cast<int*>(tmp.p);
   int* list = hist + 64;
-  LABFM_HIP(hipMemsetAsync(hist, 0, sizeof(int) * 64, st));
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, hist, 64);
   hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
                      n, hist);
   hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(64), 0, st, hist);

@@ -116,6 +116,9 @@ _SIGNATURES = {
                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                            ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P]),
+    "labfm_build_weights_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P,
+                                                   _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                                   _P]),
     "labfm_apply_operators": (ctypes.c_int, [ctypes.POINTER(_Operators), ctypes.c_uint32, _P, _P,
                                              ctypes.c_int, _P]),
     "labfm_time_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -385,6 +388,7 @@ def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, 
 
 
 TILE_NODES = 32
+NOALLOC_MAX_NODES = 4194304  # LABFM_NOALLOC_MAX_NODES
 TILE_HALO_MAX = 1024
 
 
