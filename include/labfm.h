@@ -24,7 +24,11 @@
  *  - Stencils are CSR: row_ptr int32[n+1] (row_ptr[0] = 0), col int32[nnz],
  *    the neighbours of node i in ascending index order, i itself excluded.
  *  - Operator weights are stored one operator after another:
- *    w[op * nnz + e] for edge e of the CSR, op in labfm_op order.
+ *    w[op * nnz + e] for edge e of the CSR, op in labfm_op order. The
+ *    float32 copy w32 uses a padded row stride, w32[op * labfm_w32_stride(nnz)
+ *    + e], so that every operator's row starts on a 128-byte boundary (the
+ *    float32 gathers load four consecutive edges per lane); its entries past
+ *    nnz in each row are never read as weights.
  */
 #ifndef LABFM_H
 #define LABFM_H
@@ -116,7 +120,7 @@ typedef struct {
   const int32_t* col;       /* int32[nnz] */
   const double* w;          /* float64[6*nnz], labfm_op order (may be NULL
                                when only the float32 copy is used) */
-  const float* w32;         /* float32[6*nnz] or NULL */
+  const float* w32;         /* float32[6*labfm_w32_stride(nnz)] or NULL */
   const float* mom32;       /* float32[LABFM_NUM_MOM32*n] first moments of w32
                                (required with w32 for the float32 precisions) */
   const double* kappa;      /* float64[n] filter coefficients */
@@ -171,6 +175,11 @@ typedef struct {
   int32_t lanes_per_node;
   int32_t flags;
 } labfm_launch_config;
+
+/* Row stride, in elements, of the float32 weight copy w32: nnz rounded up
+ * to a multiple of 32 (128 bytes). A w32 buffer holds 6 such rows and starts
+ * on a 128-byte boundary (device allocations do). */
+int64_t labfm_w32_stride(int64_t nnz);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* labfm_last_error(void);
@@ -236,7 +245,8 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  *   order_m     int8[n], each in 1..10.
  *   row_ptr, col, nnz  CSR from labfm_build_neighbours.
  *   w       float64[6*nnz] output.
- *   w32     float32[6*nnz] output copy, or NULL.
+ *   w32     float32[6*labfm_w32_stride(nnz)] output copy (rows of the padded
+ *           stride), or NULL.
  *   mom32   float32[LABFM_NUM_MOM32*n] output first moments of w32 (see
  *           LABFM_NUM_MOM32), or NULL.
  *   kappa   float64[n] output.
@@ -248,9 +258,11 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  * kappa = 0 except for LABFM_NODE_FEW_NEIGHBOURS, whose weights are those of
  * the (rank-deficient) solve when it completes. Nodes of different orders and
  * stencil sizes are built in one call; labfm_set_build_config selects how
- * they are spread over the GPU (default: one workgroup per node, in a work
- * list ordered by decreasing order; labfm_tune_build picks). Synchronises
- * (it sizes its work list on the host) and allocates a small work list.
+ * they are spread over the GPU (default LABFM_BUILD_ROWS: one wavefront per
+ * node holding the system's rows in registers for orders up to 9, one
+ * workgroup per node for order 10, from a work list grouped by order;
+ * labfm_tune_build picks). Synchronises (it sizes its work list on the host)
+ * and allocates a small work list.
  */
 int labfm_build_weights(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* order_m, int32_t n, labfm_box box,
@@ -390,14 +402,17 @@ int labfm_boundary_weights(const double* x, const double* y, const double* h, co
 /* How labfm_build_weights distributes nodes over the GPU. */
 enum {
   LABFM_BUILD_WAVE = 1,        /* one 64-lane wavefront per node */
-  LABFM_BUILD_BLOCK = 2,       /* one 256-thread workgroup (4 wavefronts) per node
-                                  (the default) */
+  LABFM_BUILD_BLOCK = 2,       /* one 256-thread workgroup (4 wavefronts) per node */
   LABFM_BUILD_PERSISTENT = 3,  /* one launch of persistent 256-thread workgroups taking
                                   nodes (highest order first) from a work counter */
-  LABFM_BUILD_BUCKETED = 4     /* one 256-thread-per-node launch per order class */
+  LABFM_BUILD_BUCKETED = 4,    /* one 256-thread-per-node launch per order class */
+  LABFM_BUILD_ROWS = 5         /* one 64-lane wavefront per node holding the system's
+                                  rows in registers (orders 1..9, one launch per
+                                  order present); order 10 and out-of-range orders
+                                  take the workgroup-per-node kernel */
 };
 typedef struct {
-  int32_t mode;               /* LABFM_BUILD_*; default LABFM_BUILD_BLOCK */
+  int32_t mode;               /* LABFM_BUILD_*; default LABFM_BUILD_ROWS */
   int32_t workgroups_per_cu;  /* persistent mode: 0 = as many as fit */
 } labfm_build_config;
 

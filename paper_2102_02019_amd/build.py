@@ -25,8 +25,11 @@ HIP_FLAGS = [
 # weights.hip: LDS atomics are issued as they are written. The compiler's
 # atomic optimizer would otherwise turn each pivot proposal (an LDS max from a
 # few lanes) into a loop over the active lanes, a dozen instructions per lane,
-# on the LU's critical path.
-FILE_FLAGS = {"weights.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+# on the LU's critical path. The rows-in-registers kernel's column loops must
+# unroll fully (its rows are register arrays indexed by the column); the
+# default cost limit of a requested full unroll stops short at order 8.
+FILE_FLAGS = {"weights.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+                               "-mllvm", "-pragma-unroll-threshold=1000000"]}
 SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
            "boundaries.hip", "lagrangian.hip", "morton.hip", "probe.hip"]
 

@@ -23,4 +23,6 @@ void clear_error() { g_error[0] = '\0'; }
 
 extern "C" const char* labfm_last_error(void) { return labfm::g_error; }
 
-extern "C" const char* labfm_version(void) { return "labfm-mi355x 0.1.0 (gfx950)"; }
+extern "C" const char* labfm_version(void) { return "labfm-mi355x 0.2.0 (gfx950)"; }
+
+extern "C" int64_t labfm_w32_stride(int64_t nnz) { return nnz <= 0 ? 0 : (nnz + 31) / 32 * 32; }

@@ -248,8 +248,8 @@ __global__ void __launch_bounds__(64 * kWaves) boundary_weights_kernel(BoundaryA
     a.w[LABFM_OP_X * a.nnz + e] = wx;
     a.w[LABFM_OP_Y * a.nnz + e] = wy;
     if (a.w32) {
-      a.w32[LABFM_OP_X * a.nnz + e] = static_cast<float>(wx);
-      a.w32[LABFM_OP_Y * a.nnz + e] = static_cast<float>(wy);
+      a.w32[LABFM_OP_X * w32_stride(a.nnz) + e] = static_cast<float>(wx);
+      a.w32[LABFM_OP_Y * w32_stride(a.nnz) + e] = static_cast<float>(wy);
     }
     if (q == 0) {
       a.w[LABFM_OP_L * a.nnz + e] = 0.0;
@@ -257,10 +257,10 @@ __global__ void __launch_bounds__(64 * kWaves) boundary_weights_kernel(BoundaryA
       a.w[LABFM_OP_XY * a.nnz + e] = 0.0;
       a.w[LABFM_OP_HYP * a.nnz + e] = whyp;
       if (a.w32) {
-        a.w32[LABFM_OP_L * a.nnz + e] = 0.0f;
-        a.w32[LABFM_OP_XX * a.nnz + e] = 0.0f;
-        a.w32[LABFM_OP_XY * a.nnz + e] = 0.0f;
-        a.w32[LABFM_OP_HYP * a.nnz + e] = static_cast<float>(whyp);
+        a.w32[LABFM_OP_L * w32_stride(a.nnz) + e] = 0.0f;
+        a.w32[LABFM_OP_XX * w32_stride(a.nnz) + e] = 0.0f;
+        a.w32[LABFM_OP_XY * w32_stride(a.nnz) + e] = 0.0f;
+        a.w32[LABFM_OP_HYP * w32_stride(a.nnz) + e] = static_cast<float>(whyp);
       }
       f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * whyp;
     }

@@ -53,6 +53,10 @@ constexpr int kMaxMoments = (kMaxOrder * kMaxOrder + 3 * kMaxOrder) / 2;
 
 __host__ __device__ constexpr int moments_of(int m) { return (m * m + 3 * m) / 2; }
 
+// Row stride of the float32 weight copy: nnz rounded up to 32 elements, so
+// every operator's row starts on a 128-byte boundary (labfm_w32_stride).
+__host__ __device__ constexpr long long w32_stride(long long nnz) { return (nnz + 31) / 32 * 32; }
+
 // Device-side minimum-image difference on one axis.
 __device__ __forceinline__ double wrap_axis(double d, double L, int periodic) {
   if (periodic) {

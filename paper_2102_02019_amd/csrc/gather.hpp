@@ -17,8 +17,8 @@
 //            a float32 pair hi + lo; each product w*hi split exactly with an
 //            FMA (TwoProd), w*lo added to its error term, and the products
 //            summed with TwoSum, the error terms accumulated separately
-//            (Dot2 of Ogita, Rump & Oishi 2005), partial sums combined across
-//            lanes the same way, the final pair added in float64. (A single
+//            (Dot2 of Ogita, Rump & Oishi 2005); each lane's pair is carried
+//            into float64 and the lanes' partials summed in float64. (A single
 //            float32 difference would carry a rounding error of order
 //            eps32 |grad phi| h into every product, i.e. eps32 |grad phi| / h
 //            into a second derivative, whatever the summation.)
@@ -88,19 +88,14 @@ struct F32Comp {
       s = t;
       c = c + (es + ep);
     }
+    // The lane's compensated pair is carried into float64 (s + c rounded
+    // once at float64 precision) and the lanes' partials are summed in
+    // float64: on this GPU that costs fewer instructions than combining the
+    // pairs with TwoSum in float32, and its rounding (eps64) lies far below
+    // the Dot2 error of each partial.
     template <int width>
     __device__ __forceinline__ double reduce() {
-      float hs = s, hc = c;
-#pragma unroll
-      for (int off = width / 2; off > 0; off >>= 1) {
-        const float os = __shfl_xor(hs, off, width);
-        const float oc = __shfl_xor(hc, off, width);
-        float t, e;
-        two_sum(hs, os, t, e);
-        hs = t;
-        hc = (hc + oc) + e;
-      }
-      return static_cast<double>(hs) + static_cast<double>(hc);
+      return group_sum<width>(static_cast<double>(s) + static_cast<double>(c));
     }
   };
   using D = float2;  // (hi, lo) of the float64 difference
@@ -120,6 +115,13 @@ struct F32W {
   using D = double;
   __device__ __forceinline__ static D diff(double pj, double pi) { return pj - pi; }
 };
+
+// Row stride of a policy's weight array: nnz for the float64 weights, the
+// padded w32_stride(nnz) for the float32 copy.
+template <class P>
+__host__ __device__ constexpr long long wstride(long long nnz) {
+  return std::is_same<typename P::W, float>::value ? w32_stride(nnz) : nnz;
+}
 
 // Float32 weights break the first-moment conditions sum_j w_ji r_ji = 0 of
 // the second-derivative operators by rounding; the float32 precisions remove
@@ -214,7 +216,8 @@ apply_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
         if (need & (1u << d)) {
           typename P::W wv[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) wv[u] = stream_load<FL>(w + d * nnz + ee[u]);
+          for (int u = 0; u < U; ++u)
+            wv[u] = stream_load<FL>(w + d * wstride<P>(nnz) + ee[u]);
 #pragma unroll
           for (int u = 0; u < U; ++u) acc[d].add(ok[u] ? wv[u] : typename P::W(0), dj[u]);
         }
@@ -333,11 +336,12 @@ rk_stage_kernel(const int* __restrict__ row_ptr, const int* __restrict__ col,
   const double* Yu = Y + n;
   const double* Yv = Y + 2 * static_cast<long long>(n);
   const double li = Yl[node], ui = Yu[node], vi = Yv[node];
-  const typename P::W* wx = w + 0 * nnz;
-  const typename P::W* wy = w + 1 * nnz;
-  const typename P::W* wL = w + 2 * nnz;
-  const typename P::W* wxx = w + 3 * nnz;
-  const typename P::W* wxy = w + 4 * nnz;
+  const long long wst = wstride<P>(nnz);
+  const typename P::W* wx = w + 0 * wst;
+  const typename P::W* wy = w + 1 * wst;
+  const typename P::W* wL = w + 2 * wst;
+  const typename P::W* wxx = w + 3 * wst;
+  const typename P::W* wxy = w + 4 * wst;
   typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
   lx.zero(); ly.zero();
   ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
@@ -531,11 +535,12 @@ rk_stage_tiled_kernel(const int* __restrict__ row_ptr, Tiles tl,
   double* sv = lds + 2 * tl.hmax;
   const int t = tile_of_block<FL>();
   load_halo(tl, t, Y, n, sl, su, sv);
-  const typename P::W* wx = w + 0 * nnz;
-  const typename P::W* wy = w + 1 * nnz;
-  const typename P::W* wL = w + 2 * nnz;
-  const typename P::W* wxx = w + 3 * nnz;
-  const typename P::W* wxy = w + 4 * nnz;
+  const long long wst = wstride<P>(nnz);
+  const typename P::W* wx = w + 0 * wst;
+  const typename P::W* wy = w + 1 * wst;
+  const typename P::W* wL = w + 2 * wst;
+  const typename P::W* wxx = w + 3 * wst;
+  const typename P::W* wxy = w + 4 * wst;
   constexpr int NPR = 256 / LPN;  // nodes per round
   constexpr int U = unroll_of(LPN);
   using W = typename P::W;
@@ -742,13 +747,14 @@ rk_stage_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
   load_halo(tl, t, Y, n, sl, su, sv);
   // with an odd nnz the arrays of operators 1 and 3 (y, xx) start half a pair
   // off alignment: their two edges are loaded one by one
-  const typename K::VT* wx = reinterpret_cast<const typename K::VT*>(w + 0 * nnz);
-  const typename K::VT* wy = reinterpret_cast<const typename K::VT*>(w + 1 * nnz);
-  const typename K::VT* wL = reinterpret_cast<const typename K::VT*>(w + 2 * nnz);
-  const typename K::VT* wxx = reinterpret_cast<const typename K::VT*>(w + 3 * nnz);
-  const typename K::VT* wxy = reinterpret_cast<const typename K::VT*>(w + 4 * nnz);
-  const W* wy1 = w + 1 * nnz;
-  const W* wxx1 = w + 3 * nnz;
+  const long long wst = wstride<P>(nnz);
+  const typename K::VT* wx = reinterpret_cast<const typename K::VT*>(w + 0 * wst);
+  const typename K::VT* wy = reinterpret_cast<const typename K::VT*>(w + 1 * wst);
+  const typename K::VT* wL = reinterpret_cast<const typename K::VT*>(w + 2 * wst);
+  const typename K::VT* wxx = reinterpret_cast<const typename K::VT*>(w + 3 * wst);
+  const typename K::VT* wxy = reinterpret_cast<const typename K::VT*>(w + 4 * wst);
+  const W* wy1 = w + 1 * wst;
+  const W* wxx1 = w + 3 * wst;
   const typename K::IT* lc = reinterpret_cast<const typename K::IT*>(tl.lcol);
   constexpr int NPR = 256 / LPN;
   const int sub = threadIdx.x % LPN;
@@ -920,6 +926,177 @@ filter_tiled_packed_kernel(const int* __restrict__ row_ptr, Tiles tl,
 }
 
 // --------------------------------------------------------------------------
+// tiled kernels with quad edge loads (float32 weights)
+// --------------------------------------------------------------------------
+
+// The rows of the float32 weight copy start on 128-byte boundaries (stride
+// w32_stride(nnz)), so a lane loads four consecutive edges of every weight
+// array with one 16-byte load and their four 16-bit halo slots with one
+// 8-byte load. With 8 lanes per node a load instruction covers 128
+// contiguous bytes of each node's row, a whole cache line: with 8-byte pairs
+// (two half-line requests per line) the float32 stage moved 1.35x its
+// algorithmic bytes at K ~ 90, with quads about 1.05x. Quads start at edges
+// 4g; the edges of a quad outside the node's row contribute nothing and read
+// no halo value. The last quad of the slot array may run past nnz: its slots
+// are then read one by one.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int quad_slot(u32x2 j, int h) {
+  const unsigned word = (h < 2) ? j.x : j.y;
+  return static_cast<int>((h & 1) ? (word >> 16) : (word & 0xFFFFu));
+}
+
+// Halo slots of edges 4g..4g+3 (those at or past nnz read as 0).
+__device__ __forceinline__ u32x2 quad_slots(const unsigned short* __restrict__ lcol, long long g,
+                                            long long nnz) {
+  const long long e = 4 * g;
+  if (e + 4 <= nnz) return reinterpret_cast<const u32x2*>(lcol)[g];
+  unsigned s[4] = {0u, 0u, 0u, 0u};
+  for (int h = 0; h < 4; ++h)
+    if (e + h < nnz) s[h] = lcol[e + h];
+  return u32x2{s[0] | (s[1] << 16), s[2] | (s[3] << 16)};
+}
+
+template <int LPN, int FL, class P>
+__global__ void __launch_bounds__(256)
+rk_stage_tiled_quad_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                           const float* __restrict__ w, const float* __restrict__ mom,
+                           long long nnz, const double* Y, const double* qin, double* qout,
+                           double* Yout, double dta, double dtb, Flow fl, int n,
+                           const double* __restrict__ wn) {
+  static_assert(std::is_same<typename P::W, float>::value, "quads are float32 weights");
+  using D = typename P::D;
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, Y, n, sl, su, sv);
+  const long long wst = w32_stride(nnz);
+  const f32x4* wx = reinterpret_cast<const f32x4*>(w + 0 * wst);
+  const f32x4* wy = reinterpret_cast<const f32x4*>(w + 1 * wst);
+  const f32x4* wL = reinterpret_cast<const f32x4*>(w + 2 * wst);
+  const f32x4* wxx = reinterpret_cast<const f32x4*>(w + 3 * wst);
+  const f32x4* wxy = reinterpret_cast<const f32x4*>(w + 4 * wst);
+  constexpr int NPR = 256 / LPN;
+  const int sub = threadIdx.x % LPN;
+#pragma unroll 1
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
+    if (node >= n) break;  // whole LPN groups stop together
+    const double li = Y[node], ui = Y[n + node], vi = Y[2 * static_cast<long long>(n) + node];
+    typename P::Acc lx, ly, ux, uy, uL, uxx, uxy, vx, vy, vL, vxx, vxy;
+    lx.zero(); ly.zero();
+    ux.zero(); uy.zero(); uL.zero(); uxx.zero(); uxy.zero();
+    vx.zero(); vy.zero(); vL.zero(); vxx.zero(); vxy.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    const int g0 = e0 / 4, g1 = (e1 + 3) / 4;
+    for (int g = g0 + sub; g < g1; g += LPN) {
+      const u32x2 jj = quad_slots(tl.lcol, g, nnz);
+      const f32x4 a = stream_load<FL>(wx + g), b = stream_load<FL>(wy + g);
+      const f32x4 c = stream_load<FL>(wL + g), d = stream_load<FL>(wxx + g);
+      const f32x4 f = stream_load<FL>(wxy + g);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int e = 4 * g + h;
+        const bool v = e >= e0 && e < e1;
+        const int j = v ? quad_slot(jj, h) : 0;
+        const float aw = v ? a[h] : 0.0f, bw = v ? b[h] : 0.0f, cw = v ? c[h] : 0.0f;
+        const float dw = v ? d[h] : 0.0f, fw = v ? f[h] : 0.0f;
+        // edges outside the row read no halo value (slot 0 may be unset)
+        const D dl = P::diff(v ? sl[j] : li, li);
+        const D du = P::diff(v ? su[j] : ui, ui);
+        const D dv = P::diff(v ? sv[j] : vi, vi);
+        lx.add(aw, dl);
+        ly.add(bw, dl);
+        ux.add(aw, du);
+        uy.add(bw, du);
+        uL.add(cw, du);
+        uxx.add(dw, du);
+        uxy.add(fw, du);
+        vx.add(aw, dv);
+        vy.add(bw, dv);
+        vL.add(cw, dv);
+        vxx.add(dw, dv);
+        vxy.add(fw, dv);
+      }
+    }
+    double Dv[12] = {lx.template reduce<LPN>(),  ly.template reduce<LPN>(),
+                     ux.template reduce<LPN>(),  uy.template reduce<LPN>(),
+                     uL.template reduce<LPN>(),  uxx.template reduce<LPN>(),
+                     uxy.template reduce<LPN>(), vx.template reduce<LPN>(),
+                     vy.template reduce<LPN>(),  vL.template reduce<LPN>(),
+                     vxx.template reduce<LPN>(), vxy.template reduce<LPN>()};
+    if (sub == 0) {
+      moment_fix(mom, node, n, Dv[2], Dv[3], Dv[4], Dv[5], Dv[6]);
+      moment_fix(mom, node, n, Dv[7], Dv[8], Dv[9], Dv[10], Dv[11]);
+      stage_update(node, n, li, ui, vi, Dv, qin, qout, Yout, dta, dtb, fl, wn);
+    }
+  }
+}
+
+template <int LPN, int FL, class P>
+__global__ void __launch_bounds__(256)
+filter_tiled_quad_kernel(const int* __restrict__ row_ptr, Tiles tl,
+                         const float* __restrict__ whyp, long long nnz,
+                         const double* __restrict__ kappa, const double* __restrict__ in,
+                         double* __restrict__ out, int n, const double* __restrict__ wn) {
+  static_assert(std::is_same<typename P::W, float>::value, "quads are float32 weights");
+  extern __shared__ double lds[];
+  double* sl = lds;
+  double* su = lds + tl.hmax;
+  double* sv = lds + 2 * tl.hmax;
+  const int t = tile_of_block<FL>();
+  load_halo(tl, t, in, n, sl, su, sv);
+  const f32x4* wh = reinterpret_cast<const f32x4*>(whyp);
+  constexpr int NPR = 256 / LPN;
+  const int sub = threadIdx.x % LPN;
+  const long long n2 = 2 * static_cast<long long>(n);
+#pragma unroll 1
+  for (int r = 0; r < (LABFM_TILE_NODES + NPR - 1) / NPR; ++r) {
+    const int local = r * NPR + threadIdx.x / LPN;
+    if (local >= LABFM_TILE_NODES) break;  // a tile smaller than a pass
+    const int node = t * LABFM_TILE_NODES + local;
+    if (node >= n) break;
+    const double li = in[node], ui = in[n + node], vi = in[n2 + node];
+    typename P::Acc al, au, av;
+    al.zero();
+    au.zero();
+    av.zero();
+    const int e0 = row_ptr[node], e1 = row_ptr[node + 1];
+    const int g0 = e0 / 4, g1 = (e1 + 3) / 4;
+    for (int g = g0 + sub; g < g1; g += LPN) {
+      const u32x2 jj = quad_slots(tl.lcol, g, nnz);
+      const f32x4 a = stream_load<FL>(wh + g);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int e = 4 * g + h;
+        const bool v = e >= e0 && e < e1;
+        const int j = v ? quad_slot(jj, h) : 0;
+        const float aw = v ? a[h] : 0.0f;
+        al.add(aw, P::diff(v ? sl[j] : li, li));
+        au.add(aw, P::diff(v ? su[j] : ui, ui));
+        av.add(aw, P::diff(v ? sv[j] : vi, vi));
+      }
+    }
+    const double rl = al.template reduce<LPN>();
+    const double ru = au.template reduce<LPN>();
+    const double rv = av.template reduce<LPN>();
+    if (sub == 0) {
+      const double k = kappa[node];
+      double nx, ny;
+      const bool wall = wall_node(wn, node, nx, ny);  // the wall velocity is imposed
+      out[node] = li + k * rl;
+      out[n + node] = wall ? ui : ui + k * ru;
+      out[n2 + node] = wall ? vi : vi + k * rv;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // time step and finiteness check
 // --------------------------------------------------------------------------
 
@@ -1016,9 +1193,10 @@ LaunchCfg default_cfg(int kernel, labfm_prec prec, int n, long long nnz) {
   const double k = n > 0 ? static_cast<double>(nnz) / n : 0.0;
   int lpn = k > 48.0 ? 16 : (k > 12.0 ? 8 : 4);
   if (kernel == LABFM_KERNEL_FILTER && k > 48.0) lpn = 8;
-  // float64 stage on 32-node tiles: 8 lanes per node (two passes of 32 nodes
-  // per workgroup) measured 197 us against 200 us for 16 at 262,144 nodes, K = 90
-  if (kernel == LABFM_KERNEL_STAGE && prec == LABFM_F64 && k > 48.0) lpn = 8;
+  // stage on 32-node tiles: 8 lanes per node (float64: two passes of 32
+  // nodes per workgroup, 197 us against 200 us for 16 at 262,144 nodes,
+  // K = 90; float32: the quad loads then cover whole 128-byte lines)
+  if (kernel == LABFM_KERNEL_STAGE && k > 48.0) lpn = 8;
   return LaunchCfg{lpn, 0};
 }
 
@@ -1059,11 +1237,34 @@ bool packable(const labfm_operators* o, const void* w, bool odd_ok) {
   return (odd_ok || o->nnz % 2 == 0) && wb % (2 * sizeof(typename P::W)) == 0 && lb % 4 == 0;
 }
 
+// The quad kernels apply to the float32 weights when the weight base is
+// aligned to 16 bytes (rows then are, at the padded stride) and the halo
+// slots to 8 bytes.
+template <class P>
+bool quadable(const labfm_operators* o, const void* w) {
+  if (!std::is_same<typename P::W, float>::value) return false;
+  const uintptr_t wb = reinterpret_cast<uintptr_t>(w);
+  const uintptr_t lb = reinterpret_cast<uintptr_t>(o->tiles->lcol);
+  return wb % 16 == 0 && lb % 8 == 0;
+}
+
 template <class P>
 hipError_t launch_stage(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                         const double* Y, const double* qin, double* qout, double* Yout, double dta,
                         double dtb, const Flow& fl, hipStream_t st) {
   const int n = o->n;
+  if constexpr (std::is_same<typename P::W, float>::value) {
+    if (o->tiles && quadable<P>(o, w)) {
+      const Tiles tl = tiles_of(o);
+      const size_t shmem = 3 * sizeof(double) * tl.hmax;
+      return with_cfg(cfg, [&](auto L, auto F) {
+        hipLaunchKernelGGL(
+            (rk_stage_tiled_quad_kernel<decltype(L)::value, decltype(F)::value, P>),
+            dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl, w, o->mom32,
+            static_cast<long long>(o->nnz), Y, qin, qout, Yout, dta, dtb, fl, n, o->wall_normal);
+      });
+    }
+  }
   if (o->tiles && packable<P>(o, w, true)) {
     const Tiles tl = tiles_of(o);
     const size_t shmem = 3 * sizeof(double) * tl.hmax;
@@ -1105,7 +1306,19 @@ template <class P>
 hipError_t launch_filter(LaunchCfg cfg, const labfm_operators* o, const typename P::W* w,
                          const double* in, double* out, hipStream_t st) {
   const int n = o->n;
-  const typename P::W* whyp = w + LABFM_OP_HYP * o->nnz;
+  const typename P::W* whyp = w + LABFM_OP_HYP * wstride<P>(o->nnz);
+  if constexpr (std::is_same<typename P::W, float>::value) {
+    if (o->tiles && quadable<P>(o, w)) {
+      const Tiles tl = tiles_of(o);
+      const size_t shmem = 3 * sizeof(double) * tl.hmax;
+      return with_cfg(cfg, [&](auto L, auto F) {
+        hipLaunchKernelGGL((filter_tiled_quad_kernel<decltype(L)::value, decltype(F)::value, P>),
+                           dim3(o->tiles->ntiles), dim3(kThreads), shmem, st, o->row_ptr, tl,
+                           whyp, static_cast<long long>(o->nnz), o->kappa, in, out, n,
+                           o->wall_normal);
+      });
+    }
+  }
   if (o->tiles && packable<P>(o, w, false)) {
     const Tiles tl = tiles_of(o);
     const size_t shmem = 3 * sizeof(double) * tl.hmax;

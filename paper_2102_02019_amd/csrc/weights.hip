@@ -88,7 +88,7 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         w[d * nnz + e0 + k] = 0.0;
-        if (w32) w32[d * nnz + e0 + k] = 0.0f;
+        if (w32) w32[d * w32_stride(nnz) + e0 + k] = 0.0f;
       }
     if (lane == 0) {
       kappa[i] = 0.0;
@@ -296,7 +296,7 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         w[d * nnz + e0 + k] = 0.0;
-        if (w32) w32[d * nnz + e0 + k] = 0.0f;
+        if (w32) w32[d * w32_stride(nnz) + e0 + k] = 0.0f;
       }
     if (lane == 0) {
       kappa[i] = 0.0;
@@ -373,7 +373,7 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         const double v = psi * wd[d];
         w[d * nnz + e] = v;
-        if (w32) w32[d * nnz + e] = static_cast<float>(v);
+        if (w32) w32[d * w32_stride(nnz) + e] = static_cast<float>(v);
         rs[d] += v;
       }
 #pragma unroll
@@ -948,7 +948,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
         if (half == 0) {
           const long long e = e0 + k;
           g.w[dop * g.nnz + e] = acc;
-          if (g.w32) g.w32[dop * g.nnz + e] = static_cast<float>(acc);
+          if (g.w32) g.w32[dop * w32_stride(g.nnz) + e] = static_cast<float>(acc);
           if (dop == LABFM_OP_HYP) {
             f0 += (1.0 - nbx[2 * kChunk + slot] * nbx[3 * kChunk + slot]) * acc;
           } else if (dop >= LABFM_OP_L && dop <= LABFM_OP_XY) {
@@ -995,7 +995,7 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     for (int k = tid; k < K; k += kBlock)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         g.w[d * g.nnz + e0 + k] = 0.0;
-        if (g.w32) g.w32[d * g.nnz + e0 + k] = 0.0f;
+        if (g.w32) g.w32[d * w32_stride(g.nnz) + e0 + k] = 0.0f;
       }
     if (tid == 0) {
       g.kappa[i] = 0.0;
@@ -1058,6 +1058,479 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
     asm volatile("" : "+v"(tid));
     build_node_block<MMAX>(list[k], g, sm, tid);
   }
+}
+
+// ---------------------------------------------------------------------------
+// One wavefront per node, the system's rows in registers (orders 1..9)
+// ---------------------------------------------------------------------------
+//
+// For n <= 64 moments the whole augmented system [M~ | C~] fits one row per
+// lane: lane r keeps row r (n + 6 doubles, padded to an even count) in
+// registers, so the factorisation needs no workgroup barrier and no LDS
+// traffic for the trailing updates. Per node:
+//   1. the basis tables of 16 neighbours at a time in LDS and M~ on the FP64
+//      matrix cores, exactly as in the workgroup kernel (one wavefront
+//      accumulates every 16x16 tile);
+//   2. M~ goes to row-per-lane registers through LDS, one 16-column strip at
+//      a time (a strip's accumulators die as its columns arrive); every lane
+//      forms its own row of C~ from its monomial's exponents;
+//   3. LU with partial pivoting, rows never swapped: at column c the pivot is
+//      the row (lane) not yet used with the largest |a_rc| (a 32-bit key: the
+//      high word of |a| with its 6 lowest bits replaced by 63 - lane, reduced
+//      over the wave with DPP and read lanes; candidates within about 2^-14
+//      relative of each other count as a tie and go to the lowest lane). The
+//      pivot row reaches the other lanes through scalar registers (v_readlane)
+//      and the lanes not yet used subtract l_r = a_rc / u_cc times it (the
+//      multiplier from the reciprocal of the pivot, as LAPACK's unblocked
+//      factorisation forms it: a hardware reciprocal and one Newton step).
+//      The right-hand sides are eliminated along. (Broadcasting the rows
+//      through LDS instead makes every lane pull every value: 64 x 8 bytes per
+//      value through the CU's shared LDS data path, which then bounds the
+//      kernel.)
+//   4. back substitution from the last column: the pivot lane of column c
+//      (a ballot) forms x_c = y_c / u_cc (times its stored reciprocal), which
+//      every lane reads and subtracts from its right-hand sides, and writes it
+//      into Psi in LDS;
+//   5. one lane per neighbour: w^d_j = psi_j sum_q He_a(x_j) He_b(y_j) Psi^d_q
+//      (Psi read from LDS a row at a time: there the reads cost less than
+//      reading each row out of its lane, measured), then the float32 copy,
+//      the filter calibration sum, the row sums and the first moments,
+//      reduced over the wave in a fixed order.
+// The register arrays are indexed by compile-time constants only (every loop
+// over columns is unrolled), so the order is a template parameter.
+
+template <int M>
+struct RowShape {
+  static constexpr int N = moments_of(M);
+  static constexpr int NB = (N + 15) / 16;        // 16-wide MFMA tiles per side
+  static constexpr int RC = ((N + LABFM_NUM_OPS) + 1) & ~1;  // row length, even
+  static constexpr int TW = M + 1;                 // one basis table's length
+  static constexpr int TABLE = 4 * TW + 1;         // four tables and a zero
+  static constexpr int ZERO = 4 * TW;
+  static constexpr int SS = 17;                    // strip row stride (doubles)
+  static constexpr int kTable = kChunk * TABLE;
+  static constexpr int kStrip = NB * 16 * SS;
+  static constexpr int kPsi = N * LABFM_NUM_OPS;
+  static constexpr int kShared = (kTable > kStrip ? (kTable > kPsi ? kTable : kPsi)
+                                                  : (kStrip > kPsi ? kStrip : kPsi));
+};
+
+// LDS of the rows kernel: the basis tables during the assembly, then the
+// strips that carry M~ into the lanes' registers, then the solution Psi (read
+// by every lane in the weights phase).
+template <int M>
+struct alignas(16) RowSmem {
+  double buf[RowShape<M>::kShared];
+};
+
+// Register fence: an empty asm statement that reads and writes v. Such
+// statements keep their program order, so a value pinned after its update
+// is computed there, not sunk to its next use (the compiler otherwise defers
+// the trailing updates and the weight sums and keeps all their operands live
+// in registers). It emits no instruction.
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+
+// Largest 32-bit key of the wavefront (all 64 lanes active).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xF,
+                                                               0xF, false)));  // quad [1,0,3,2]
+  v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xF,
+                                                               0xF, false)));  // quad [2,3,0,1]
+  v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x141, 0xF,
+                                                               0xF, false)));  // half-row mirror
+  v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x140, 0xF,
+                                                               0xF, false)));  // row mirror
+  const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) |
+                                                     lo));
+}
+
+// Row r of C~ (the six right-hand sides C^d h^-(a+b)) for the monomial of
+// exponents (a, b) of an order-m system.
+__device__ __forceinline__ void rhs_row(int a, int b, int m, double h, double* c) {
+  const double h1 = 1.0 / h, h2 = 1.0 / (h * h);
+  c[LABFM_OP_X] = (a == 1 && b == 0) ? h1 : 0.0;
+  c[LABFM_OP_Y] = (a == 0 && b == 1) ? h1 : 0.0;
+  c[LABFM_OP_L] = (m >= 2 && ((a == 2 && b == 0) || (a == 0 && b == 2))) ? h2 : 0.0;
+  c[LABFM_OP_XX] = (m >= 2 && a == 2 && b == 0) ? h2 : 0.0;
+  c[LABFM_OP_XY] = (m >= 2 && a == 1 && b == 1) ? h2 : 0.0;
+  const int mp = (m % 2 == 0) ? m : m - 1;
+  double hyp = 0.0;
+  if (mp >= 2 && a + b == mp && a % 2 == 0) {
+    double hp = 1.0;
+    for (int k = 0; k < mp; ++k) hp *= h;
+    const int half = mp / 2;
+    double binom = 1.0;  // binom(half, p) for p = a/2, built as the other kernels do
+    for (int p = 0; p < a / 2; ++p)
+      binom = binom * static_cast<double>(half - p) / static_cast<double>(p + 1);
+    hyp = binom / hp;
+  }
+  c[LABFM_OP_HYP] = hyp;
+}
+
+// Wavefronts per SIMD the rows kernel is compiled for (its registers: the
+// rows, n + 6 doubles each, plus the assembly's accumulators in AGPRs).
+template <int M>
+constexpr int rows_waves() {
+  return M <= 6 ? 4 : (M <= 8 ? 3 : 2);
+}
+
+template <int M>
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(rows_waves<M>())))
+build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
+  using S = RowShape<M>;
+  constexpr int N = S::N, NB = S::NB, RC = S::RC, TW = S::TW;
+  __shared__ RowSmem<M> sm;
+  const int k_ = blockIdx.x;
+  if (k_ >= count) return;
+  const int lane = threadIdx.x;
+  const int i = uniform(list ? list[k_] : k_);
+  const int e0 = uniform(g.row_ptr[i]);
+  const int K = uniform(g.row_ptr[i + 1]) - e0;
+  const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
+  const int px = g.box.periodic_x, py = g.box.periodic_y;
+  const double hinv = 1.0 / h;
+  double* T = sm.buf;
+
+  // ---- 1: basis tables and MFMA assembly -----------------------------------
+  // exponents of this lane's moment index in each tile (row p or column q)
+  int ea[NB], eb[NB];
+#pragma unroll
+  for (int P = 0; P < NB; ++P) {
+    const int p = P * 16 + (lane & 15);
+    if (p < N) {
+      exponents_of(p, ea[P], eb[P]);
+    } else {
+      ea[P] = -1;
+      eb[P] = -1;
+    }
+  }
+  double4_t acc[NB][NB];
+#pragma unroll
+  for (int P = 0; P < NB; ++P)
+#pragma unroll
+    for (int Q = 0; Q < NB; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
+  const int kk = lane >> 2, t = lane & 3;  // table lanes: neighbour kk, table t
+  // coordinates of the lane's neighbour one chunk ahead
+  double xn = 0.0, yn = 0.0;
+  if (kk < K) {
+    const int j = g.col[e0 + kk];
+    xn = g.x[j];
+    yn = g.y[j];
+  }
+  if (lane < kChunk) T[lane * S::TABLE + S::ZERO] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += kChunk) {
+    const bool have = k0 + kk < K;
+    const double xj = xn, yj = yn;
+    if (k0 + kChunk + kk < K) {  // the next chunk's coordinates, in flight meanwhile
+      const int j = g.col[e0 + k0 + kChunk + kk];
+      xn = g.x[j];
+      yn = g.y[j];
+    }
+    double* tab = &T[kk * S::TABLE + t * TW];
+    if (have) {
+      const double dx = wrap_axis(xj - xi, g.box.Lx, px);
+      const double dy = wrap_axis(yj - yi, g.box.Ly, py);
+      const double xs = dx * hinv, ys = dy * hinv;
+      const double z = (t == 0 || t == 2) ? xs : ys;
+      if (t < 2) {
+        double v = 1.0;
+        tab[0] = 1.0;
+#pragma unroll
+        for (int a = 1; a <= M; ++a) {
+          v = v * z * (1.0 / static_cast<double>(a));  // z^a / a!
+          tab[a] = v;
+        }
+      } else {
+        const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+        double h0 = 1.0, h1 = z;
+        tab[0] = psi;
+        if (M >= 1) tab[1] = psi * z;
+#pragma unroll
+        for (int a = 1; a < M; ++a) {
+          const double h2 = z * h1 - static_cast<double>(a) * h0;
+          h0 = h1;
+          h1 = h2;
+          tab[a + 1] = psi * h2;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a <= M; ++a) tab[a] = 0.0;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int ks = 0; ks < kChunk / 4; ++ks) {
+      const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
+      double av[NB], bv[NB];
+#pragma unroll
+      for (int P = 0; P < NB; ++P) {
+        const int oa = ea[P] >= 0 ? ea[P] : S::ZERO, ob = ea[P] >= 0 ? TW + eb[P] : S::ZERO;
+        const int oc = ea[P] >= 0 ? 2 * TW + ea[P] : S::ZERO;
+        const int od = ea[P] >= 0 ? 3 * TW + eb[P] : S::ZERO;
+        av[P] = tk[oa] * tk[ob];
+        bv[P] = tk[oc] * tk[od];
+      }
+#pragma unroll
+      for (int P = 0; P < NB; ++P)
+#pragma unroll
+        for (int Q = 0; Q < NB; ++Q)
+          acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
+    }
+    lds_barrier();
+  }
+
+  // ---- 2: rows of [M~ | C~] into registers ----------------------------------
+  // element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
+  double a[RC];
+  double* strip = sm.buf;
+#pragma unroll
+  for (int Q = 0; Q < NB; ++Q) {
+#pragma unroll
+    for (int P = 0; P < NB; ++P)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        strip[(P * 16 + (lane >> 4) + 4 * v) * S::SS + (lane & 15)] = acc[P][Q][v];
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (Q * 16 + j < N) a[Q * 16 + j] = (lane < N) ? strip[lane * S::SS + j] : 0.0;
+    lds_barrier();
+  }
+  int ra = 0, rb = 0;
+  if (lane < N) exponents_of(lane, ra, rb);
+  {
+    double c[LABFM_NUM_OPS];
+    rhs_row(ra, rb, M, h, c);
+#pragma unroll
+    for (int d = 0; d < LABFM_NUM_OPS; ++d) a[N + d] = (lane < N) ? c[d] : 0.0;
+    if (RC > N + LABFM_NUM_OPS) a[RC - 1] = 0.0;
+  }
+
+  // ---- 3: LU with partial pivoting, rows in place ---------------------------
+  // (no early exit: a zero pivot sets `singular`, a wave-uniform flag, and
+  // the remaining columns are skipped, so the loop unrolls fully and the rows
+  // stay in registers)
+  bool used = lane >= N;  // rows beyond n never pivot and are never updated
+  int mycol = used ? N : -1;
+  double myinv = 0.0;
+  bool singular = false;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if (!singular) {
+      const unsigned mag = static_cast<unsigned>(
+          static_cast<unsigned long long>(__double_as_longlong(fabs(a[c]))) >> 32);
+      const unsigned key = used ? 0u : ((mag & ~63u) | static_cast<unsigned>(63 - lane));
+      const unsigned kmax = wave_max_u32(key);
+      const int p = 63 - static_cast<int>(kmax & 63u);
+      // the pivot row is broadcast lane to scalar registers (v_readlane):
+      // through LDS every lane would pull the whole row (64 lanes x 8 bytes
+      // per value), more than the CU's shared LDS data path feeds
+      const double ucc = readlane_f64(a[c], p);
+      singular = (kmax == 0u || ucc == 0.0 || !isfinite(ucc));  // wave-uniform
+      if (!singular) {
+        // 1 / u_cc: hardware reciprocal and one Newton step
+        double inv = __builtin_amdgcn_rcp(ucc);
+        inv = fma(inv, fma(-ucc, inv, 1.0), inv);
+        if (lane == p) {
+          used = true;
+          mycol = c;
+          myinv = inv;
+        }
+        const double l = used ? 0.0 : a[c] * inv;
+        // 8 values of the pivot row read out first, then their updates (a
+        // read lane's result is used a few instructions later, not at once)
+#pragma unroll
+        for (int j0 = c + 1; j0 < RC; j0 += 8) {
+          double u[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) u[t] = (j0 + t < RC) ? readlane_f64(a[j0 + t], p) : 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (j0 + t < RC) {
+              a[j0 + t] = fma(-l, u[t], a[j0 + t]);
+              pin(a[j0 + t]);
+            }
+        }
+      }
+    }
+  }
+
+  int st = (K < N) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
+  if (!singular) {
+    // ---- 4: back substitution ------------------------------------------------
+    // the pivot lane of column c forms x_c = y_c / u_cc, writes it into Psi
+    // (LDS) and every lane reads it from that lane (the value is consumed at
+    // once, so nothing uniform stays live across columns)
+    double* psi_t = sm.buf;  // Psi[q][d], q < n (the strips are done)
+#pragma unroll
+    for (int c = N - 1; c >= 0; --c) {
+      const unsigned long long b = __builtin_amdgcn_ballot_w64(mycol == c);
+      const int pc = static_cast<int>(__builtin_ctzll(b));
+      const double coef = (mycol < c) ? a[c] : 0.0;
+      double xv[LABFM_NUM_OPS];
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) xv[d] = a[N + d] * myinv;
+      if (lane == pc) {
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; d += 2)
+          *reinterpret_cast<double2*>(&psi_t[c * LABFM_NUM_OPS + d]) =
+              make_double2(xv[d], xv[d + 1]);
+      }
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d)
+        a[N + d] = fma(-coef, readlane_f64(xv[d], pc), a[N + d]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    lds_barrier();
+
+    // ---- 5: weights, filter calibration, row sums, first moments -------------
+    // one lane per neighbour; Psi read from LDS a row at a time (the lanes'
+    // reads of one row are a broadcast)
+    const double kf = 2.0 * M_PI / (3.0 * s);
+    double f0 = 0.0;
+    double rs[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double mo[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const long long s32 = w32_stride(g.nnz);
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      const int k = k0 + lane;
+      // Psi's offset passes through an empty asm statement every pass, so the
+      // compiler does not hoist all of its reads out of the loop (n * 6
+      // values held in registers)
+      int pbase = 0;
+      asm volatile("" : "+v"(pbase));
+      if (k < K) {
+        const int j = g.col[e0 + k];
+        const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
+        const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+        const double xs = dx * hinv, ys = dy * hinv;
+        const double psi = wendland_c2(sqrt(xs * xs + ys * ys));
+        double hx[M + 1], hy[M + 1];
+        hx[0] = psi;
+        hy[0] = 1.0;
+        hx[1] = psi * xs;
+        hy[1] = ys;
+        {
+          double a0 = 1.0, a1 = xs, b0 = 1.0, b1 = ys;
+#pragma unroll
+          for (int q = 1; q < M; ++q) {
+            const double a2 = xs * a1 - static_cast<double>(q) * a0;
+            const double b2 = ys * b1 - static_cast<double>(q) * b0;
+            a0 = a1;
+            a1 = a2;
+            b0 = b1;
+            b1 = b2;
+            hx[q + 1] = psi * a2;
+            hy[q + 1] = b2;
+          }
+        }
+        double wd[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        // Psi row q in registers, row q+1 read from LDS while q is used
+        double r0[LABFM_NUM_OPS], r1[LABFM_NUM_OPS];
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) r0[d] = psi_t[pbase + d];
+#pragma unroll
+        for (int deg = 1, q = 0; deg <= M; ++deg) {
+#pragma unroll
+          for (int bb = 0; bb <= deg; ++bb, ++q) {
+            if (q + 1 < N) {
+#pragma unroll
+              for (int d = 0; d < LABFM_NUM_OPS; ++d)
+                r1[d] = psi_t[pbase + (q + 1) * LABFM_NUM_OPS + d];
+            }
+            const double Wq = hx[deg - bb] * hy[bb];
+#pragma unroll
+            for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+              wd[d] = fma(Wq, r0[d], wd[d]);
+              pin(wd[d]);
+            }
+#pragma unroll
+            for (int d = 0; d < LABFM_NUM_OPS; ++d) r0[d] = r1[d];
+          }
+        }
+        const long long e = e0 + k;
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+          g.w[d * g.nnz + e] = wd[d];
+          if (g.w32) g.w32[d * s32 + e] = static_cast<float>(wd[d]);
+          rs[d] += wd[d];
+        }
+#pragma unroll
+        for (int d = LABFM_OP_L; d <= LABFM_OP_XY; ++d) {
+          const double v32 = static_cast<double>(static_cast<float>(wd[d]));
+          mo[2 * (d - LABFM_OP_L)] += v32 * dx;
+          mo[2 * (d - LABFM_OP_L) + 1] += v32 * dy;
+        }
+        f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * wd[LABFM_OP_HYP];
+      }
+    }
+    f0 = group_sum<64>(f0);
+#pragma unroll
+    for (int d = 0; d < LABFM_NUM_OPS; ++d) rs[d] = group_sum<64>(rs[d]);
+#pragma unroll
+    for (int q = 0; q < kMoments; ++q) mo[q] = group_sum<64>(mo[q]);
+    if (lane == 0) {
+      if (g.mom32)
+#pragma unroll
+        for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = static_cast<float>(mo[q]);
+      const bool bad = !isfinite(f0) || f0 == 0.0;
+      g.kappa[i] = bad ? 0.0 : 2.0 / (3.0 * f0);
+      if (st == LABFM_NODE_OK && bad) st = LABFM_NODE_BAD_FILTER;
+      g.status[i] = static_cast<int8_t>(st);
+      if (g.rowsum)
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = rs[d];
+    }
+  } else {
+    const long long s32 = w32_stride(g.nnz);
+    for (int k = lane; k < K; k += 64)
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        g.w[d * g.nnz + e0 + k] = 0.0;
+        if (g.w32) g.w32[d * s32 + e0 + k] = 0.0f;
+      }
+    if (lane == 0) {
+      g.kappa[i] = 0.0;
+      g.status[i] = LABFM_NODE_SINGULAR;
+      if (g.rowsum)
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = 0.0;
+      if (g.mom32)
+        for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = 0.0f;
+    }
+  }
+}
+
+template <int M>
+hipError_t launch_rows(const BuildArgs& g, const int* list, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(build_rows_kernel<M>, dim3(count), dim3(64), 0, st, g, list, count);
+  return hipGetLastError();
+}
+
+// Calls fn(integral_constant<M>) for an order 1..9 of the rows kernel.
+template <class Fn>
+hipError_t with_rows_order(int m, Fn&& fn) {
+  using std::integral_constant;
+  switch (m) {
+    case 1: return fn(integral_constant<int, 1>{});
+    case 2: return fn(integral_constant<int, 2>{});
+    case 3: return fn(integral_constant<int, 3>{});
+    case 4: return fn(integral_constant<int, 4>{});
+    case 5: return fn(integral_constant<int, 5>{});
+    case 6: return fn(integral_constant<int, 6>{});
+    case 7: return fn(integral_constant<int, 7>{});
+    case 8: return fn(integral_constant<int, 8>{});
+    case 9: return fn(integral_constant<int, 9>{});
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---- stencil optimisation (section "Stencil optimisation") -------------------
@@ -1405,7 +1878,7 @@ hipError_t with_mmax(int mmax, Fn&& fn) {
 }
 
 std::mutex g_build_mutex;
-labfm_build_config g_build_cfg = {LABFM_BUILD_BLOCK, 0};
+labfm_build_config g_build_cfg = {LABFM_BUILD_ROWS, 0};
 
 }  // namespace
 }  // namespace labfm
@@ -1414,9 +1887,9 @@ using namespace labfm;
 
 extern "C" int labfm_set_build_config(const labfm_build_config* cfg) {
   clear_error();
-  labfm_build_config c{LABFM_BUILD_BLOCK, 0};
+  labfm_build_config c{LABFM_BUILD_ROWS, 0};
   if (cfg) {
-    LABFM_REQUIRE(cfg->mode >= LABFM_BUILD_WAVE && cfg->mode <= LABFM_BUILD_BUCKETED,
+    LABFM_REQUIRE(cfg->mode >= LABFM_BUILD_WAVE && cfg->mode <= LABFM_BUILD_ROWS,
                   "set_build_config: unknown mode %d", cfg->mode);
     LABFM_REQUIRE(cfg->workgroups_per_cu >= 0, "set_build_config: negative workgroups_per_cu");
     c = *cfg;
@@ -1492,6 +1965,24 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
                                                      st);
       });
       break;
+    case LABFM_BUILD_ROWS: {
+      // orders 1..9: one wavefront per node with the rows in registers, one
+      // launch per order present; order 10 and out-of-range orders (buckets
+      // of orders 15..10, and the bucket of orders <= 0): the workgroup kernel
+      for (int m = 1; m <= 9 && e == hipSuccess; ++m) {
+        const int b = 15 - m;
+        const int first = starts[b], count = starts[b + 1] - first;
+        if (count <= 0) continue;
+        e = with_rows_order(m, [&](auto M) {
+          return launch_rows<decltype(M)::value>(g, list + first, count, st);
+        });
+      }
+      if (e == hipSuccess && starts[6] > starts[0])
+        e = launch_block<10>(g, list + starts[0], starts[6] - starts[0], st);
+      if (e == hipSuccess && starts[16] > starts[15])
+        e = launch_block<10>(g, list + starts[15], starts[16] - starts[15], st);
+      break;
+    }
     case LABFM_BUILD_BUCKETED: {
       // one launch per order class, each with the template of the highest
       // order present in it
@@ -1620,18 +2111,19 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   clear_error();
   LABFM_REQUIRE(best && best_ms, "tune_build: null output");
   hipStream_t st = as_stream(stream_);
-  const labfm_build_config cands[5] = {{LABFM_BUILD_WAVE, 0},
+  const labfm_build_config cands[6] = {{LABFM_BUILD_WAVE, 0},
                                        {LABFM_BUILD_BLOCK, 0},
                                        {LABFM_BUILD_PERSISTENT, 0},
                                        {LABFM_BUILD_PERSISTENT, 2},
-                                       {LABFM_BUILD_BUCKETED, 0}};
+                                       {LABFM_BUILD_BUCKETED, 0},
+                                       {LABFM_BUILD_ROWS, 0}};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   LABFM_HIP(hipEventCreate(&e0));
   LABFM_HIP(hipEventCreate(&e1));
   double bms = 1e300;
   labfm_build_config bc = cands[1];
   int rc = LABFM_OK;
-  for (int k = 0; k < 5 && rc == LABFM_OK; ++k) {
+  for (int k = 0; k < 6 && rc == LABFM_OK; ++k) {
     labfm_set_build_config(&cands[k]);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess)

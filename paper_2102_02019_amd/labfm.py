@@ -24,7 +24,7 @@ F64, F32W, F32_COMP = 0, 1, 2
 
 KERNEL_STAGE, KERNEL_FILTER, KERNEL_APPLY = 0, 1, 2
 NUM_MOM32 = 6  # rows of the float32-weight first moments: (L,x) (L,y) (xx,x) (xx,y) (xy,x) (xy,y)
-BUILD_WAVE, BUILD_BLOCK, BUILD_PERSISTENT, BUILD_BUCKETED = 1, 2, 3, 4
+BUILD_WAVE, BUILD_BLOCK, BUILD_PERSISTENT, BUILD_BUCKETED, BUILD_ROWS = 1, 2, 3, 4, 5
 XCD_ORDER, STREAMING = 1, 2
 OK, ERR_ARG, ERR_HIP, ERR_CAPACITY, ERR_NONFINITE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 NODE_OK, NODE_SINGULAR, NODE_FEW_NEIGHBOURS, NODE_BAD_FILTER, NODE_BAD_ORDER = range(5)
@@ -110,6 +110,7 @@ class _Timing(ctypes.Structure):
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "labfm_last_error": (ctypes.c_char_p, []),
+    "labfm_w32_stride": (ctypes.c_int64, [ctypes.c_int64]),
     "labfm_version": (ctypes.c_char_p, []),
     "labfm_morton_order": (ctypes.c_int, [_P, _P, ctypes.c_int32, _Box, ctypes.c_double, _P, _P]),
     "labfm_build_neighbours": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _Box, _P, _P,
@@ -210,6 +211,18 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _w32_ptr(t: Optional[torch.Tensor]):
+    """Pointer of a float32 weight copy held as the (6, nnz) view of rows at
+    the padded stride labfm_w32_stride(nnz)."""
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 6:
+        raise ValueError("labfm expects float32 weights of shape (6, nnz) on the device")
+    if t.stride() != (w32_stride(t.shape[1]), 1):
+        raise ValueError("float32 weight rows must use the stride labfm_w32_stride(nnz)")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -256,7 +269,7 @@ class Operators:
     row_ptr: torch.Tensor
     col: torch.Tensor
     w: Optional[torch.Tensor]       # float64 (6, nnz)
-    w32: Optional[torch.Tensor]     # float32 (6, nnz)
+    w32: Optional[torch.Tensor]     # float32 (6, nnz) view of rows at labfm_w32_stride(nnz)
     kappa: torch.Tensor             # float64 (n,)
     mom32: Optional[torch.Tensor] = None  # float32 (6, n) first moments of w32
     rowsum: Optional[torch.Tensor] = None
@@ -287,10 +300,16 @@ class Operators:
             tp = ctypes.pointer(self._ctiles)
         return _Operators(self.n, self.nnz, _ptr(self.row_ptr).value, _ptr(self.col).value,
                           None if self.w is None else _ptr(self.w).value,
-                          None if self.w32 is None else _ptr(self.w32).value,
+                          None if self.w32 is None else _w32_ptr(self.w32).value,
                           None if self.mom32 is None else _ptr(self.mom32).value,
                           _ptr(self.kappa).value, tp,
                           None if self.wall_normal is None else _ptr(self.wall_normal).value)
+
+
+def w32_stride(nnz: int) -> int:
+    """Row stride of the float32 weight copy (labfm_w32_stride), at least 1
+    so that an empty set still gets a valid allocation."""
+    return max(1, int(lib().labfm_w32_stride(int(nnz))))
 
 
 def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
@@ -304,14 +323,16 @@ def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
         m = torch.full((n,), int(m), dtype=torch.int8, device=dev)
     # one extra element keeps the data pointer valid when nnz == 0
     w = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)[: 6 * nnz].view(6, nnz)
-    w32 = (torch.empty(6 * nnz + 1, dtype=torch.float32, device=dev)[: 6 * nnz].view(6, nnz)
+    # float32 rows at the library's padded stride (128-byte aligned rows); the
+    # operators keep the (6, nnz) view of it
+    w32 = (torch.empty((6, w32_stride(nnz)), dtype=torch.float32, device=dev)[:, :nnz]
            if f32 else None)
     mom32 = torch.empty((NUM_MOM32, n), dtype=torch.float32, device=dev) if f32 else None
     kappa = torch.empty(n, dtype=torch.float64, device=dev)
     rs = torch.empty((6, n), dtype=torch.float64, device=dev) if rowsum else None
     status = torch.empty(n, dtype=torch.int8, device=dev)
     args = (_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box), _ptr(row_ptr), _ptr(col),
-            nnz, _ptr(w), _ptr(w32), _ptr(mom32), _ptr(kappa), _ptr(rs), _ptr(status))
+            nnz, _ptr(w), _w32_ptr(w32), _ptr(mom32), _ptr(kappa), _ptr(rs), _ptr(status))
     if tune:
         best, ms = _BuildConfig(), ctypes.c_double(0.0)
         _check(lib().labfm_tune_build(*args, ctypes.byref(best), ctypes.byref(ms), _stream()))
@@ -339,8 +360,8 @@ def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
     wn = torch.empty((n, 2), dtype=torch.float64, device=x.device)
     _check(lib().labfm_boundary_weights(
         _ptr(x), _ptr(y), _ptr(h), _ptr(s), n, _box(box), _ptr(ops.row_ptr), _ptr(ops.col),
-        ops.nnz, ctypes.byref(st), _ptr(ops.w), _ptr(ops.w32), _ptr(ops.mom32), _ptr(ops.kappa),
-        _ptr(ops.status), _ptr(wn), _stream()))
+        ops.nnz, ctypes.byref(st), _ptr(ops.w), _w32_ptr(ops.w32), _ptr(ops.mom32),
+        _ptr(ops.kappa), _ptr(ops.status), _ptr(wn), _stream()))
     ops.wall_normal = wn
     return ops
 
@@ -581,7 +602,7 @@ def mfma_f64_rate(iters: int = 4096, device=None) -> float:
 
 def set_build_config(mode: int = 0, workgroups_per_cu: int = 0) -> None:
     """Choose how build_weights spreads nodes over the GPU (mode 0 restores
-    the default, one workgroup per node)."""
+    the default, BUILD_ROWS)."""
     if mode == 0:
         _check(lib().labfm_set_build_config(None))
     else:

@@ -205,10 +205,11 @@ def test_graded_holes_1m_build(dev):
     finally:
         labfm.set_build_config(0)
     assert mode in (labfm.BUILD_WAVE, labfm.BUILD_BLOCK, labfm.BUILD_PERSISTENT,
-                    labfm.BUILD_BUCKETED)
+                    labfm.BUILD_BUCKETED, labfm.BUILD_ROWS)
     assert torch.equal(pers.w, blk.w) and torch.equal(pers.status, blk.status)
-    if mode != labfm.BUILD_WAVE:
+    if mode not in (labfm.BUILD_WAVE, labfm.BUILD_ROWS):  # the two with their own LU
         assert torch.equal(ops.w, blk.w)
+    assert torch.equal(ops.status, blk.status)
     st = blk.status.cpu().numpy()
     assert set(np.unique(st)) <= {labfm.NODE_OK, labfm.NODE_FEW_NEIGHBOURS}
     assert (st == labfm.NODE_FEW_NEIGHBOURS).mean() < 0.01

@@ -28,8 +28,11 @@ def T(a, dev):
 
 
 def _outputs(n, nnz, dev):
+    from paper_2102_02019_amd import labfm
+
     return {"w": torch.full((6, nnz), np.nan, dtype=torch.float64, device=dev),
-            "w32": torch.full((6, nnz), np.nan, dtype=torch.float32, device=dev),
+            "w32": torch.full((6, labfm.w32_stride(nnz)), np.nan, dtype=torch.float32,
+                              device=dev),
             "mom32": torch.full((6, n), np.nan, dtype=torch.float32, device=dev),
             "kappa": torch.full((n,), np.nan, dtype=torch.float64, device=dev),
             "rowsum": torch.full((6, n), np.nan, dtype=torch.float64, device=dev),
@@ -55,7 +58,7 @@ def _case(nodes, dev):
     return arr, rp, col
 
 
-@pytest.mark.parametrize("mode", [2, 3])  # workgroup per node; persistent (uses the counter)
+@pytest.mark.parametrize("mode", [2, 3, 5])  # workgroup per node; persistent (uses the counter); rows
 def test_noalloc_build_matches_allocating_build(dev, mode):
     from paper_2102_02019_amd import labfm
 
