@@ -1334,7 +1334,9 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       const int p = 63 - static_cast<int>(kmax & 63u);
       // the pivot row is broadcast lane to scalar registers (v_readlane):
       // through LDS every lane would pull the whole row (64 lanes x 8 bytes
-      // per value), more than the CU's shared LDS data path feeds
+      // per value), more than the CU's shared LDS data path feeds (measured:
+      // 8.7 ms against 7.3 ms at m = 8, 262,144 nodes; splitting each row
+      // between the two ways was slower than read lanes alone)
       const double ucc = readlane_f64(a[c], p);
       singular = (kmax == 0u || ucc == 0.0 || !isfinite(ucc));  // wave-uniform
       if (!singular) {
