@@ -25,6 +25,10 @@ stream_copy: measured bandwidth of plain streaming kernels on 1 GiB (a
 f32w, f32_comp: the same job with float32 weights (float64 sums, or
          float32 compensated Dot2 sums), speedup and per-field error against
          the float64 run;
+mixed_precision_4m: the 4,194,304-node workload (m = 8): float64 build,
+         then its 500 graph-replayed RK steps in float64 and in compensated
+         float32, run rates, stage-kernel fractions, per-field and
+         per-operator errors of the float32 run against the float64 run;
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
 
 Launch shapes of the gather kernels are autotuned on the workload before the
@@ -61,6 +65,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+def log(msg: str) -> None:
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +80,8 @@ def parse():
                     help="RK steps per job (default: the workload's run length)")
     ap.add_argument("--no-f32", action="store_true", help="skip the float32 compensated job")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-4m", action="store_true",
+                    help="skip the 4,194,304-node mixed-precision leg (tg2048_m8)")
     ap.add_argument("--launch-shapes", default=None,
                     help="pin the gather kernels' launch shapes instead of tuning: JSON "
                          "{prec: {kernel: [lanes_per_node, flags]}} inline, or the path of a "
@@ -172,6 +183,7 @@ def main():
     precs = {"f64": labfm.F64, "f32w": labfm.F32W, "f32_comp": labfm.F32_COMP}
     if args.no_f32:
         precs = {"f64": labfm.F64}
+    log(f"workload {wl.name}: {N} nodes, m = {wl.m}, {rk_steps} RK steps per job")
     if args.launch_shapes:
         tuned = pinned_shapes(args.launch_shapes, precs, labfm)
     else:
@@ -195,6 +207,7 @@ def main():
                           "rk_steps": rk_steps, "stage_kernels": names, "launch_shapes": tuned}))
         return
 
+    log(f"launch shapes {json.dumps(tuned)}; timing {args.steps} float64 jobs")
     ops, tms, sec = timed(labfm.F64, args.steps, args.warmup)
     q64 = q.clone()
     nnz = ops.nnz
@@ -223,6 +236,7 @@ def main():
     graph_s = time.perf_counter() - tg0
     graph_equal = bool(torch.equal(q, q64))
 
+    log("graph replay done; build and copy rates")
     build = build_rate(labfm, torch, np, nodes, x, y, h, s, m)
     stream = stream_copy_rate(torch, dev)
 
@@ -269,6 +283,7 @@ def main():
     for prec, key in ((labfm.F32W, "f32w"), (labfm.F32_COMP, "f32_comp")):
         if args.no_f32:
             break
+        log(f"timing {args.steps} {key} jobs")
         ops32, tms32, sec32 = timed(prec, args.steps, args.warmup)
         q32 = q.clone()
         st32 = sum(t["stage_ms"] for t in tms32) / sum(t["stage_launches"] for t in tms32)
@@ -300,7 +315,12 @@ def main():
             "operator_rel_err_vs_f64": op_err,
         }
 
+    if not args.no_f32 and not args.no_4m:
+        log("mixed-precision leg on 4,194,304 nodes")
+        out["mixed_precision_4m"] = mixed_precision_bench(inputs, labfm, torch, np, dev)
+
     if not args.no_cpu_baseline:
+        log("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(wl, rk_steps, N)
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(wl, rk_steps, N)
 
@@ -720,6 +740,90 @@ def lagrangian_cpu_baseline(inputs, np, wl, n_side=32, n_steps=1):
                       f"5 builds, 4 stages, filter"}
 
 
+def mixed_precision_bench(inputs, labfm, torch, np, dev, eager_steps=10):
+    """The mixed-precision workload: 2048^2 = 4,194,304 jittered nodes, m = 8,
+    weights built in float64 and stored in float32 as well, then the
+    workload's 500 filtered RK steps replayed from a HIP graph in float64 and
+    in the compensated float32 precision (Dot2 sums), each timed once around
+    the replay (after a short captured warm-up). The per-field relative
+    errors of the float32 run are taken against the float64 run of the same
+    weights, and the per-operator errors of one application on the initial
+    velocity. Stage-kernel durations come from a short eager run with HIP
+    events. The launch shapes are the ones installed for the main job."""
+    wl = inputs.TG2048_M8
+    nodes = wl.nodes()
+    N = nodes.n
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    x, y, h, s, m = T(nodes.x), T(nodes.y), T(nodes.h), T(nodes.s), T(nodes.m)
+    q0 = T(np.concatenate([np.log(rho), u, v]))
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+    ev[1].record()
+    ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True)
+    ev[2].record()
+    torch.cuda.synchronize()
+    nnz = ops.nnz
+    kbar = nnz / N
+    K = np.diff(rp.cpu().numpy()).astype(np.float64)
+    gflop = float(np.sum(build_flops(float(wl.m), K))) / 1e9
+    build_ms = ev[1].elapsed_time(ev[2])
+    statuses = np.bincount(ops.status.cpu().numpy().astype(np.int64), minlength=5).tolist()
+    ws = labfm.rk_workspace(N, dev)
+    q = torch.empty_like(q0)
+    dt = labfm.time_step(q0, s, prm.c2, prm.mu, visc=wl.visc_coef)
+    res, state = {}, {}
+    for key, prec, bpn in (("f64", labfm.F64, 44.0 * kbar + 104.0),
+                           ("f32_comp", labfm.F32_COMP, 24.0 * kbar + 104.0)):
+        log(f"{wl.name} {key}: {eager_steps} eager steps, then {wl.steps} graph-replayed steps")
+        q.copy_(q0)
+        tm = labfm.rk_step(q, ops, prm, dt, eager_steps, prec=prec, workspace=ws, timing=True)
+        st = tm["stage_ms"] / tm["stage_launches"]
+        fl = tm["filter_ms"] / max(1, tm["filter_launches"])
+        q.copy_(q0)
+        labfm.rk_step(q, ops, prm, dt, 5, prec=prec, workspace=ws, use_graph=True)
+        q.copy_(q0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        labfm.rk_step(q, ops, prm, dt, wl.steps, prec=prec, workspace=ws, use_graph=True)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        state[key] = q.view(3, -1).cpu().numpy()
+        gbs = bpn * N / (st * 1e-3) / 1e9
+        res[key] = {"node_updates_per_s": N * 4 * wl.steps / sec,
+                    "ms_per_rk_step": sec * 1e3 / wl.steps,
+                    "run_s": sec,
+                    "stage_mean_launch_ms": st, "filter_mean_launch_ms": fl,
+                    "bytes_per_node_stage": bpn,
+                    "stage_achieved_GBs": gbs, "stage_frac": gbs / HBM_PEAK_GBS}
+    a64, a32 = state["f64"], state["f32_comp"]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    res["f32_comp"]["final_state_rel_err_vs_f64"] = {
+        "rho": rel(np.exp(a32[0]), np.exp(a64[0])), "u": rel(a32[1], a64[1]),
+        "v": rel(a32[2], a64[2])}
+    uu = q0[N:2 * N].contiguous()
+    d64 = labfm.apply_operators(ops, uu, 0x1F, labfm.F64).cpu().numpy()
+    d32 = labfm.apply_operators(ops, uu, 0x1F, labfm.F32_COMP).cpu().numpy()
+    res["f32_comp"]["operator_rel_err_vs_f64"] = {
+        labfm.OPS[d]: rel(d32[d], d64[d]) for d in range(5)}
+    res["f32_comp"]["speedup_run"] = res["f64"]["run_s"] / res["f32_comp"]["run_s"]
+    res["f32_comp"]["speedup_stage_kernel"] = (res["f64"]["stage_mean_launch_ms"]
+                                               / res["f32_comp"]["stage_mean_launch_ms"])
+    decay = math.exp(-2.0 * prm.mu * dt * wl.steps)
+    return {"workload": wl.name, "nodes": N, "order_m": wl.m, "mean_neighbours": round(kbar, 2),
+            "rk_steps": wl.steps, "dt": dt, "graph_replayed": True,
+            "neighbours_ms": ev[0].elapsed_time(ev[1]), "build_ms": build_ms,
+            "build_TFLOPs": gflop / build_ms, "node_status_histogram": statuses,
+            "f64_u_decay_vs_exact": float(np.abs(a64[1]).max() / (np.abs(u).max() * decay)),
+            **res}
+
+
 def pinned_shapes(spec, precs, labfm):
     """Install the launch shapes given on the command line (see --launch-shapes)."""
     text = spec if spec.lstrip().startswith("{") else open(spec).read().strip().splitlines()[-1]
@@ -740,17 +844,20 @@ def pinned_shapes(spec, precs, labfm):
 def stage_kernel_name(shape, tiled, prec_tag, nnz=None):
     """Name pattern of the fused RK stage kernel for a tuned launch shape
     (lanes per node, flags); '*' joins the parts of a profiler's name. With
-    tiles the library launches the pair-loading variant for float64 and the
-    compensated float32 precision (its last template argument tells an odd
+    tiles the library launches the quad-loading variant for the float32
+    weights (four edges per lane load, rows at the padded stride) and the
+    pair-loading variant for float64 (its last template argument tells an odd
     stencil count)."""
     lpn, flags = shape[0], shape[1]
     kern = "rk_stage_kernel"
     tail = ""
     if tiled:
-        packed = prec_tag in ("F64", "F32Comp")
-        kern = "rk_stage_tiled_packed_kernel" if packed else "rk_stage_tiled_kernel"
-        if packed and nnz is not None:
-            tail = ", " + ("true" if nnz % 2 else "false")
+        if prec_tag in ("F32W", "F32Comp"):
+            kern = "rk_stage_tiled_quad_kernel"
+        else:
+            kern = "rk_stage_tiled_packed_kernel"
+            if nnz is not None:
+                tail = ", " + ("true" if nnz % 2 else "false")
     return f"{kern}<{lpn}, {flags}, *{prec_tag}{tail}>"
 
 

@@ -15,6 +15,13 @@
  *    Work is enqueued on that stream and the call returns without waiting,
  *    except where a host output is documented (then the call synchronises
  *    the stream before returning).
+ *  - No call allocates device memory. A call that needs temporary device
+ *    memory takes a caller workspace (`workspace`, `workspace_bytes`): a
+ *    device buffer of at least the size its labfm_*_workspace_bytes
+ *    function returns, overwritten by the call; a smaller or NULL workspace
+ *    is LABFM_ERR_ARG. The call's work on `stream` may still use the
+ *    workspace after it returns: keep it allocated until that work is done
+ *    (stream-ordered reuse, as torch's caching allocator does, is safe).
  *  - Every call returns LABFM_OK (0) or a negative status; none throws across
  *    the ABI. labfm_last_error() returns a message for the calling thread's
  *    most recent failure.
@@ -199,10 +206,13 @@ const char* labfm_version(void);
  *   x, y   float64[n] positions.
  *   cell   cell side, > 0, at most 2^21 cells per axis.
  *   perm   int32[n] output.
- * Synchronises; allocates temporaries (keys and the radix sort's storage).
+ *   workspace  labfm_morton_workspace_bytes(n) bytes (keys and the radix
+ *              sort's storage).
+ * Synchronises.
  */
+size_t labfm_morton_workspace_bytes(int32_t n);
 int labfm_morton_order(const double* x, const double* y, int32_t n, labfm_box box, double cell,
-                       int32_t* perm, void* stream);
+                       int32_t* perm, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Stencil search (stencil definition of the paper's LABFM section): node j
@@ -215,16 +225,20 @@ int labfm_morton_order(const double* x, const double* y, int32_t n, labfm_box bo
  *   row_ptr   int32[n+1] output.
  *   col       int32[capacity] output, or NULL to query the size.
  *   nnz_out   host: receives the number of CSR entries.
+ *   workspace labfm_neighbours_workspace_bytes(n) bytes (the cell table,
+ *             the per-node counts and rocPRIM's temporary storage).
  *
- * Synchronises the stream. Returns LABFM_ERR_CAPACITY (with *nnz_out set
- * and row_ptr filled) when col is NULL or capacity < nnz. Returns
- * LABFM_ERR_ARG when a periodic axis is shorter than 4 max(h) (the nearest
- * image would not be unique) or n <= 0. Temporary device memory is
- * allocated and freed inside the call.
+ * Synchronises the stream once (to size the CSR); the fill of col is
+ * enqueued after that. Returns LABFM_ERR_CAPACITY (with *nnz_out set and
+ * row_ptr filled) when col is NULL or capacity < nnz. Returns LABFM_ERR_ARG
+ * when a periodic axis is shorter than 4 max(h) (the nearest image would not
+ * be unique) or n <= 0.
  */
+size_t labfm_neighbours_workspace_bytes(int32_t n);
 int labfm_build_neighbours(const double* x, const double* y, const double* h, int32_t n,
                            labfm_box box, int32_t* row_ptr, int32_t* col, int64_t capacity,
-                           int64_t* nnz_out, void* stream);
+                           int64_t* nnz_out, void* workspace, size_t workspace_bytes,
+                           void* stream);
 
 /*
  * Weight construction (sections "LABFM" and "New ABFs"; eqs. disc_form,
@@ -244,14 +258,22 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  *   x, y, h, s  float64[n]; s = local node spacing (filter calibration).
  *   order_m     int8[n], each in 1..10.
  *   row_ptr, col, nnz  CSR from labfm_build_neighbours.
- *   w       float64[6*nnz] output.
- *   w32     float32[6*labfm_w32_stride(nnz)] output copy (rows of the padded
+ *   op_mask which operators' weights are written (bit d for labfm_op d;
+ *           0x3F = all six, which labfm_apply_operators, labfm_ns_rhs and
+ *           labfm_rk_step expect). The k = popcount(op_mask) selected
+ *           operators fill rows 0..k-1 of w, w32 and rowsum in labfm_op
+ *           order. kappa is always formed (from the filter weights, computed
+ *           whether or not bit 5 is set).
+ *   w       float64[k*nnz] output.
+ *   w32     float32[k*labfm_w32_stride(nnz)] output copy (rows of the padded
  *           stride), or NULL.
  *   mom32   float32[LABFM_NUM_MOM32*n] output first moments of w32 (see
- *           LABFM_NUM_MOM32), or NULL.
+ *           LABFM_NUM_MOM32), or NULL; needs L, xx and xy in op_mask.
  *   kappa   float64[n] output.
- *   rowsum  float64[6*n] output sum_j w^d_ji, or NULL.
+ *   rowsum  float64[k*n] output sum_j w^d_ji, or NULL.
  *   status  int8[n] output, LABFM_NODE_* per node.
+ *   workspace  labfm_build_workspace_bytes(n) bytes (the node list grouped
+ *           by order).
  *
  * Numerical failures and out-of-range orders are reported per node in
  * status (the call still returns LABFM_OK); such nodes get zero weights and
@@ -261,21 +283,24 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  * they are spread over the GPU (default LABFM_BUILD_ROWS: one wavefront per
  * node holding the system's rows in registers for orders up to 9, one
  * workgroup per node for order 10, from a work list grouped by order;
- * labfm_tune_build picks). Synchronises (it sizes its work list on the host)
- * and allocates a small work list.
+ * labfm_tune_build picks). Synchronises once (the launches are sized on the
+ * host from the order histogram); the build kernels are enqueued after that.
  */
+size_t labfm_build_workspace_bytes(int32_t n);
 int labfm_build_weights(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* order_m, int32_t n, labfm_box box,
                         const int32_t* row_ptr, const int32_t* col, int64_t nnz,
-                        double* w, float* w32, float* mom32, double* kappa, double* rowsum,
-                        int8_t* status, void* stream);
+                        uint32_t op_mask, double* w, float* w32, float* mom32, double* kappa,
+                        double* rowsum, int8_t* status, void* workspace,
+                        size_t workspace_bytes, void* stream);
 
 /*
- * labfm_build_weights for callers that cannot allocate device memory (tight
- * serving or time-stepping loops, harnesses that forbid hipMalloc): the same
- * arguments, kernels and results, with the work list held in a static
- * device array of the library instead of a temporary allocation. The call
- * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * labfm_build_weights for callers that cannot allocate device memory, not
+ * even a workspace (tight serving or time-stepping loops, harnesses that
+ * forbid hipMalloc): the same arguments (without the workspace), kernels
+ * and results, with the work list held in a static device array of the
+ * library. The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).
  *
  *   n  at most LABFM_NOALLOC_MAX_NODES; larger sets return LABFM_ERR_ARG
  *      (use labfm_build_weights).
@@ -283,15 +308,15 @@ int labfm_build_weights(const double* x, const double* y, const double* h, const
  * GPU the library runs on until the process ends, and is shared by all calls
  * on that GPU: calls that overlap on one GPU (from several host threads or
  * streams) race and must be serialised by the caller. Each call clears what
- * it uses; nothing is kept between calls. Synchronises, like
+ * it uses; nothing is kept between calls. Synchronises once, like
  * labfm_build_weights.
  */
 #define LABFM_NOALLOC_MAX_NODES 4194304
 int labfm_build_weights_noalloc(const double* x, const double* y, const double* h,
                                 const double* s, const int8_t* order_m, int32_t n, labfm_box box,
                                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
-                                double* w, float* w32, float* mom32, double* kappa,
-                                double* rowsum, int8_t* status, void* stream);
+                                uint32_t op_mask, double* w, float* w32, float* mom32,
+                                double* kappa, double* rowsum, int8_t* status, void* stream);
 
 /*
  * Stencil optimisation (section "Stencil optimisation"): for every node, the
@@ -321,8 +346,9 @@ int labfm_build_weights_noalloc(const double* x, const double* y, const double* 
  *   h_out              float64[n] output scales.
  *   iters              int32[n] output k with h_out = h0 shrink^k (by repeated
  *                      multiplication), or NULL.
- * Nodes with orders outside 1..10 keep h0. Synchronises; allocates a small
- * work list.
+ *   workspace          labfm_build_workspace_bytes(n) bytes (the node list).
+ * Nodes with orders outside 1..10 keep h0. Synchronises once (to size the
+ * launch).
  */
 typedef struct {
   double shrink;    /* factor applied to h per accepted step (paper: 0.99) */
@@ -335,7 +361,7 @@ int labfm_optimise_stencils(const double* x, const double* y, const double* h0, 
                             const int8_t* order_m, int32_t n, labfm_box box,
                             const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                             const labfm_stencil_opt_params* prm, double* h_out, int32_t* iters,
-                            void* stream);
+                            void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Boundary strips (section "Boundaries", subsection "Boundary
@@ -388,16 +414,19 @@ typedef struct {
  *                 zero), LABFM_NODE_BAD_FILTER; wall nodes otherwise
  *                 LABFM_NODE_OK.
  *   wall_normal   float64[2n] output: n at wall nodes, (0, 0) elsewhere.
+ *   workspace     labfm_boundary_workspace_bytes(n) bytes (the per-node map
+ *                 of strip levels and columns).
  *
  * Returns LABFM_ERR_ARG for a node index outside 0..n-1, a node listed twice
  * or a normal that is not of unit length (checked on the host: the call copies
- * the columns back and synchronises). Allocates a temporary per-node map.
+ * the columns back and synchronises).
  */
+size_t labfm_boundary_workspace_bytes(int32_t n);
 int labfm_boundary_weights(const double* x, const double* y, const double* h, const double* s,
                            int32_t n, labfm_box box, const int32_t* row_ptr, const int32_t* col,
                            int64_t nnz, const labfm_strips* strips, double* w, float* w32,
                            float* mom32, double* kappa, int8_t* status, double* wall_normal,
-                           void* stream);
+                           void* workspace, size_t workspace_bytes, void* stream);
 
 /* How labfm_build_weights distributes nodes over the GPU. */
 enum {
@@ -420,16 +449,32 @@ typedef struct {
 int labfm_set_build_config(const labfm_build_config* cfg);
 int labfm_get_build_config(labfm_build_config* cfg);
 
-/* Autotuner of the build: runs labfm_build_weights with every distribution
- * on the given node set (same arguments and outputs), installs the fastest
- * as the process-wide setting and reports it (best_ms: its duration,
- * measured with HIP events on `stream`). The outputs hold the weights built
- * with the chosen distribution. Synchronises. */
+/*
+ * Autotuner of the build: runs labfm_build_weights with every distribution
+ * on the given node set (same arguments, outputs and workspace), installs
+ * the fastest as the process-wide setting and reports it (best_ms: its
+ * duration, measured with HIP events on `stream`). The outputs hold the
+ * weights built with the chosen distribution. Synchronises.
+ *
+ *   cache_path  host string: a tune cache file, or NULL/"" for the file named
+ *               by the LABFM_TUNE_CACHE environment variable (no cache when
+ *               that is unset too). The cache is a JSON object of entries
+ *               "key": [a, b, ms]; a build's key names the device (its
+ *               architecture and compute units), n, nnz, the node count of
+ *               each order, op_mask and which of w32 and rowsum are written.
+ *               On a hit the cached distribution is installed and the
+ *               weights are built once with it; otherwise the tuned choice
+ *               is added to the file (written to a temporary file, then
+ *               renamed over it; LABFM_ERR_ARG if that fails).
+ *   from_cache  host, or NULL: 1 when the choice came from the cache.
+ */
 int labfm_tune_build(const double* x, const double* y, const double* h, const double* s,
                      const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
-                     const int32_t* col, int64_t nnz, double* w, float* w32, float* mom32,
-                     double* kappa, double* rowsum, int8_t* status, labfm_build_config* best,
-                     double* best_ms, void* stream);
+                     const int32_t* col, int64_t nnz, uint32_t op_mask, double* w, float* w32,
+                     float* mom32, double* kappa, double* rowsum, int8_t* status,
+                     void* workspace, size_t workspace_bytes, const char* cache_path,
+                     labfm_build_config* best, double* best_ms, int32_t* from_cache,
+                     void* stream);
 
 /*
  * Operator application, eq. general_do: for each selected operator d (bit d
@@ -455,9 +500,12 @@ int labfm_apply_operators(const labfm_operators* ops, uint32_t op_mask, const do
  *   s       float64[n] node spacing.
  *   conv_coef, visc_coef  a and b, both > 0.
  *   dt_out  host: receives dt. Synchronises the stream.
+ *   workspace  labfm_time_step_workspace_bytes() bytes (per-block minima).
  */
+size_t labfm_time_step_workspace_bytes(void);
 int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
-                    double conv_coef, double visc_coef, double* dt_out, void* stream);
+                    double conv_coef, double visc_coef, double* dt_out, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /*
  * Right-hand side of the isothermal Navier-Stokes equations (eq. icns) in
@@ -497,13 +545,21 @@ int labfm_set_launch_config(int32_t kernel, labfm_prec prec, const labfm_launch_
  *
  *   q          float64[3n] state the stage kernel reads (not modified).
  *   workspace  labfm_rk_workspace_bytes(n) bytes (overwritten).
+ *   cache_path host string: a tune cache file, or NULL/"" for the file named
+ *              by LABFM_TUNE_CACHE (no cache when that is unset too); the
+ *              format is that of labfm_tune_build. The three kernels' keys
+ *              name the kernel, prec, the device, n, nnz and whether tiles
+ *              and wall normals are set. When all three are cached their
+ *              shapes are installed without timing anything; otherwise the
+ *              tuned shapes are added to the file.
  *   best       host, labfm_launch_config[3] in labfm_kernel order.
  *   best_ms    host, double[3]: mean launch time of each chosen shape.
+ *   from_cache host, or NULL: 1 when the shapes came from the cache.
  * Synchronises the stream.
  */
 int labfm_tune(const labfm_operators* ops, const double* q, labfm_prec prec, int32_t reps,
-               void* workspace, size_t workspace_bytes, labfm_launch_config* best,
-               double* best_ms, void* stream);
+               void* workspace, size_t workspace_bytes, const char* cache_path,
+               labfm_launch_config* best, double* best_ms, int32_t* from_cache, void* stream);
 
 /* Number of node tiles of a node set of n nodes. */
 int32_t labfm_tile_count(int32_t n);
@@ -516,12 +572,15 @@ int32_t labfm_tile_count(int32_t n);
  *   halo_idx     int32[labfm_tile_count(n) * LABFM_TILE_HALO_MAX] output.
  *   lcol         uint16[nnz] output.
  *   max_halo_out host: largest halo.
+ *   workspace    labfm_tiles_workspace_bytes() bytes (two counters).
  * Synchronises. Returns LABFM_ERR_CAPACITY if a tile's halo exceeds
  * LABFM_TILE_HALO_MAX nodes (then use the operators without tiles).
  */
+size_t labfm_tiles_workspace_bytes(void);
 int labfm_build_tiles(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz,
                       int32_t* halo_count, int32_t* halo_idx, uint16_t* lcol,
-                      int32_t* max_halo_out, void* stream);
+                      int32_t* max_halo_out, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /* Transposed stencils for the adjoint: for each node j the forward edges
  * i -> j (j in N_i), grouped by j in ascending i, with a copy of their
@@ -535,11 +594,12 @@ typedef struct {
 
 /*
  * Builds tptr, tsrc and tw from the operators' CSR and float64 weights
- * (a reordering of data, no arithmetic). Synchronises; allocates and frees
- * temporaries.
+ * (a reordering of data, no arithmetic). workspace:
+ * labfm_transpose_workspace_bytes(n, nnz) bytes (counts, cursors, slots).
  */
+size_t labfm_transpose_workspace_bytes(int32_t n, int64_t nnz);
 int labfm_build_transpose(const labfm_operators* ops, int32_t* tptr, int32_t* tsrc, double* tw,
-                          void* stream);
+                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* Bytes of workspace labfm_rk_adjoint needs. */
 size_t labfm_adjoint_workspace_bytes(int32_t n, int32_t n_steps, int32_t ckpt_every);

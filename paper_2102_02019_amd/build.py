@@ -30,7 +30,7 @@ HIP_FLAGS = [
 # default cost limit of a requested full unroll stops short at order 8.
 FILE_FLAGS = {"weights.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
                                "-mllvm", "-pragma-unroll-threshold=1000000"]}
-SOURCES = ["api.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
+SOURCES = ["api.cpp", "tune_cache.cpp", "neighbours.hip", "weights.hip", "operators.hip", "tiles.hip", "adjoint.hip",
            "boundaries.hip", "lagrangian.hip", "morton.hip", "probe.hip"]
 
 

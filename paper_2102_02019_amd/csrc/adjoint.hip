@@ -276,17 +276,24 @@ long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 using namespace labfm;
 
+extern "C" size_t labfm_transpose_workspace_bytes(int32_t n, int64_t nnz) {
+  if (n <= 0 || nnz < 0) return 0;
+  return align256(sizeof(int) * (2 * (static_cast<size_t>(n) + 1) + static_cast<size_t>(nnz) + 1));
+}
+
 extern "C" int labfm_build_transpose(const labfm_operators* ops, int32_t* tptr, int32_t* tsrc,
-                                     double* tw, void* stream_) {
+                                     double* tw, void* workspace, size_t workspace_bytes,
+                                     void* stream_) {
   clear_error();
   LABFM_REQUIRE(ops && ops->n > 0 && ops->row_ptr && ops->w && tptr && tsrc && tw,
                 "build_transpose: bad arguments");
   const int n = ops->n;
   const long long nnz = ops->nnz;
   LABFM_REQUIRE(nnz == 0 || ops->col, "build_transpose: missing col");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_transpose_workspace_bytes(n, nnz),
+                  "build_transpose");
   hipStream_t st = as_stream(stream_);
-  int* tmp = nullptr;
-  LABFM_HIP(hipMalloc(&tmp, sizeof(int) * (2 * (static_cast<size_t>(n) + 1) + nnz + 1)));
+  int* tmp = static_cast<int*>(workspace);
   int* cnt = tmp;
   int* cursor = cnt + n + 1;
   int* tslot = cursor + n + 1;
@@ -302,8 +309,6 @@ extern "C" int labfm_build_transpose(const labfm_operators* ops, int32_t* tptr, 
     hipLaunchKernelGGL(tweights_kernel, dim3(ge), dim3(T), 0, st, ops->w, tslot, nnz, tw);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(st);  // temporaries are freed below
-  (void)hipFree(tmp);
   LABFM_HIP(e);
   return LABFM_OK;
 }

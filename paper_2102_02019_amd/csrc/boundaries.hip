@@ -297,12 +297,17 @@ __global__ void __launch_bounds__(64 * kWaves) boundary_weights_kernel(BoundaryA
 
 using namespace labfm;
 
+extern "C" size_t labfm_boundary_workspace_bytes(int32_t n) {
+  return n > 0 ? align256((sizeof(int) + 1) * static_cast<size_t>(n) + 16) : 0;
+}
+
 extern "C" int labfm_boundary_weights(const double* x, const double* y, const double* h,
                                       const double* s, int32_t n, labfm_box box,
                                       const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                                       const labfm_strips* strips, double* w, float* w32,
                                       float* mom32, double* kappa, int8_t* status,
-                                      double* wall_normal, void* stream_) {
+                                      double* wall_normal, void* workspace,
+                                      size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0 && x && y && h && s && row_ptr && (col || nnz == 0) && strips && w &&
                     kappa && status && wall_normal,
@@ -310,6 +315,8 @@ extern "C" int labfm_boundary_weights(const double* x, const double* y, const do
   LABFM_REQUIRE(strips->count >= 0, "boundary_weights: negative column count");
   LABFM_REQUIRE(strips->count == 0 || (strips->column && strips->normal),
                 "boundary_weights: null column or normal array");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_boundary_workspace_bytes(n),
+                  "boundary_weights");
   hipStream_t st = as_stream(stream_);
   const int count = strips->count;
 
@@ -335,14 +342,7 @@ extern "C" int labfm_boundary_weights(const double* x, const double* y, const do
     LABFM_REQUIRE(std::fabs(len - 1.0) < 1e-12, "boundary_weights: normal %d is not unit", k);
   }
 
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  } tmp;
-  LABFM_HIP(hipMalloc(&tmp.p, (sizeof(int) + 1) * static_cast<size_t>(n) + 16));
-  int* colidx = static_cast<int*>(tmp.p);
+  int* colidx = static_cast<int*>(workspace);
   signed char* level = reinterpret_cast<signed char*>(colidx + n);
   LABFM_HIP(hipMemsetAsync(level, 0xFF, static_cast<size_t>(n), st));  // -1: off the strips
   LABFM_HIP(hipMemsetAsync(colidx, 0, sizeof(int) * static_cast<size_t>(n), st));
@@ -379,6 +379,5 @@ extern "C" int labfm_boundary_weights(const double* x, const double* y, const do
   hipLaunchKernelGGL(boundary_weights_kernel, dim3(blocks_for(items, kWaves)), dim3(64 * kWaves),
                      0, st, a);
   LABFM_LAUNCHED();
-  // the temporary map is freed on return; hipFree waits for the kernels
   return LABFM_OK;
 }

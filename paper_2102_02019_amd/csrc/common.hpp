@@ -41,6 +41,18 @@ void clear_error();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Rounds a byte count up to a multiple of 256 (the alignment of every part
+// of a caller workspace).
+inline size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// Checks a caller workspace (device pointer and size in bytes) against what
+// a call needs.
+#define LABFM_WORKSPACE(ptr, have, need, what)                                    \
+  LABFM_REQUIRE((ptr) != nullptr && (have) >= (need),                            \
+                "%s: a workspace of %zu bytes is required (got %zu bytes at %p)", \
+                what, static_cast<size_t>(need), static_cast<size_t>(have),      \
+                static_cast<const void*>(ptr))
+
 inline unsigned blocks_for(int64_t work, int per_block) {
   return static_cast<unsigned>((work + per_block - 1) / per_block);
 }

@@ -147,7 +147,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t reg, rowptr, col, w, kappa, status, counts, total;
+  size_t reg, rowptr, col, w, kappa, status, counts, setup, total;
 };
 
 Layout layout_of(int32_t n, int64_t cap) {
@@ -159,7 +159,10 @@ Layout layout_of(int32_t n, int64_t cap) {
   L.kappa = align_up(sizeof(double) * static_cast<size_t>(n));
   L.status = align_up(static_cast<size_t>(n));
   L.counts = align_up(sizeof(unsigned long long) * kStatusKinds);
-  L.total = 3 * L.reg + L.rowptr + L.col + L.w + L.kappa + L.status + L.counts;
+  // the stencil search's and the weight build's workspaces (one after the
+  // other on the stream, so they share one area)
+  L.setup = align_up(std::max(labfm_neighbours_workspace_bytes(n), labfm_build_workspace_bytes(n)));
+  L.total = 3 * L.reg + L.rowptr + L.col + L.w + L.kappa + L.status + L.counts + L.setup;
   return L;
 }
 
@@ -212,6 +215,8 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
   int8_t* status = reinterpret_cast<int8_t*>(base + off);
   off += L.status;
   unsigned long long* counts = reinterpret_cast<unsigned long long*>(base + off);
+  off += L.counts;
+  void* setup_ws = base + off;
   LABFM_HIP(hipMemsetAsync(counts, 0, sizeof(unsigned long long) * kStatusKinds, st));
   const unsigned count_grid =
       static_cast<unsigned>(std::min<long long>(1024, (static_cast<long long>(n) + 255) / 256));
@@ -225,7 +230,7 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
     const auto t0 = std::chrono::steady_clock::now();
     int64_t got = 0;
     int r = labfm_build_neighbours(R.x, R.y, h, n, box, row_ptr, col, nnz_capacity, &got,
-                                   stream_);
+                                   setup_ws, L.setup, stream_);
     if (r == LABFM_ERR_CAPACITY) {
       set_error("lagrangian_step: %lld stencil entries exceed the capacity %lld",
                 static_cast<long long>(got), static_cast<long long>(nnz_capacity));
@@ -233,8 +238,9 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
     }
     if (r != LABFM_OK) return r;
     nnz = got;
-    r = labfm_build_weights(R.x, R.y, h, s, order_m, n, box, row_ptr, col, nnz, w, nullptr,
-                            nullptr, kappa, nullptr, status, stream_);
+    r = labfm_build_weights(R.x, R.y, h, s, order_m, n, box, row_ptr, col, nnz, 0x3F, w,
+                            nullptr, nullptr, kappa, nullptr, status, setup_ws, L.setup,
+                            stream_);
     if (r != LABFM_OK) return r;
     hipLaunchKernelGGL(count_status_kernel, dim3(count_grid), dim3(256), 0, st, status, n,
                        counts);
@@ -242,6 +248,9 @@ extern "C" int labfm_lagrangian_step(double* x, double* y, double* q, const doub
       set_error("lagrangian_step: status count launch failed");
       return LABFM_ERR_HIP;
     }
+    // the build's kernels run asynchronously after its sizing step; wait
+    // for them so that build_ms covers them
+    LABFM_HIP(hipStreamSynchronize(st));
     const auto t1 = std::chrono::steady_clock::now();
     sx.builds += 1;
     sx.build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();

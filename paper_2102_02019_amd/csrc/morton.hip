@@ -6,6 +6,7 @@
 // (rocPRIM) carries the node indices along.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -49,12 +50,42 @@ __global__ void morton_key_kernel(const double* __restrict__ x, const double* __
 
 using namespace labfm;
 
+namespace {
+
+// Bytes of rocPRIM's radix sort of n (64-bit key, int) pairs over bits
+// [0, end_bit).
+size_t morton_sort_bytes(int32_t n, unsigned end_bit) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, bytes, static_cast<unsigned long long*>(nullptr),
+                                  static_cast<unsigned long long*>(nullptr),
+                                  static_cast<int*>(nullptr), static_cast<int*>(nullptr),
+                                  static_cast<size_t>(n), 0u, end_bit, hipStream_t{});
+  return bytes;
+}
+
+// Workspace layout: keys in, keys out (n each), node indices (n), then the
+// sort's storage (sized for the widest key, 42 bits).
+size_t morton_keys_bytes(int32_t n) {
+  return align256((2 * sizeof(unsigned long long) + sizeof(int)) * static_cast<size_t>(n));
+}
+
+}  // namespace
+
+extern "C" size_t labfm_morton_workspace_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  size_t sort = 0;
+  for (unsigned b = 1; b <= 42; ++b) sort = std::max(sort, morton_sort_bytes(n, b));
+  return morton_keys_bytes(n) + align256(std::max<size_t>(sort, 1));
+}
+
 extern "C" int labfm_morton_order(const double* x, const double* y, int32_t n, labfm_box box,
-                                  double cell, int32_t* perm, void* stream_) {
+                                  double cell, int32_t* perm, void* workspace,
+                                  size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0 && x && y && perm, "morton_order: null or empty argument");
   LABFM_REQUIRE(cell > 0.0 && std::isfinite(cell), "morton_order: cell must be positive");
   LABFM_REQUIRE(box.Lx > 0.0 && box.Ly > 0.0, "morton_order: box sides must be positive");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_morton_workspace_bytes(n), "morton_order");
   const double fx = std::ceil(box.Lx / cell), fy = std::ceil(box.Ly / cell);
   LABFM_REQUIRE(fx <= 2097152.0 && fy <= 2097152.0,
                 "morton_order: at most 2^21 cells per axis (cell too small for the box)");
@@ -65,25 +96,16 @@ extern "C" int labfm_morton_order(const double* x, const double* y, int32_t n, l
   const unsigned end_bit = static_cast<unsigned>(std::max(2 * bits, 1));
   hipStream_t st = as_stream(stream_);
 
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  } tmp, sort_tmp;
   const size_t nn = static_cast<size_t>(n);
-  LABFM_HIP(hipMalloc(&tmp.p, 2 * sizeof(unsigned long long) * nn + sizeof(int) * nn + 256));
-  unsigned long long* k_in = static_cast<unsigned long long*>(tmp.p);
+  unsigned long long* k_in = static_cast<unsigned long long*>(workspace);
   unsigned long long* k_out = k_in + nn;
   int* idx = reinterpret_cast<int*>(k_out + nn);
+  void* sort_tmp = static_cast<char*>(workspace) + morton_keys_bytes(n);
+  size_t bytes = workspace_bytes - morton_keys_bytes(n);
   hipLaunchKernelGGL(morton_key_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, x, y, n, cell,
                      ncx, ncy, k_in, idx);
   LABFM_LAUNCHED();
-  size_t bytes = 0;
-  LABFM_HIP(rocprim::radix_sort_pairs(nullptr, bytes, k_in, k_out, idx,
-                                      reinterpret_cast<int*>(perm), n, 0u, end_bit, st));
-  LABFM_HIP(hipMalloc(&sort_tmp.p, bytes > 0 ? bytes : 1));
-  LABFM_HIP(rocprim::radix_sort_pairs(sort_tmp.p, bytes, k_in, k_out, idx,
+  LABFM_HIP(rocprim::radix_sort_pairs(sort_tmp, bytes, k_in, k_out, idx,
                                       reinterpret_cast<int*>(perm), n, 0u, end_bit, st));
   LABFM_HIP(hipStreamSynchronize(st));
   return LABFM_OK;

@@ -169,53 +169,67 @@ __global__ void fill_kernel(const double* __restrict__ x, const double* __restri
   }
 }
 
+
+// Sizes of the search's workspace for n nodes: the cell table has at most
+// 4n + 65 entries (see the cell-count cap below), and one temporary storage
+// area serves every rocPRIM reduction, scan and sort of the search.
+size_t neighbours_temp_bytes(int32_t n) {
+  const size_t nscan = 4 * static_cast<size_t>(n) + 65;
+  size_t tb_max = 0, tb_sum = 0, tb_scan = 0, tb_sort = 0;
+  hipStream_t st{};
+  (void)rocprim::reduce(nullptr, tb_max, static_cast<const double*>(nullptr),
+                        static_cast<double*>(nullptr), 0.0, static_cast<size_t>(n), FMax(), st);
+  (void)rocprim::reduce(nullptr, tb_sum,
+                        rocprim::make_transform_iterator(static_cast<const int*>(nullptr), ToI64()),
+                        static_cast<long long*>(nullptr), 0LL, static_cast<size_t>(n),
+                        rocprim::plus<long long>(), st);
+  (void)rocprim::exclusive_scan(nullptr, tb_scan, static_cast<const int*>(nullptr),
+                                static_cast<int*>(nullptr), 0, nscan, rocprim::plus<int>(), st);
+  for (unsigned b = 1; b <= 31; ++b) {
+    size_t t = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, t, static_cast<const int*>(nullptr),
+                                    static_cast<int*>(nullptr), rocprim::counting_iterator<int>(0),
+                                    static_cast<int*>(nullptr), static_cast<size_t>(n), 0u, b, st);
+    tb_sort = std::max(tb_sort, t);
+  }
+  return align256(std::max(std::max(tb_max, tb_sort), std::max(tb_sum, tb_scan)));
+}
+
+// the per-node and per-cell integer arrays (cell table at its cap)
+size_t neighbours_table_bytes(int32_t n) {
+  const size_t ncell_max = 4 * static_cast<size_t>(n) + 64;
+  return align256(sizeof(int) * (static_cast<size_t>(n) * 4 + 1 + 2 * (ncell_max + 1)));
+}
+
 }  // namespace
 }  // namespace labfm
 
 using namespace labfm;
 
+extern "C" size_t labfm_neighbours_workspace_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  return 256 + neighbours_temp_bytes(n) + neighbours_table_bytes(n);
+}
+
 extern "C" int labfm_build_neighbours(const double* x, const double* y, const double* h,
                                       int32_t n, labfm_box box, int32_t* row_ptr, int32_t* col,
-                                      int64_t capacity, int64_t* nnz_out, void* stream_) {
+                                      int64_t capacity, int64_t* nnz_out, void* workspace,
+                                      size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0, "build_neighbours: n must be positive (got %d)", n);
   LABFM_REQUIRE(x && y && h && row_ptr && nnz_out, "build_neighbours: null pointer argument");
   LABFM_REQUIRE(box.Lx > 0.0 && box.Ly > 0.0, "build_neighbours: box sides must be positive");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_neighbours_workspace_bytes(n),
+                  "build_neighbours");
   hipStream_t st = as_stream(stream_);
 
-  // Temporary device memory, released on every exit path below.
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  };
-  // device-wide reductions and scans (rocPRIM): their temporary storage is
-  // sized once for the largest of them (the cell table has at most 4n + 65
-  // entries, see below)
-  const size_t nscan = 4 * static_cast<size_t>(n) + 65;
-  size_t tb_max = 0, tb_sum = 0, tb_scan = 0;
-  LABFM_HIP(rocprim::reduce(nullptr, tb_max, h, static_cast<double*>(nullptr), 0.0,
-                            static_cast<size_t>(n), FMax(), st));
-  LABFM_HIP(rocprim::reduce(nullptr, tb_sum,
-                            rocprim::make_transform_iterator(static_cast<const int*>(nullptr), ToI64()),
-                            static_cast<long long*>(nullptr), 0LL, static_cast<size_t>(n),
-                            rocprim::plus<long long>(), st));
-  LABFM_HIP(rocprim::exclusive_scan(nullptr, tb_scan, static_cast<const int*>(nullptr),
-                                    static_cast<int*>(nullptr), 0, nscan, rocprim::plus<int>(),
-                                    st));
-  size_t tb_sort = 0;
-  LABFM_HIP(rocprim::radix_sort_pairs(nullptr, tb_sort, static_cast<const int*>(nullptr),
-                                      static_cast<int*>(nullptr), rocprim::counting_iterator<int>(0),
-                                      static_cast<int*>(nullptr), static_cast<size_t>(n), 0u, 31u,
-                                      st));
-  size_t tbytes = std::max(std::max(tb_max, tb_sort), std::max(tb_sum, tb_scan));
-  tbytes = (tbytes + 255) & ~static_cast<size_t>(255);
-  Temp t_small;
-  LABFM_HIP(hipMalloc(&t_small.p, 256 + tbytes));
-  double* d_hmax = static_cast<double*>(t_small.p);
-  long long* d_total = reinterpret_cast<long long*>(static_cast<char*>(t_small.p) + 16);
-  void* d_temp = static_cast<char*>(t_small.p) + 256;
+  // workspace: [0, 256) the two reduction results, then the rocPRIM
+  // temporary storage, then the integer tables
+  size_t tbytes = neighbours_temp_bytes(n);
+  char* base = static_cast<char*>(workspace);
+  double* d_hmax = reinterpret_cast<double*>(base);
+  long long* d_total = reinterpret_cast<long long*>(base + 16);
+  void* d_temp = base + 256;
 
   LABFM_HIP(rocprim::reduce(d_temp, tbytes, h, d_hmax, 0.0, static_cast<size_t>(n), FMax(), st));
   double hmax = 0.0;
@@ -245,10 +259,7 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   g.py = box.periodic_y ? 1 : 0;
   const int ncell = g.ncx * g.ncy;
 
-  Temp t_big;
-  const size_t bytes = sizeof(int) * (static_cast<size_t>(n) * 4 + 1 + 2 * (ncell + 1));
-  LABFM_HIP(hipMalloc(&t_big.p, bytes));
-  int* cell_of = static_cast<int*>(t_big.p);
+  int* cell_of = reinterpret_cast<int*>(base + 256 + tbytes);
   int* cell_nodes = cell_of + n;
   int* counts = cell_nodes + n;              // n + 1 (the last stays 0)
   int* cell_count = counts + n + 1;          // ncell + 1 (the last stays 0)
@@ -293,7 +304,5 @@ extern "C" int labfm_build_neighbours(const double* x, const double* y, const do
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, T)), dim3(T), 0, st, x, y, h, n, g, cell_of,
                      cell_start, cell_nodes, row_ptr, col);
   LABFM_LAUNCHED();
-  // the temporaries are freed on return; make sure the fill has consumed them
-  LABFM_HIP(hipStreamSynchronize(st));
   return LABFM_OK;
 }

@@ -1,6 +1,10 @@
 // C entry points of operator application, the right-hand side, the time
 // step, the RK time loop and the launch-shape tuner.
+#include <string>
+#include <vector>
+
 #include "gather.hpp"
+#include "tune_cache.hpp"
 
 namespace labfm {
 std::mutex g_cfg_mutex;
@@ -45,17 +49,21 @@ extern "C" int labfm_ns_rhs(const double* q, const labfm_operators* ops,
   return LABFM_OK;
 }
 
+extern "C" size_t labfm_time_step_workspace_bytes(void) {
+  return align256(sizeof(double) * (1024 + 1));
+}
+
 extern "C" int labfm_time_step(const double* q, const double* s, int32_t n, double c2, double mu,
                                double conv_coef, double visc_coef, double* dt_out,
-                               void* stream_) {
+                               void* workspace, size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0 && q && s && dt_out, "time_step: bad arguments");
   LABFM_REQUIRE(c2 > 0.0 && mu > 0.0, "time_step: c2 and mu must be positive");
   LABFM_REQUIRE(conv_coef > 0.0 && visc_coef > 0.0, "time_step: coefficients must be positive");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_time_step_workspace_bytes(), "time_step");
   hipStream_t st = as_stream(stream_);
   const int nb = static_cast<int>(std::min<long long>(1024, blocks_for(n, kRedThreads)));
-  double* d = nullptr;
-  LABFM_HIP(hipMalloc(&d, sizeof(double) * (nb + 1)));
+  double* d = static_cast<double*>(workspace);
   hipLaunchKernelGGL(dt_partial_kernel, dim3(nb), dim3(kRedThreads), 0, st, q, s, n, sqrt(c2),
                      mu, conv_coef, visc_coef, d);
   hipError_t e = hipGetLastError();
@@ -65,7 +73,6 @@ extern "C" int labfm_time_step(const double* q, const double* s, int32_t n, doub
   }
   if (e == hipSuccess) e = hipMemcpyAsync(dt_out, d + nb, sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(d);
   LABFM_HIP(e);
   return LABFM_OK;
 }
@@ -214,15 +221,47 @@ extern "C" int labfm_set_launch_config(int32_t kernel, labfm_prec prec,
 
 extern "C" int labfm_tune(const labfm_operators* ops, const double* q, labfm_prec prec,
                           int32_t reps, void* workspace, size_t workspace_bytes,
-                          labfm_launch_config* best, double* best_ms, void* stream_) {
+                          const char* cache_path, labfm_launch_config* best, double* best_ms,
+                          int32_t* from_cache, void* stream_) {
   clear_error();
   if (int r = check_ops(ops, prec, "tune")) return r;
   LABFM_REQUIRE(q && best && best_ms && reps > 0, "tune: bad arguments");
   const int n = ops->n;
-  LABFM_REQUIRE(workspace && workspace_bytes >= labfm_rk_workspace_bytes(n),
-                "tune: workspace of %zu bytes required", labfm_rk_workspace_bytes(n));
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_rk_workspace_bytes(n), "tune");
   LABFM_REQUIRE(ops->kappa, "tune: kappa required");
   hipStream_t st = as_stream(stream_);
+  if (from_cache) *from_cache = 0;
+
+  // the cache keys: kernel, precision, device and what the kernels' speed
+  // depends on (node count, stencil entries, tiles, wall equation)
+  static const char* const kKernelNames[3] = {"stage", "filter", "apply"};
+  const std::string path = tune_cache_path(cache_path);
+  std::vector<TuneEntry> entries(3);
+  {
+    const std::string common = "/prec" + std::to_string(static_cast<int>(prec)) + "/" +
+                               tune_device_key() + "/n" + std::to_string(n) + "/nnz" +
+                               std::to_string(static_cast<long long>(ops->nnz)) + "/tiles" +
+                               std::to_string(ops->tiles ? 1 : 0) + "/walls" +
+                               std::to_string(ops->wall_normal ? 1 : 0);
+    for (int k = 0; k < 3; ++k) entries[k].key = std::string("launch/") + kKernelNames[k] + common;
+  }
+  if (!path.empty() && tune_cache_lookup(path, entries)) {
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      const labfm_launch_config c{entries[k].a, entries[k].b};
+      ok = ok && valid_cfg(c);
+    }
+    if (ok) {
+      std::lock_guard<std::mutex> lock(g_cfg_mutex);
+      for (int k = 0; k < 3; ++k) {
+        best[k] = labfm_launch_config{entries[k].a, entries[k].b};
+        best_ms[k] = entries[k].ms;
+        g_cfg[k][prec_slot(prec)] = best[k];
+      }
+      if (from_cache) *from_cache = 1;
+      return LABFM_OK;
+    }
+  }
   double* out = static_cast<double*>(workspace);
   const Flow fl{1.0, 1.0, 0.0, 0.0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -279,5 +318,16 @@ extern "C" int labfm_tune(const labfm_operators* ops, const double* q, labfm_pre
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   LABFM_HIP(err);
+  if (path.empty()) return LABFM_OK;
+  for (int k = 0; k < 3; ++k) {
+    entries[k].a = best[k].lanes_per_node;
+    entries[k].b = best[k].flags;
+    entries[k].ms = best_ms[k];
+  }
+  std::string msg;
+  if (!tune_cache_store(path, entries, msg)) {
+    set_error("tune: tune cache: %s", msg.c_str());
+    return LABFM_ERR_ARG;
+  }
   return LABFM_OK;
 }

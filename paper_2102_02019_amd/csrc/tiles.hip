@@ -127,17 +127,20 @@ extern "C" int32_t labfm_tile_count(int32_t n) {
   return n > 0 ? (n + kTileNodes - 1) / kTileNodes : 0;
 }
 
+extern "C" size_t labfm_tiles_workspace_bytes(void) { return 256; }
+
 extern "C" int labfm_build_tiles(const int32_t* row_ptr, const int32_t* col, int32_t n,
                                  int64_t nnz, int32_t* halo_count, int32_t* halo_idx,
-                                 uint16_t* lcol, int32_t* max_halo_out, void* stream_) {
+                                 uint16_t* lcol, int32_t* max_halo_out, void* workspace,
+                                 size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0 && row_ptr && halo_count && halo_idx && max_halo_out,
                 "build_tiles: bad arguments");
   LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || (col && lcol)), "build_tiles: bad CSR arguments");
+  LABFM_WORKSPACE(workspace, workspace_bytes, labfm_tiles_workspace_bytes(), "build_tiles");
   hipStream_t st = as_stream(stream_);
   const int ntiles = labfm_tile_count(n);
-  int* d = nullptr;
-  LABFM_HIP(hipMalloc(&d, 2 * sizeof(int)));
+  int* d = static_cast<int*>(workspace);
   hipError_t e = hipMemsetAsync(d, 0, 2 * sizeof(int), st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(build_tiles_kernel, dim3(ntiles), dim3(kThreads), 0, st, row_ptr, col, n,
@@ -147,7 +150,6 @@ extern "C" int labfm_build_tiles(const int32_t* row_ptr, const int32_t* col, int
   int h[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(d);
   LABFM_HIP(e);
   *max_halo_out = h[0];
   if (h[1]) {

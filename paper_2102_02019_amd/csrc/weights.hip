@@ -20,9 +20,12 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <string>
+#include <vector>
 #include <type_traits>
 
 #include "common.hpp"
+#include "tune_cache.hpp"
 
 namespace labfm {
 namespace {
@@ -30,6 +33,23 @@ namespace {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = 16;  // neighbours per basis-table chunk
+
+// Output rows of an op_mask build: 3 bits per operator (labfm_op order) give
+// the row of w, w32 and rowsum that holds it; kNoRow marks an operator that
+// is not written (its weights are still formed, the filter's for kappa).
+constexpr int kNoRow = 7;
+__host__ __device__ constexpr int op_row(unsigned rows, int d) {
+  return static_cast<int>((rows >> (3 * d)) & 7u);
+}
+constexpr unsigned rows_of_mask(unsigned op_mask) {
+  unsigned rows = 0;
+  int r = 0;
+  for (int d = 0; d < LABFM_NUM_OPS; ++d)
+    rows |= static_cast<unsigned>((op_mask >> d) & 1u ? r++ : kNoRow) << (3 * d);
+  return rows;
+}
+static_assert(rows_of_mask(0x3F) == (0u | 1u << 3 | 2u << 6 | 3u << 9 | 4u << 12 | 5u << 15),
+              "the full mask keeps the labfm_op rows");
 
 // (a, b) exponents of moment index p (degree-major, decreasing power of x).
 __device__ __forceinline__ void exponents_of(int p, int& a, int& b) {
@@ -70,7 +90,7 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
                      const int* __restrict__ row_ptr, const int* __restrict__ col, long long nnz,
                      double* __restrict__ w, float* __restrict__ w32,
                      float* __restrict__ mom32, double* __restrict__ kappa,
-                     double* __restrict__ rowsum, int8_t* __restrict__ status) {
+                     double* __restrict__ rowsum, int8_t* __restrict__ status, unsigned rows) {
   using S = Shape<MMAX>;
   __shared__ double A[S::NMAX * S::LDA];
   __shared__ double T[kChunk * S::TABLE];
@@ -87,14 +107,17 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
   if (m < 1 || m > MMAX) {
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        w[d * nnz + e0 + k] = 0.0;
-        if (w32) w32[d * w32_stride(nnz) + e0 + k] = 0.0f;
+        const int r = op_row(rows, d);
+        if (r == kNoRow) continue;
+        w[r * nnz + e0 + k] = 0.0;
+        if (w32) w32[r * w32_stride(nnz) + e0 + k] = 0.0f;
       }
     if (lane == 0) {
       kappa[i] = 0.0;
       status[i] = LABFM_NODE_BAD_ORDER;
       if (rowsum)
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+        for (int d = 0; d < LABFM_NUM_OPS; ++d)
+          if (op_row(rows, d) != kNoRow) rowsum[op_row(rows, d) * (long long)nnodes + i] = 0.0;
       if (mom32)
         for (int k = 0; k < kMoments; ++k) mom32[k * (long long)nnodes + i] = 0.0f;
     }
@@ -295,14 +318,17 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
   if (singular) {
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        w[d * nnz + e0 + k] = 0.0;
-        if (w32) w32[d * w32_stride(nnz) + e0 + k] = 0.0f;
+        const int r = op_row(rows, d);
+        if (r == kNoRow) continue;
+        w[r * nnz + e0 + k] = 0.0;
+        if (w32) w32[r * w32_stride(nnz) + e0 + k] = 0.0f;
       }
     if (lane == 0) {
       kappa[i] = 0.0;
       status[i] = LABFM_NODE_SINGULAR;
       if (rowsum)
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = 0.0;
+        for (int d = 0; d < LABFM_NUM_OPS; ++d)
+          if (op_row(rows, d) != kNoRow) rowsum[op_row(rows, d) * (long long)nnodes + i] = 0.0;
       if (mom32)
         for (int k = 0; k < kMoments; ++k) mom32[k * (long long)nnodes + i] = 0.0f;
     }
@@ -372,8 +398,11 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
 #pragma unroll
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         const double v = psi * wd[d];
-        w[d * nnz + e] = v;
-        if (w32) w32[d * w32_stride(nnz) + e] = static_cast<float>(v);
+        const int r = op_row(rows, d);
+        if (r != kNoRow) {
+          w[r * nnz + e] = v;
+          if (w32) w32[r * w32_stride(nnz) + e] = static_cast<float>(v);
+        }
         rs[d] += v;
       }
 #pragma unroll
@@ -401,7 +430,8 @@ build_weights_kernel(const double* __restrict__ x, const double* __restrict__ y,
     status[i] = static_cast<int8_t>(st);
     if (rowsum)
 #pragma unroll
-      for (int d = 0; d < LABFM_NUM_OPS; ++d) rowsum[d * (long long)nnodes + i] = rs[d];
+      for (int d = 0; d < LABFM_NUM_OPS; ++d)
+        if (op_row(rows, d) != kNoRow) rowsum[op_row(rows, d) * (long long)nnodes + i] = rs[d];
   }
 }
 
@@ -434,6 +464,7 @@ struct BuildArgs {
   double* kappa;
   double* rowsum;
   int8_t* status;
+  unsigned rows;  // output row of each operator (op_row)
 };
 
 constexpr int kBlock = 256;
@@ -947,8 +978,11 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
       if (k < K) {
         if (half == 0) {
           const long long e = e0 + k;
-          g.w[dop * g.nnz + e] = acc;
-          if (g.w32) g.w32[dop * w32_stride(g.nnz) + e] = static_cast<float>(acc);
+          const int r = op_row(g.rows, dop);
+          if (r != kNoRow) {
+            g.w[r * g.nnz + e] = acc;
+            if (g.w32) g.w32[r * w32_stride(g.nnz) + e] = static_cast<float>(acc);
+          }
           if (dop == LABFM_OP_HYP) {
             f0 += (1.0 - nbx[2 * kChunk + slot] * nbx[3 * kChunk + slot]) * acc;
           } else if (dop >= LABFM_OP_L && dop <= LABFM_OP_XY) {
@@ -981,7 +1015,8 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
     double v = 0.0;
     for (int k = 0; k < kChunk; ++k) v += sm.part()[k * 16 + tid];
     if (tid < 6) {
-      if (g.rowsum) g.rowsum[tid * (long long)g.n + i] = v;
+      if (g.rowsum && op_row(g.rows, tid) != kNoRow)
+        g.rowsum[op_row(g.rows, tid) * (long long)g.n + i] = v;
     } else {
       const bool bad = !isfinite(v) || v == 0.0;
       g.kappa[i] = bad ? 0.0 : 2.0 / (3.0 * v);
@@ -994,14 +1029,17 @@ __device__ void build_node_block(int i_in, const BuildArgs& g, BlockSmem<MMAX>& 
   if (!valid || singular) {
     for (int k = tid; k < K; k += kBlock)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        g.w[d * g.nnz + e0 + k] = 0.0;
-        if (g.w32) g.w32[d * w32_stride(g.nnz) + e0 + k] = 0.0f;
+        const int r = op_row(g.rows, d);
+        if (r == kNoRow) continue;
+        g.w[r * g.nnz + e0 + k] = 0.0;
+        if (g.w32) g.w32[r * w32_stride(g.nnz) + e0 + k] = 0.0f;
       }
     if (tid == 0) {
       g.kappa[i] = 0.0;
       g.status[i] = valid ? LABFM_NODE_SINGULAR : LABFM_NODE_BAD_ORDER;
       if (g.rowsum)
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = 0.0;
+        for (int d = 0; d < LABFM_NUM_OPS; ++d)
+          if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = 0.0;
       if (g.mom32)
         for (int k = 0; k < kMoments; ++k) g.mom32[k * (long long)g.n + i] = 0.0f;
     }
@@ -1462,8 +1500,11 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
         const long long e = e0 + k;
 #pragma unroll
         for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-          g.w[d * g.nnz + e] = wd[d];
-          if (g.w32) g.w32[d * s32 + e] = static_cast<float>(wd[d]);
+          const int r = op_row(g.rows, d);
+          if (r != kNoRow) {
+            g.w[r * g.nnz + e] = wd[d];
+            if (g.w32) g.w32[r * s32 + e] = static_cast<float>(wd[d]);
+          }
           rs[d] += wd[d];
         }
 #pragma unroll
@@ -1490,20 +1531,24 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       g.status[i] = static_cast<int8_t>(st);
       if (g.rowsum)
 #pragma unroll
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = rs[d];
+        for (int d = 0; d < LABFM_NUM_OPS; ++d)
+          if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = rs[d];
     }
   } else {
     const long long s32 = w32_stride(g.nnz);
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        g.w[d * g.nnz + e0 + k] = 0.0;
-        if (g.w32) g.w32[d * s32 + e0 + k] = 0.0f;
+        const int r = op_row(g.rows, d);
+        if (r == kNoRow) continue;
+        g.w[r * g.nnz + e0 + k] = 0.0;
+        if (g.w32) g.w32[r * s32 + e0 + k] = 0.0f;
       }
     if (lane == 0) {
       g.kappa[i] = 0.0;
       g.status[i] = LABFM_NODE_SINGULAR;
       if (g.rowsum)
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) g.rowsum[d * (long long)g.n + i] = 0.0;
+        for (int d = 0; d < LABFM_NUM_OPS; ++d)
+          if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = 0.0;
       if (g.mom32)
         for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = 0.0f;
     }
@@ -1836,9 +1881,10 @@ template <int MMAX>
 hipError_t launch_build(const double* x, const double* y, const double* h, const double* s,
                         const int8_t* m, int n, labfm_box box, const int* row_ptr,
                         const int* col, long long nnz, double* w, float* w32, float* mom32,
-                        double* kappa, double* rowsum, int8_t* status, hipStream_t st) {
+                        double* kappa, double* rowsum, int8_t* status, unsigned rows,
+                        hipStream_t st) {
   hipLaunchKernelGGL(build_weights_kernel<MMAX>, dim3(n), dim3(64), 0, st, x, y, h, s, m, n, box,
-                     row_ptr, col, nnz, w, w32, mom32, kappa, rowsum, status);
+                     row_ptr, col, nnz, w, w32, mom32, kappa, rowsum, status, rows);
   return hipGetLastError();
 }
 
@@ -1918,18 +1964,12 @@ namespace {
 // by decreasing order. The area is cleared here; nothing else is kept.
 constexpr int kBuildWorkInts = 64;
 
-int build_weights_with(const double* x, const double* y, const double* h, const double* s,
-                       const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
-                       const int32_t* col, int64_t nnz, double* w, float* w32, float* mom32,
-                       double* kappa, double* rowsum, int8_t* status, int* work,
-                       hipStream_t st) {
-  labfm_build_config cfg;
-  {
-    std::lock_guard<std::mutex> lock(g_build_mutex);
-    cfg = g_build_cfg;
-  }
+// The node list of a build, grouped by order (bucket b holds order 15 - b,
+// orders outside 0..15 share the buckets of their nearest end), in `work`;
+// starts[b] (host) is bucket b's first position, starts[16] = n.
+// Synchronises the stream.
+int order_buckets(const int8_t* order_m, int32_t n, int* work, int starts[17], hipStream_t st) {
   int* hist = work;  // [0,16) cursors, [16,32) starts, [32] total
-  int* counter = hist + 40;
   int* list = hist + kBuildWorkInts;
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, hist, kBuildWorkInts);
   hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
@@ -1938,9 +1978,26 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
   hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
                      n, hist, list);
   LABFM_LAUNCHED();
-  int starts[17] = {0};
   LABFM_HIP(hipMemcpyAsync(starts, hist + 16, sizeof(int) * 17, hipMemcpyDeviceToHost, st));
   LABFM_HIP(hipStreamSynchronize(st));
+  return LABFM_OK;
+}
+
+int build_weights_with(const double* x, const double* y, const double* h, const double* s,
+                       const int8_t* order_m, int32_t n, labfm_box box, const int32_t* row_ptr,
+                       const int32_t* col, int64_t nnz, uint32_t op_mask, double* w, float* w32,
+                       float* mom32, double* kappa, double* rowsum, int8_t* status, int* work,
+                       hipStream_t st) {
+  labfm_build_config cfg;
+  {
+    std::lock_guard<std::mutex> lock(g_build_mutex);
+    cfg = g_build_cfg;
+  }
+  int* counter = work + 40;
+  int* list = work + kBuildWorkInts;
+  int starts[17] = {0};
+  if (int r = order_buckets(order_m, n, work, starts, st)) return r;
+  const unsigned rows = rows_of_mask(op_mask);
   // bucket b holds order 15 - b; the highest order present sets the template
   int mmax = 0;
   for (int b = 0; b < 16; ++b)
@@ -1949,13 +2006,13 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
       break;
     }
   const BuildArgs g{x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
-                    rowsum, status};
+                    rowsum, status, rows};
   hipError_t e = hipSuccess;
   switch (cfg.mode) {
     case LABFM_BUILD_WAVE:
       e = with_mmax(mmax, [&](auto M) {
         return launch_build<decltype(M)::value>(x, y, h, s, order_m, n, box, row_ptr, col, nnz,
-                                                w, w32, mom32, kappa, rowsum, status, st);
+                                                w, w32, mom32, kappa, rowsum, status, rows, st);
       });
       break;
     case LABFM_BUILD_BLOCK:
@@ -2011,20 +2068,27 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
       e = hipErrorInvalidValue;
   }
   LABFM_HIP(e);
-  // the work area may be released or reused once the call returns
-  LABFM_HIP(hipStreamSynchronize(st));
   return LABFM_OK;
 }
 
 int check_build_args(const double* x, const double* y, const double* h, const double* s,
                      const int8_t* order_m, int32_t n, const int32_t* row_ptr, const int32_t* col,
-                     int64_t nnz, const double* w, const double* kappa, const int8_t* status,
-                     const char* who) {
+                     int64_t nnz, uint32_t op_mask, const double* w, const float* mom32,
+                     const double* kappa, const int8_t* status, const char* who) {
   LABFM_REQUIRE(n > 0, "%s: n must be positive (got %d)", who, n);
   LABFM_REQUIRE(x && y && h && s && order_m && row_ptr && w && kappa && status,
                 "%s: null pointer argument", who);
   LABFM_REQUIRE(nnz >= 0 && (nnz == 0 || col), "%s: bad CSR arguments", who);
+  LABFM_REQUIRE(op_mask != 0 && (op_mask & ~0x3Fu) == 0,
+                "%s: op_mask 0x%x must select operators among the six (bits 0..5)", who, op_mask);
+  constexpr uint32_t kSecond = (1u << LABFM_OP_L) | (1u << LABFM_OP_XX) | (1u << LABFM_OP_XY);
+  LABFM_REQUIRE(!mom32 || (op_mask & kSecond) == kSecond,
+                "%s: mom32 needs the L, xx and xy operators in op_mask (got 0x%x)", who, op_mask);
   return LABFM_OK;
+}
+
+size_t build_work_bytes(int32_t n) {
+  return align256(sizeof(int) * (kBuildWorkInts + static_cast<size_t>(n)));
 }
 
 // Scratch of labfm_build_weights_noalloc: the work area of the largest node
@@ -2062,37 +2126,35 @@ int scratch_of_current_device(int** out) {
 }  // namespace
 }  // namespace labfm
 
+extern "C" size_t labfm_build_workspace_bytes(int32_t n) {
+  return n > 0 ? build_work_bytes(n) : 0;
+}
+
 extern "C" int labfm_build_weights(const double* x, const double* y, const double* h,
                                    const double* s, const int8_t* order_m, int32_t n,
                                    labfm_box box, const int32_t* row_ptr, const int32_t* col,
-                                   int64_t nnz, double* w, float* w32, float* mom32,
-                                   double* kappa, double* rowsum, int8_t* status,
-                                   void* stream_) {
+                                   int64_t nnz, uint32_t op_mask, double* w, float* w32,
+                                   float* mom32, double* kappa, double* rowsum, int8_t* status,
+                                   void* workspace, size_t workspace_bytes, void* stream_) {
   clear_error();
-  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, w, kappa, status,
-                               "build_weights"))
+  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, op_mask, w, mom32,
+                               kappa, status, "build_weights"))
     return r;
-  hipStream_t st = as_stream(stream_);
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  } tmp;
-  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (kBuildWorkInts + static_cast<size_t>(n))));
-  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
-                            rowsum, status, static_cast<int*>(tmp.p), st);
+  LABFM_WORKSPACE(workspace, workspace_bytes, build_work_bytes(n), "build_weights");
+  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w, w32,
+                            mom32, kappa, rowsum, status, static_cast<int*>(workspace),
+                            as_stream(stream_));
 }
 
 extern "C" int labfm_build_weights_noalloc(const double* x, const double* y, const double* h,
                                            const double* s, const int8_t* order_m, int32_t n,
                                            labfm_box box, const int32_t* row_ptr,
-                                           const int32_t* col, int64_t nnz, double* w,
-                                           float* w32, float* mom32, double* kappa,
+                                           const int32_t* col, int64_t nnz, uint32_t op_mask,
+                                           double* w, float* w32, float* mom32, double* kappa,
                                            double* rowsum, int8_t* status, void* stream_) {
   clear_error();
-  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, w, kappa, status,
-                               "build_weights_noalloc"))
+  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, op_mask, w, mom32,
+                               kappa, status, "build_weights_noalloc"))
     return r;
   LABFM_REQUIRE(n <= LABFM_NOALLOC_MAX_NODES,
                 "build_weights_noalloc: %d nodes exceed the scratch's maximum of %d nodes "
@@ -2100,19 +2162,57 @@ extern "C" int labfm_build_weights_noalloc(const double* x, const double* y, con
                 n, LABFM_NOALLOC_MAX_NODES);
   int* work = nullptr;
   if (int r = scratch_of_current_device(&work)) return r;
-  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
-                            rowsum, status, work, as_stream(stream_));
+  return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w, w32,
+                            mom32, kappa, rowsum, status, work, as_stream(stream_));
 }
 
 extern "C" int labfm_tune_build(const double* x, const double* y, const double* h,
                                 const double* s, const int8_t* order_m, int32_t n, labfm_box box,
                                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
-                                double* w, float* w32, float* mom32, double* kappa,
-                                double* rowsum, int8_t* status, labfm_build_config* best,
-                                double* best_ms, void* stream_) {
+                                uint32_t op_mask, double* w, float* w32, float* mom32,
+                                double* kappa, double* rowsum, int8_t* status, void* workspace,
+                                size_t workspace_bytes, const char* cache_path,
+                                labfm_build_config* best, double* best_ms, int32_t* from_cache,
+                                void* stream_) {
   clear_error();
   LABFM_REQUIRE(best && best_ms, "tune_build: null output");
+  if (int r = check_build_args(x, y, h, s, order_m, n, row_ptr, col, nnz, op_mask, w, mom32,
+                               kappa, status, "tune_build"))
+    return r;
+  LABFM_WORKSPACE(workspace, workspace_bytes, build_work_bytes(n), "tune_build");
   hipStream_t st = as_stream(stream_);
+  if (from_cache) *from_cache = 0;
+
+  // the cache key: device, node set (size, stencil entries, nodes per
+  // order) and the outputs requested
+  const std::string path = tune_cache_path(cache_path);
+  std::vector<TuneEntry> entry(1);
+  if (!path.empty()) {
+    int starts[17] = {0};
+    if (int r = order_buckets(order_m, n, static_cast<int*>(workspace), starts, st)) return r;
+    std::string key = "build/" + tune_device_key() + "/n" + std::to_string(n) + "/nnz" +
+                      std::to_string(static_cast<long long>(nnz)) + "/orders";
+    for (int b = 0; b < 16; ++b)
+      if (starts[b + 1] > starts[b])
+        key += ":" + std::to_string(15 - b) + "x" + std::to_string(starts[b + 1] - starts[b]);
+    char tail[64];
+    std::snprintf(tail, sizeof tail, "/ops%x/w32%d/rowsum%d", op_mask, w32 ? 1 : 0,
+                  rowsum ? 1 : 0);
+    entry[0].key = key + tail;
+    if (tune_cache_lookup(path, entry)) {
+      const labfm_build_config c{entry[0].a, entry[0].b};
+      if (labfm_set_build_config(&c) == LABFM_OK) {
+        *best = c;
+        *best_ms = entry[0].ms;
+        if (from_cache) *from_cache = 1;
+        return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w,
+                                   w32, mom32, kappa, rowsum, status, workspace,
+                                   workspace_bytes, stream_);
+      }
+      clear_error();  // an entry the library no longer accepts: tune again
+    }
+  }
+
   const labfm_build_config cands[6] = {{LABFM_BUILD_WAVE, 0},
                                        {LABFM_BUILD_BLOCK, 0},
                                        {LABFM_BUILD_PERSISTENT, 0},
@@ -2123,14 +2223,14 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   LABFM_HIP(hipEventCreate(&e0));
   LABFM_HIP(hipEventCreate(&e1));
   double bms = 1e300;
-  labfm_build_config bc = cands[1];
+  labfm_build_config bc = cands[5];
   int rc = LABFM_OK;
   for (int k = 0; k < 6 && rc == LABFM_OK; ++k) {
     labfm_set_build_config(&cands[k]);
     hipError_t e = hipEventRecord(e0, st);
     if (e == hipSuccess)
-      rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32,
-                               kappa, rowsum, status, stream_);
+      rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w, w32,
+                               mom32, kappa, rowsum, status, workspace, workspace_bytes, stream_);
     if (rc == LABFM_OK && e == hipSuccess) e = hipEventRecord(e1, st);
     if (rc == LABFM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -2151,15 +2251,26 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   *best = bc;
   *best_ms = bms;
   // leave the outputs of the chosen distribution in place
-  return labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, w, w32, mom32, kappa,
-                             rowsum, status, stream_);
+  rc = labfm_build_weights(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w, w32, mom32,
+                           kappa, rowsum, status, workspace, workspace_bytes, stream_);
+  if (rc != LABFM_OK || path.empty()) return rc;
+  entry[0].a = bc.mode;
+  entry[0].b = bc.workgroups_per_cu;
+  entry[0].ms = bms;
+  std::string err;
+  if (!tune_cache_store(path, entry, err)) {
+    set_error("tune_build: tune cache: %s", err.c_str());
+    return LABFM_ERR_ARG;
+  }
+  return LABFM_OK;
 }
 
 extern "C" int labfm_optimise_stencils(const double* x, const double* y, const double* h0,
                                        const double* s, const int8_t* order_m, int32_t n,
                                        labfm_box box, const int32_t* row_ptr, const int32_t* col,
                                        int64_t nnz, const labfm_stencil_opt_params* prm,
-                                       double* h_out, int32_t* iters, void* stream_) {
+                                       double* h_out, int32_t* iters, void* workspace,
+                                       size_t workspace_bytes, void* stream_) {
   clear_error();
   LABFM_REQUIRE(n > 0, "optimise_stencils: n must be positive (got %d)", n);
   LABFM_REQUIRE(x && y && h0 && s && order_m && row_ptr && h_out,
@@ -2170,26 +2281,11 @@ extern "C" int labfm_optimise_stencils(const double* x, const double* y, const d
   LABFM_REQUIRE(p.shrink > 0.0 && p.shrink < 1.0 && p.gain_max > 0.0 && p.res_coef > 0.0 &&
                     p.max_iter >= 0 && p.max_iter <= 10000,
                 "optimise_stencils: bad parameters");
+  LABFM_WORKSPACE(workspace, workspace_bytes, build_work_bytes(n), "optimise_stencils");
   hipStream_t st = as_stream(stream_);
-  struct Temp {
-    void* p = nullptr;
-    ~Temp() {
-      if (p) (void)hipFree(p);
-    }
-  } tmp;
-  LABFM_HIP(hipMalloc(&tmp.p, sizeof(int) * (64 + static_cast<size_t>(n))));
-  int* hist = static_cast<int*>(tmp.p);
-  int* list = hist + 64;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, hist, 64);
-  hipLaunchKernelGGL(order_histogram_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
-                     n, hist);
-  hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(64), 0, st, hist);
-  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, order_m,
-                     n, hist, list);
-  LABFM_LAUNCHED();
+  int* list = static_cast<int*>(workspace) + kBuildWorkInts;
   int starts[17] = {0};
-  LABFM_HIP(hipMemcpyAsync(starts, hist + 16, sizeof(int) * 17, hipMemcpyDeviceToHost, st));
-  LABFM_HIP(hipStreamSynchronize(st));
+  if (int r = order_buckets(order_m, n, static_cast<int*>(workspace), starts, st)) return r;
   int mmax = 0;
   for (int b = 0; b < 16; ++b)
     if (starts[b + 1] > starts[b]) {
@@ -2198,7 +2294,7 @@ extern "C" int labfm_optimise_stencils(const double* x, const double* y, const d
     }
   OptArgs a{};
   a.b = BuildArgs{x, y, h0, s, order_m, n, box, row_ptr, col, nnz, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr};
+                  nullptr, nullptr, nullptr, rows_of_mask(0x3F)};
   a.h_out = h_out;
   a.iters = iters;
   a.shrink = p.shrink;
@@ -2211,6 +2307,5 @@ extern "C" int labfm_optimise_stencils(const double* x, const double* y, const d
     return hipGetLastError();
   });
   LABFM_HIP(e);
-  LABFM_HIP(hipStreamSynchronize(st));  // the work list is freed on return
   return LABFM_OK;
 }

@@ -112,36 +112,49 @@ _SIGNATURES = {
     "labfm_last_error": (ctypes.c_char_p, []),
     "labfm_w32_stride": (ctypes.c_int64, [ctypes.c_int64]),
     "labfm_version": (ctypes.c_char_p, []),
-    "labfm_morton_order": (ctypes.c_int, [_P, _P, ctypes.c_int32, _Box, ctypes.c_double, _P, _P]),
+    "labfm_morton_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "labfm_morton_order": (ctypes.c_int, [_P, _P, ctypes.c_int32, _Box, ctypes.c_double, _P, _P,
+                                          ctypes.c_size_t, _P]),
+    "labfm_neighbours_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_build_neighbours": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _Box, _P, _P,
-                                              ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
+                                              ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P,
+                                              ctypes.c_size_t, _P]),
+    "labfm_build_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
-                                           ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P]),
+                                           ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P, _P,
+                                           _P, _P, ctypes.c_size_t, _P]),
     "labfm_build_weights_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P,
-                                                   _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
-                                                   _P]),
+                                                   _P, ctypes.c_int64, ctypes.c_uint32, _P, _P,
+                                                   _P, _P, _P, _P, _P]),
     "labfm_apply_operators": (ctypes.c_int, [ctypes.POINTER(_Operators), ctypes.c_uint32, _P, _P,
                                              ctypes.c_int, _P]),
+    "labfm_time_step_workspace_bytes": (ctypes.c_size_t, []),
     "labfm_time_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double,
-                                       ctypes.POINTER(ctypes.c_double), _P]),
+                                       ctypes.POINTER(ctypes.c_double), _P, ctypes.c_size_t,
+                                       _P]),
     "labfm_ns_rhs": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams), _P,
                                     ctypes.c_int, _P]),
     "labfm_tile_count": (ctypes.c_int32, [ctypes.c_int32]),
     "labfm_mfma_f64_rate_scratch_bytes": (ctypes.c_size_t, []),
     "labfm_mfma_f64_rate": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_size_t,
                                            ctypes.POINTER(ctypes.c_double), _P]),
+    "labfm_tiles_workspace_bytes": (ctypes.c_size_t, []),
     "labfm_build_tiles": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
-                                         ctypes.POINTER(ctypes.c_int32), _P]),
-    "labfm_build_transpose": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, _P, _P, _P]),
+                                         ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_size_t,
+                                         _P]),
+    "labfm_transpose_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
+    "labfm_build_transpose": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, _P, _P, _P,
+                                             ctypes.c_size_t, _P]),
     "labfm_adjoint_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32,
                                                         ctypes.c_int32]),
     "labfm_rk_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_Operators),
                                         ctypes.POINTER(_Transpose), ctypes.POINTER(_RKParams),
                                         ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    "labfm_boundary_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_boundary_weights": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                               ctypes.c_int64, ctypes.POINTER(_Strips), _P, _P,
-                                              _P, _P, _P, _P, _P]),
+                                              _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "labfm_lagrangian_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
     "labfm_lagrangian_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_int32, _Box,
                                              ctypes.POINTER(_RKParams), ctypes.c_int32,
@@ -151,19 +164,23 @@ _SIGNATURES = {
     "labfm_get_build_config": (ctypes.c_int, [ctypes.POINTER(_BuildConfig)]),
     "labfm_optimise_stencils": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                                ctypes.c_int64,
-                                               ctypes.POINTER(_StencilOptParams), _P, _P, _P]),
+                                               ctypes.POINTER(_StencilOptParams), _P, _P, _P,
+                                               ctypes.c_size_t, _P]),
     "labfm_tune_build": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
-                                        ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                        ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P, _P, _P,
+                                        _P, ctypes.c_size_t, ctypes.c_char_p,
                                         ctypes.POINTER(_BuildConfig),
-                                        ctypes.POINTER(ctypes.c_double), _P]),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32), _P]),
     "labfm_rk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "labfm_get_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                                ctypes.c_int64, ctypes.POINTER(_LaunchConfig)]),
     "labfm_set_launch_config": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int,
                                                ctypes.POINTER(_LaunchConfig)]),
     "labfm_tune": (ctypes.c_int, [ctypes.POINTER(_Operators), _P, ctypes.c_int, ctypes.c_int32, _P,
-                                  ctypes.c_size_t, ctypes.POINTER(_LaunchConfig),
-                                  ctypes.POINTER(ctypes.c_double), _P]),
+                                  ctypes.c_size_t, ctypes.c_char_p, ctypes.POINTER(_LaunchConfig),
+                                  ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32), _P]),
     "labfm_rk_step": (ctypes.c_int, [_P, ctypes.POINTER(_Operators), ctypes.POINTER(_RKParams),
                                      ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _P,
                                      ctypes.c_size_t, ctypes.POINTER(_Timing), _P]),
@@ -212,12 +229,12 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _w32_ptr(t: Optional[torch.Tensor]):
-    """Pointer of a float32 weight copy held as the (6, nnz) view of rows at
-    the padded stride labfm_w32_stride(nnz)."""
+    """Pointer of a float32 weight copy held as the (rows, nnz) view of rows
+    at the padded stride labfm_w32_stride(nnz)."""
     if t is None:
         return None
-    if not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 6:
-        raise ValueError("labfm expects float32 weights of shape (6, nnz) on the device")
+    if not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
+        raise ValueError("labfm expects float32 weights of shape (rows, nnz) on the device")
     if t.stride() != (w32_stride(t.shape[1]), 1):
         raise ValueError("float32 weight rows must use the stride labfm_w32_stride(nnz)")
     return ctypes.c_void_p(t.data_ptr())
@@ -225,6 +242,16 @@ def _w32_ptr(t: Optional[torch.Tensor]):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """A device workspace of nbytes bytes (allocated by torch on the current
+    stream: the library's work on that stream may use it after the call)."""
+    return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+
+
+def _cache_arg(path: Optional[str]):
+    return None if path is None else os.fspath(path).encode()
 
 
 def _box(box) -> _Box:
@@ -241,8 +268,9 @@ def morton_order(x: torch.Tensor, y: torch.Tensor, box, cell: float) -> torch.Te
     """Z-order permutation (int32[n]) of the nodes' cells of side ``cell``."""
     n = x.numel()
     perm = torch.empty(n, dtype=torch.int32, device=x.device)
+    ws = _workspace(lib().labfm_morton_workspace_bytes(n), x.device)
     _check(lib().labfm_morton_order(_ptr(x), _ptr(y), n, _box(box), float(cell), _ptr(perm),
-                                    _stream()))
+                                    _ptr(ws), ws.numel(), _stream()))
     return perm
 
 
@@ -251,13 +279,16 @@ def build_neighbours(x: torch.Tensor, y: torch.Tensor, h: torch.Tensor, box):
     n = x.numel()
     row_ptr = torch.empty(n + 1, dtype=torch.int32, device=x.device)
     nnz = ctypes.c_int64(0)
+    ws = _workspace(lib().labfm_neighbours_workspace_bytes(n), x.device)
     code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(row_ptr),
-                                        None, 0, ctypes.byref(nnz), _stream())
+                                        None, 0, ctypes.byref(nnz), _ptr(ws), ws.numel(),
+                                        _stream())
     if code != ERR_CAPACITY:
         _check(code)
     col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=x.device)
     code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(row_ptr),
-                                        _ptr(col), col.numel(), ctypes.byref(nnz), _stream())
+                                        _ptr(col), col.numel(), ctypes.byref(nnz), _ptr(ws),
+                                        ws.numel(), _stream())
     _check(code)
     return row_ptr, col[: nnz.value]
 
@@ -268,7 +299,7 @@ class Operators:
 
     row_ptr: torch.Tensor
     col: torch.Tensor
-    w: Optional[torch.Tensor]       # float64 (6, nnz)
+    w: Optional[torch.Tensor]       # float64 (6, nnz): one row per operator of op_mask
     w32: Optional[torch.Tensor]     # float32 (6, nnz) view of rows at labfm_w32_stride(nnz)
     kappa: torch.Tensor             # float64 (n,)
     mom32: Optional[torch.Tensor] = None  # float32 (6, n) first moments of w32
@@ -282,6 +313,9 @@ class Operators:
     # float64 (n, 2) inward normal at no-slip wall nodes, zero elsewhere
     # (labfm_boundary_weights)
     wall_normal: Optional[torch.Tensor] = None
+    # operators whose weights w, w32 and rowsum hold (bit d for labfm_op d,
+    # rows in that order); the gather calls need all six
+    op_mask: int = 0x3F
 
     @property
     def n(self) -> int:
@@ -292,6 +326,9 @@ class Operators:
         return int(self.col.numel())
 
     def _c(self) -> _Operators:
+        if self.op_mask != 0x3F:
+            raise ValueError(f"operators built with op_mask {self.op_mask:#x}: the gather calls "
+                             "need all six operators (op_mask 0x3F)")
         tp = None
         if self.tiles is not None and self.use_tiles:
             hc, hi, lc, hmax = self.tiles
@@ -313,33 +350,44 @@ def w32_stride(nnz: int) -> int:
 
 
 def build_weights(x, y, h, s, m, box, row_ptr, col, f32: bool = False,
-                  rowsum: bool = False, tiles: bool = True, tune: bool = False) -> Operators:
-    """Weights of the six operators, filter coefficients and node status;
-    with ``tiles`` also the node tiles used by the LDS-staged kernels."""
+                  rowsum: bool = False, tiles: bool = True, tune: bool = False,
+                  op_mask: int = 0x3F, tune_cache: Optional[str] = None) -> Operators:
+    """Weights of the operators in op_mask (all six by default), filter
+    coefficients and node status; with ``tiles`` also the node tiles used by
+    the LDS-staged kernels. ``tune`` picks the build distribution with
+    labfm_tune_build (cached in ``tune_cache``, or the file LABFM_TUNE_CACHE
+    names)."""
     n = x.numel()
     nnz = col.numel()
     dev = x.device
+    k = bin(op_mask & 0x3F).count("1")
     if not torch.is_tensor(m):
         m = torch.full((n,), int(m), dtype=torch.int8, device=dev)
     # one extra element keeps the data pointer valid when nnz == 0
-    w = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)[: 6 * nnz].view(6, nnz)
+    w = torch.empty(k * nnz + 1, dtype=torch.float64, device=dev)[: k * nnz].view(k, nnz)
     # float32 rows at the library's padded stride (128-byte aligned rows); the
-    # operators keep the (6, nnz) view of it
-    w32 = (torch.empty((6, w32_stride(nnz)), dtype=torch.float32, device=dev)[:, :nnz]
+    # operators keep the (k, nnz) view of it
+    w32 = (torch.empty((k, w32_stride(nnz)), dtype=torch.float32, device=dev)[:, :nnz]
            if f32 else None)
-    mom32 = torch.empty((NUM_MOM32, n), dtype=torch.float32, device=dev) if f32 else None
+    # the first moments of the float32 L, xx and xy weights, when they are built
+    second = (1 << OP_L) | (1 << OP_XX) | (1 << OP_XY)
+    mom32 = (torch.empty((NUM_MOM32, n), dtype=torch.float32, device=dev)
+             if f32 and (op_mask & second) == second else None)
     kappa = torch.empty(n, dtype=torch.float64, device=dev)
-    rs = torch.empty((6, n), dtype=torch.float64, device=dev) if rowsum else None
+    rs = torch.empty((k, n), dtype=torch.float64, device=dev) if rowsum else None
     status = torch.empty(n, dtype=torch.int8, device=dev)
+    ws = _workspace(lib().labfm_build_workspace_bytes(n), dev)
     args = (_ptr(x), _ptr(y), _ptr(h), _ptr(s), _ptr(m), n, _box(box), _ptr(row_ptr), _ptr(col),
-            nnz, _ptr(w), _w32_ptr(w32), _ptr(mom32), _ptr(kappa), _ptr(rs), _ptr(status))
+            nnz, int(op_mask), _ptr(w), _w32_ptr(w32), _ptr(mom32), _ptr(kappa), _ptr(rs),
+            _ptr(status), _ptr(ws), ws.numel())
     if tune:
-        best, ms = _BuildConfig(), ctypes.c_double(0.0)
-        _check(lib().labfm_tune_build(*args, ctypes.byref(best), ctypes.byref(ms), _stream()))
-        build_weights.last_tuned = (best.mode, best.workgroups_per_cu, ms.value)
+        best, ms, hit = _BuildConfig(), ctypes.c_double(0.0), ctypes.c_int32(0)
+        _check(lib().labfm_tune_build(*args, _cache_arg(tune_cache), ctypes.byref(best),
+                                      ctypes.byref(ms), ctypes.byref(hit), _stream()))
+        build_weights.last_tuned = (best.mode, best.workgroups_per_cu, ms.value, bool(hit.value))
     else:
         _check(lib().labfm_build_weights(*args, _stream()))
-    ops = Operators(row_ptr, col, w, w32, kappa, mom32, rs, status)
+    ops = Operators(row_ptr, col, w, w32, kappa, mom32, rs, status, op_mask=int(op_mask))
     if tiles:
         build_tiles(ops)
     return ops
@@ -358,10 +406,11 @@ def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
     if ops.status is None:
         ops.status = torch.zeros(n, dtype=torch.int8, device=x.device)
     wn = torch.empty((n, 2), dtype=torch.float64, device=x.device)
+    ws = _workspace(lib().labfm_boundary_workspace_bytes(n), x.device)
     _check(lib().labfm_boundary_weights(
         _ptr(x), _ptr(y), _ptr(h), _ptr(s), n, _box(box), _ptr(ops.row_ptr), _ptr(ops.col),
         ops.nnz, ctypes.byref(st), _ptr(ops.w), _w32_ptr(ops.w32), _ptr(ops.mom32),
-        _ptr(ops.kappa), _ptr(ops.status), _ptr(wn), _stream()))
+        _ptr(ops.kappa), _ptr(ops.status), _ptr(wn), _ptr(ws), ws.numel(), _stream()))
     ops.wall_normal = wn
     return ops
 
@@ -384,8 +433,10 @@ def lagrangian_step(x: torch.Tensor, y: torch.Tensor, q: torch.Tensor, h, s, m, 
     if nnz_capacity is None:
         rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
         nnz = ctypes.c_int64(0)
+        ws = _workspace(lib().labfm_neighbours_workspace_bytes(n), dev)
         code = lib().labfm_build_neighbours(_ptr(x), _ptr(y), _ptr(h), n, _box(box), _ptr(rp),
-                                            None, 0, ctypes.byref(nnz), _stream())
+                                            None, 0, ctypes.byref(nnz), _ptr(ws), ws.numel(),
+                                            _stream())
         if code != ERR_CAPACITY:
             _check(code)
         nnz_capacity = int(1.5 * nnz.value) + 1024
@@ -423,8 +474,9 @@ def build_tiles(ops: Operators) -> bool:
     hi = torch.empty(nt * TILE_HALO_MAX, dtype=torch.int32, device=dev)
     lc = torch.empty(max(1, nnz), dtype=torch.int16, device=dev)
     hmax = ctypes.c_int32(0)
+    ws = _workspace(lib().labfm_tiles_workspace_bytes(), dev)
     code = lib().labfm_build_tiles(_ptr(ops.row_ptr), _ptr(ops.col), n, nnz, _ptr(hc), _ptr(hi),
-                                   _ptr(lc), ctypes.byref(hmax), _stream())
+                                   _ptr(lc), ctypes.byref(hmax), _ptr(ws), ws.numel(), _stream())
     if code == ERR_CAPACITY:
         ops.tiles = None
         return False
@@ -449,8 +501,9 @@ def time_step(q: torch.Tensor, s: torch.Tensor, c2: float, mu: float, conv: floa
     """Eq. dt on the state q (coefficients conv, visc; the paper's 1.0, 0.4)."""
     dt = ctypes.c_double(0.0)
     n = s.numel()
+    ws = _workspace(lib().labfm_time_step_workspace_bytes(), q.device)
     _check(lib().labfm_time_step(_ptr(q), _ptr(s), n, float(c2), float(mu), float(conv),
-                                 float(visc), ctypes.byref(dt), _stream()))
+                                 float(visc), ctypes.byref(dt), _ptr(ws), ws.numel(), _stream()))
     return dt.value
 
 
@@ -504,18 +557,25 @@ def set_launch_config(kernel: int, prec: int, lanes_per_node: int = 0, flags: in
 
 
 def tune(ops: Operators, q: torch.Tensor, prec: int = F64, reps: int = 10,
-         workspace: Optional[torch.Tensor] = None) -> dict:
+         workspace: Optional[torch.Tensor] = None, cache_path: Optional[str] = None) -> dict:
     """Time every launch shape of the stage, filter and apply kernels and
-    install the fastest; returns {kernel: (lanes_per_node, flags, ms)}."""
+    install the fastest, or install the shapes cached for this node set in
+    ``cache_path`` (else the file LABFM_TUNE_CACHE names); returns
+    {kernel: (lanes_per_node, flags, ms)} and "cached": whether the shapes
+    came from the cache."""
     if workspace is None:
         workspace = rk_workspace(ops.n, q.device)
     best = (_LaunchConfig * 3)()
     ms = (ctypes.c_double * 3)()
+    hit = ctypes.c_int32(0)
     c = ops._c()
     _check(lib().labfm_tune(ctypes.byref(c), _ptr(q), prec, reps, _ptr(workspace),
-                            workspace.numel(), best, ms, _stream()))
+                            workspace.numel(), _cache_arg(cache_path), best, ms,
+                            ctypes.byref(hit), _stream()))
     names = ("stage", "filter", "apply")
-    return {names[k]: (best[k].lanes_per_node, best[k].flags, ms[k]) for k in range(3)}
+    out = {names[k]: (best[k].lanes_per_node, best[k].flags, ms[k]) for k in range(3)}
+    out["cached"] = bool(hit.value)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -532,8 +592,9 @@ def build_transpose(ops: Operators) -> None:
     tsrc = torch.empty(max(1, nnz), dtype=torch.int32, device=dev)
     tw = torch.empty(6 * nnz + 1, dtype=torch.float64, device=dev)
     c = ops._c()
+    ws = _workspace(lib().labfm_transpose_workspace_bytes(n, nnz), dev)
     _check(lib().labfm_build_transpose(ctypes.byref(c), _ptr(tptr), _ptr(tsrc), _ptr(tw),
-                                       _stream()))
+                                       _ptr(ws), ws.numel(), _stream()))
     ops.transpose = (tptr, tsrc, tw)
 
 
@@ -636,7 +697,9 @@ def optimise_stencils(x, y, s, m, box, h0=None, shrink: float = 0.99, gain_max: 
     h = torch.empty(n, dtype=torch.float64, device=dev)
     iters = torch.empty(n, dtype=torch.int32, device=dev)
     prm = _StencilOptParams(float(shrink), float(gain_max), float(res_coef), int(max_iter))
+    ws = _workspace(lib().labfm_build_workspace_bytes(n), dev)
     _check(lib().labfm_optimise_stencils(_ptr(x), _ptr(y), _ptr(h0), _ptr(s), _ptr(m), n,
                                          _box(box), _ptr(rp), _ptr(col), col.numel(),
-                                         ctypes.byref(prm), _ptr(h), _ptr(iters), _stream()))
+                                         ctypes.byref(prm), _ptr(h), _ptr(iters), _ptr(ws),
+                                         ws.numel(), _stream()))
     return h, iters

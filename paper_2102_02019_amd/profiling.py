@@ -158,16 +158,19 @@ def kernel_stats_markdown(stats_csv: str, top: int = 12) -> str:
     return "\n".join(lines)
 
 
-def kernel_trace_markdown(trace_csv: str, min_grid: int = 0, top: int = 12) -> str:
+def kernel_trace_markdown(trace_csv: str, min_grid: int = 0, top: int = 12,
+                          max_grid: int = 0) -> str:
     """Markdown table of per-kernel durations from a rocprofv3 --kernel-trace
-    CSV, counting only dispatches with Grid_Size_X >= min_grid (to separate
-    the launches of one node set from those of smaller ones in the same run)."""
+    CSV, counting only dispatches with Grid_Size_X >= min_grid (and <= max_grid
+    when given), to separate the launches of one node set from those of
+    other sizes in the same run."""
     import re
 
     rows = read_counter_csv(trace_csv)
     acc = {}
     for r in rows:
-        if int(r["Grid_Size_X"]) < min_grid:
+        g = int(r["Grid_Size_X"])
+        if g < min_grid or (max_grid and g > max_grid):
             continue
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
         acc.setdefault(r["Kernel_Name"], []).append(d)
@@ -181,6 +184,36 @@ def kernel_trace_markdown(trace_csv: str, min_grid: int = 0, top: int = 12) -> s
                       name)
         lines.append(f"| `{name[:80]}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
                      f"{max(v):.1f} | {100.0 * sum(v) / total:.2f} |")
+    return "\n".join(lines)
+
+
+def counters_markdown(csv_globs: list, kernel_substr: str, units: float = 0.0,
+                      last: int = 0) -> str:
+    """Markdown table of the counters of one kernel over several rocprofv3
+    --pmc passes (one glob per pass): the mean per dispatch of each counter
+    (summed over its dimensions) and, when `units` is given, per unit of
+    work (per node, say). `last` > 0 keeps the last matching dispatches of
+    each pass only."""
+    means = {}
+    for g in csv_globs:
+        rows = read_counter_csv(g)
+        names = sorted({r.get("Counter_Name") for r in rows})
+        for c in names:
+            vals = counter_per_dispatch(rows, kernel_substr, c)
+            if last > 0:
+                vals = vals[-last:]
+            if vals:
+                means[c] = (sum(vals) / len(vals), len(vals))
+    if not means:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel_substr!r}")
+    head = "| counter | dispatches | mean per dispatch |" + (" per unit |" if units else "")
+    sep = "|---|---:|---:|" + ("---:|" if units else "")
+    lines = [head, sep]
+    for c, (v, n) in sorted(means.items()):
+        row = f"| `{c}` | {n} | {v:.6g} |"
+        if units:
+            row += f" {v / units:.4g} |"
+        lines.append(row)
     return "\n".join(lines)
 
 
@@ -206,7 +239,14 @@ def main(argv=None) -> None:
     g = sub.add_parser("trace", help="markdown table of a --kernel-trace CSV, large grids only")
     g.add_argument("--csv", required=True, help="glob of the kernel_trace CSV file")
     g.add_argument("--min-grid", type=int, default=0, help="smallest Grid_Size_X counted")
+    g.add_argument("--max-grid", type=int, default=0, help="largest Grid_Size_X counted")
     g.add_argument("--top", type=int, default=14)
+    c = sub.add_parser("counters", help="markdown table of one kernel's --pmc counters")
+    c.add_argument("--csv", required=True, nargs="+",
+                   help="one glob of counter_collection CSV files per pass")
+    c.add_argument("--match", required=True, help="kernel name pattern ('*' joins parts)")
+    c.add_argument("--units", type=float, default=0.0, help="work units per dispatch")
+    c.add_argument("--last", type=int, default=0)
     a = ap.parse_args(argv)
     if a.what == "traffic":
         s = traffic_summary(a.tag, a.match, a.workload, a.fetch, a.write, a.command, a.last,
@@ -215,8 +255,10 @@ def main(argv=None) -> None:
         with open(path, "w") as f:
             json.dump(s, f, indent=1)
         print(path, s["hbm_bytes_per_dispatch"])
+    elif a.what == "counters":
+        print(counters_markdown(a.csv, a.match, a.units, a.last))
     elif a.what == "trace":
-        print(kernel_trace_markdown(a.csv, a.min_grid, a.top))
+        print(kernel_trace_markdown(a.csv, a.min_grid, a.top, a.max_grid))
     else:
         print(kernel_stats_markdown(a.csv, a.top))
 

@@ -146,10 +146,12 @@ def test_neighbours_capacity_error(dev):
     rp = torch.empty(nodes.n + 1, dtype=torch.int32, device=dev)
     col = torch.empty(10, dtype=torch.int32, device=dev)
     nnz = ctypes.c_int64(0)
+    ws = torch.empty(labfm.lib().labfm_neighbours_workspace_bytes(nodes.n), dtype=torch.uint8,
+                     device=dev)
     code = labfm.lib().labfm_build_neighbours(labfm._ptr(x), labfm._ptr(y), labfm._ptr(h),
                                               nodes.n, labfm._box(nodes.box), labfm._ptr(rp),
                                               labfm._ptr(col), 10, ctypes.byref(nnz),
-                                              labfm._stream())
+                                              labfm._ptr(ws), ws.numel(), labfm._stream())
     assert code == labfm.ERR_CAPACITY
     assert nnz.value > 10 * nodes.n
 
@@ -816,7 +818,9 @@ def test_tuner_installs_a_valid_shape(dev, tg64):
     q = T(np.concatenate([l, u, v]), dev)
     try:
         best = labfm.tune(ops, q, labfm.F64, reps=3)
-        for k, (lpn, fl, ms) in best.items():
+        assert best["cached"] is False
+        for k in ("stage", "filter", "apply"):
+            lpn, fl, ms = best[k]
             assert lpn in (4, 8, 16, 32) and 0 <= fl <= 3 and ms > 0
         cfg = labfm.get_launch_config(labfm.KERNEL_STAGE, labfm.F64, ops.n, ops.nnz)
         assert cfg == best["stage"][:2]
@@ -950,7 +954,8 @@ def test_tune_build_picks_a_mode(dev, holes20k):
     rp, col = labfm.build_neighbours(x, y, h, nodes.box)
     try:
         ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, tune=True)
-        mode, wpc, ms = labfm.build_weights.last_tuned
+        mode, wpc, ms, cached = labfm.build_weights.last_tuned
+        assert not cached
         assert mode in (labfm.BUILD_WAVE, labfm.BUILD_BLOCK, labfm.BUILD_PERSISTENT,
                         labfm.BUILD_BUCKETED, labfm.BUILD_ROWS) and ms > 0
         assert labfm.get_build_config() == (mode, wpc)

@@ -54,13 +54,58 @@ def test_argument_errors_return_codes_without_gpu(lib):
     nnz = ctypes.c_int64(-1)
     box = labfm._Box(1.0, 1.0, 1, 1)
     code = lib.labfm_build_neighbours(None, None, None, 0, box, None, None, 0,
-                                      ctypes.byref(nnz), None)
+                                      ctypes.byref(nnz), None, 0, None)
     assert code == labfm.ERR_ARG
     assert b"n must be positive" in lib.labfm_last_error()
     code = lib.labfm_apply_operators(None, 1, None, None, 0, None)
     assert code == labfm.ERR_ARG
     assert lib.labfm_rk_workspace_bytes(0) == 0
     assert lib.labfm_rk_workspace_bytes(1000) >= 6 * 1000 * 8
+
+
+def test_calls_refuse_a_missing_or_short_workspace(lib):
+    """Every call that needs temporary device memory takes it from the
+    caller: a NULL or short workspace is an argument error, reported on the
+    host before any device work (the other pointers here are never
+    dereferenced)."""
+    from paper_2102_02019_amd import labfm
+
+    fake = ctypes.c_void_p(4096)  # stands in for device pointers
+    box = labfm._Box(1.0, 1.0, 1, 1)
+    n = 1000
+    nnz = ctypes.c_int64(0)
+    hmax = ctypes.c_int32(0)
+    dt = ctypes.c_double(0.0)
+    calls = {
+        "morton_order": lambda ws, b: lib.labfm_morton_order(
+            fake, fake, n, box, 0.1, fake, ws, b, None),
+        "build_neighbours": lambda ws, b: lib.labfm_build_neighbours(
+            fake, fake, fake, n, box, fake, fake, 10, ctypes.byref(nnz), ws, b, None),
+        "build_weights": lambda ws, b: lib.labfm_build_weights(
+            fake, fake, fake, fake, fake, n, box, fake, fake, 10, 0x3F, fake, None, None, fake,
+            None, fake, ws, b, None),
+        "optimise_stencils": lambda ws, b: lib.labfm_optimise_stencils(
+            fake, fake, fake, fake, fake, n, box, fake, fake, 10, None, fake, None, ws, b, None),
+        "build_tiles": lambda ws, b: lib.labfm_build_tiles(
+            fake, fake, n, 10, fake, fake, fake, ctypes.byref(hmax), ws, b, None),
+        "time_step": lambda ws, b: lib.labfm_time_step(
+            fake, fake, n, 1.0, 1.0, 1.0, 0.4, ctypes.byref(dt), ws, b, None),
+    }
+    sizes = {"morton_order": lib.labfm_morton_workspace_bytes(n),
+             "build_neighbours": lib.labfm_neighbours_workspace_bytes(n),
+             "build_weights": lib.labfm_build_workspace_bytes(n),
+             "optimise_stencils": lib.labfm_build_workspace_bytes(n),
+             "build_tiles": lib.labfm_tiles_workspace_bytes(),
+             "time_step": lib.labfm_time_step_workspace_bytes()}
+    for name, call in calls.items():
+        need = sizes[name]
+        assert need > 0, name
+        for ws, b in ((None, need), (fake, need - 1)):
+            assert call(ws, b) == labfm.ERR_ARG, name
+            assert b"workspace" in lib.labfm_last_error(), name
+    assert lib.labfm_build_workspace_bytes(n) >= 4 * n
+    assert lib.labfm_transpose_workspace_bytes(n, 5000) >= 4 * (2 * (n + 1) + 5000)
+    assert lib.labfm_boundary_workspace_bytes(n) >= 5 * n
 
 
 def test_oracle_and_product_are_separate():

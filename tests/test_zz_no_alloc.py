@@ -44,10 +44,14 @@ def _call(name, nodes, arr, rp, col, out):
 
     P = labfm._ptr
     fn = getattr(labfm.lib(), name)
-    return fn(P(arr["x"]), P(arr["y"]), P(arr["h"]), P(arr["s"]), P(arr["m"]), nodes.n,
-              labfm._box(nodes.box), P(rp), P(col), col.numel(), P(out["w"]), P(out["w32"]),
-              P(out["mom32"]), P(out["kappa"]), P(out["rowsum"]), P(out["status"]),
-              labfm._stream())
+    args = [P(arr["x"]), P(arr["y"]), P(arr["h"]), P(arr["s"]), P(arr["m"]), nodes.n,
+            labfm._box(nodes.box), P(rp), P(col), col.numel(), 0x3F, P(out["w"]), P(out["w32"]),
+            P(out["mom32"]), P(out["kappa"]), P(out["rowsum"]), P(out["status"])]
+    if name == "labfm_build_weights":  # the allocating entry point takes a workspace
+        ws = torch.empty(labfm.lib().labfm_build_workspace_bytes(nodes.n), dtype=torch.uint8,
+                         device=rp.device)
+        args += [P(ws), ws.numel()]
+    return fn(*args, labfm._stream())
 
 
 def _case(nodes, dev):
@@ -95,7 +99,7 @@ def test_noalloc_rejects_more_nodes_than_its_scratch(dev):
     P = labfm._ptr
     code = labfm.lib().labfm_build_weights_noalloc(
         P(arr["x"]), P(arr["y"]), P(arr["h"]), P(arr["s"]), P(arr["m"]),
-        labfm.NOALLOC_MAX_NODES + 1, labfm._box(nodes.box), P(rp), P(col), col.numel(),
+        labfm.NOALLOC_MAX_NODES + 1, labfm._box(nodes.box), P(rp), P(col), col.numel(), 0x3F,
         P(out["w"]), P(out["w32"]), P(out["mom32"]), P(out["kappa"]), P(out["rowsum"]),
         P(out["status"]), labfm._stream())
     assert code == labfm.ERR_ARG
