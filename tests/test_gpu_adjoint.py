@@ -64,8 +64,10 @@ def test_adjoint_matches_oracle(dev, small, filt):
     ref = O.rk_adjoint(*q, W, prm, dt, n_steps, qbar, filt=filt)
     got = labfm.rk_adjoint(T(np.concatenate(q), dev), T(np.concatenate(qbar), dev), ops, prm, dt,
                            n_steps, ckpt_every=2, filter=filt).cpu().numpy().reshape(3, -1)
+    errs = [rel(got[k], ref[k]) for k in range(3)]
+    print(f"gate adjoint(filter={filt}): {errs}")
     for k in range(3):
-        assert rel(got[k], ref[k]) <= 1e-11, k
+        assert errs[k] <= 1e-12, k
 
 
 def test_transpose_is_the_reordered_stencil(dev, small):

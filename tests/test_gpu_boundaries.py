@@ -2,10 +2,11 @@
 wall equation of the stage kernels) with the FP64 CPU oracle, and the
 Poiseuille start-up against its analytic solution.
 
-Gates: boundary weights within 1e-11 relative l2 per row (the strip rows come
+Gates: boundary weights within 1e-12 relative l2 per row (the strip rows come
 from a 4 x 4 solve and fixed differences; the other rows keep the build's
-cond-based bound), right-hand sides and RK states within 1e-11 relative, the
-float32 copies the rounded float64 weights."""
+cond-based bound), right-hand sides and RK states within 1e-12 relative
+(measured: 1e-14 to 2.4e-13), the float32 copies the rounded float64
+weights."""
 import math
 
 import numpy as np
@@ -18,7 +19,7 @@ from paper_2102_02019_amd import inputs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-11
+TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -70,6 +71,7 @@ def _check_channel_weights(nodes, strips, ops, W):
     assert np.array_equal(ops.col.cpu().numpy(), W["col"])
     w = ops.w.cpu().numpy()
     kappa = ops.kappa.cpu().numpy()
+    worst = {}
     for i in range(nodes.n):
         a, b = rp[i], rp[i + 1]
         lvl = strips.level[i]
@@ -77,10 +79,14 @@ def _check_channel_weights(nodes, strips, ops, W):
         for d in range(6):
             boundary = lvl == 0 or (lvl in (1, 2) and d in (O.OP_X, O.OP_Y))
             tol = TOL if boundary else tol2d
-            assert rel(w[d, a:b], W["w"][d, a:b]) <= tol, (i, lvl, d)
+            e = rel(w[d, a:b], W["w"][d, a:b])
+            key = "strip rows" if boundary else "2D rows / their gate"
+            worst[key] = max(worst.get(key, 0.0), e if boundary else e / tol)
+            assert e <= tol, (i, lvl, d)
         # kappa comes from the filter weights: the 1D solve at wall nodes, the
         # two-dimensional one elsewhere
         assert abs(kappa[i] - W["kappa"][i]) <= max(1e-9, tol2d) * abs(W["kappa"][i]), i
+    print(f"gate channel weights: {worst}")
     assert np.array_equal(ops.status.cpu().numpy(), W["status"])
     assert np.array_equal(ops.wall_normal.cpu().numpy(), W["wall_normal"])
 
@@ -158,6 +164,8 @@ def test_channel_rhs_matches_oracle(dev, ch20):
     ref = B.channel_rhs(l, u, v, W, flow)
     wall = strips.column[:, 0]
     assert np.all(got[1:, wall] == 0.0)
+    print(f"gate channel rhs: {[rel(got[k], ref[k]) for k in range(3)]} "
+          f"wall {rel(got[0, wall], ref[0][wall])}")
     for k in range(3):
         assert rel(got[k], ref[k]) <= TOL, k
     assert rel(got[0, wall], ref[0][wall]) <= TOL
@@ -183,6 +191,7 @@ def test_channel_rk_matches_oracle(dev, ch20, graph):
     ref = B.channel_run(l, u, v, W, flow, dt, 40)
     got = q.cpu().numpy()
     errs = _compare_state(got, ref)
+    print(f"gate channel rk(graph={graph}): {errs}")
     assert max(errs) <= TOL, errs
     wall = strips.column[:, 0]
     assert np.all(got.reshape(3, -1)[1:, wall] == 0.0)
@@ -260,7 +269,8 @@ def test_poiseuille_startup_matches_oracle(dev):
     # compared as a vector
     e_rho = rel(np.exp(g[0]), np.exp(ref[0]))
     e_vel = rel(np.concatenate([g[1], g[2]]), np.concatenate([ref[1], ref[2]]))
-    assert max(e_rho, e_vel) <= 1e-10, (e_rho, e_vel)
+    print(f"gate poiseuille start-up: rho {e_rho} velocity {e_vel}")
+    assert max(e_rho, e_vel) <= 1e-12, (e_rho, e_vel)
     ua = B.poiseuille_startup(nodes.y, P.time(1.0), P.H, P.mu / P.rho0, P.gx)
     assert err == pytest.approx(B.velocity_error(ref[1], ref[2], ua), rel=1e-6)
 
@@ -321,9 +331,11 @@ def test_channel_full_size_sampled(dev):
     l, u, v = _smooth_state(nodes)
     got = labfm.ns_rhs(T(np.concatenate([l, u, v]), dev), ops, flow).cpu().numpy().reshape(3, -1)
     ref = B.channel_rhs(l, u, v, W, flow)
+    errs = [np.max(np.abs(got[k][rows] - ref[k][rows])) / (np.max(np.abs(ref[k][rows])) + 1e-300)
+            for k in range(3)]
+    print(f"gate channel 1.05M sampled rhs: {errs}")
     for k in range(3):
-        scale = np.max(np.abs(ref[k][rows])) + 1e-300
-        assert np.max(np.abs(got[k][rows] - ref[k][rows])) <= 1e-11 * scale, k
+        assert errs[k] <= 1e-12, k
 
 
 def test_cylinder_matches_oracle(dev):
@@ -348,6 +360,7 @@ def test_cylinder_matches_oracle(dev):
     flow = inputs.FlowParams(c2=400.0, mu=0.05, gx=0.3, gy=0.1)
     got = labfm.ns_rhs(T(np.concatenate([l, u, v]), dev), ops, flow).cpu().numpy().reshape(3, -1)
     ref = B.channel_rhs(l, u, v, W, flow)
+    print(f"gate cylinder rhs: {[rel(got[k], ref[k]) for k in range(3)]}")
     for k in range(3):
         assert rel(got[k], ref[k]) <= TOL, k
     assert rel(got[0, wall], ref[0][wall]) <= TOL
@@ -356,4 +369,5 @@ def test_cylinder_matches_oracle(dev):
     labfm.rk_step(q, ops, flow, dt, 10, check_finite=True)
     refq = B.channel_run(l, u, v, W, flow, dt, 10)
     errs = _compare_state(q.cpu().numpy(), refq)
+    print(f"gate cylinder rk: {errs}")
     assert max(errs) <= TOL, errs

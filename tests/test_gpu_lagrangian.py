@@ -2,7 +2,7 @@
 and weights rebuilt at every stage's positions) with the FP64 CPU oracle.
 
 Gates: positions within 1e-12 L (nearest periodic image), fields within
-1e-11 relative l2 after several steps. Stencil membership may differ where a
+1e-12 relative l2 after several steps. Stencil membership may differ where a
 node sits within rounding of a stencil's edge; the Wendland kernel vanishes
 there with its derivatives, so the weights, and the results, do not jump."""
 import math
@@ -70,8 +70,9 @@ def test_lagrangian_taylor_green_matches_oracle(dev, filt):
     ref = G.lagrangian_run(nodes.x, nodes.y, l, u, v, nodes.h, nodes.s, nodes.m, nodes.box, prm,
                            dt, 4, filt=filt)
     pos, fields = _compare(nodes, (x, y, g), ref)
+    print(f"gate lagrangian(filter={filt}): pos {pos} fields {fields}")
     assert pos <= 1e-12, pos
-    assert max(fields) <= 1e-11, fields
+    assert max(fields) <= 1e-12, fields
     assert st["steps_done"] == 4 and st["builds"] == 17
     assert st["node_status"] == [17 * nodes.n, 0, 0, 0, 0]
     # the nodes did move: by about |u| dt per step
@@ -93,8 +94,9 @@ def test_lagrangian_mixed_orders_matches_oracle(dev):
     ref = G.lagrangian_run(nodes.x, nodes.y, l, u, v, nodes.h, nodes.s, nodes.m, nodes.box, prm,
                            dt, 2)
     pos, fields = _compare(nodes, (x, y, g), ref)
+    print(f"gate lagrangian(mixed): pos {pos} fields {fields}")
     assert pos <= 1e-12, pos
-    assert max(fields) <= 1e-11, fields
+    assert max(fields) <= 1e-12, fields
 
 
 def test_uniform_stream_translates_the_nodes(dev):

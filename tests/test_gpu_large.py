@@ -97,9 +97,14 @@ def test_convergence_sweep_m8(dev):
     512^2 jittered nodes: the first derivatives converge as s^8 and the
     second derivatives as s^7 (the error floor of sin x cos 2y is reached
     below 256^2, so the faster-varying field carries the rates). At 64^2 the
-    oracle's operators give the same errors (the field is barely resolved
-    there, so the two differ by the weights' cond(M) eps, not by 1e-12; the
-    1e-12 gate on smooth fields is in the parity tests)."""
+    oracle's operators give the same errors to 1e-6, and the two differ by
+    at most 1e-10 relative (measured: 6e-13 for x, y, L, 3.5e-12 for xy,
+    1.0e-11 for xx). With 8 nodes per wavelength of sin 8y the differences
+    phi_j - phi_i are far from the polynomials the moment conditions make
+    exact, so the outputs take up the weights' own difference between two
+    correct float64 solves (up to 100 cond(M) eps, about 1e-10 relative
+    here) instead of cancelling it as they do on smooth fields; the 1e-12
+    gate on smooth fields is in the parity tests."""
     errs = []
     for nside in (64, 128, 256, 512):
         nodes, d, e = _sweep_errors(dev, nside, 4, 8)
@@ -113,8 +118,10 @@ def test_convergence_sweep_m8(dev):
                      -80 * f, -16 * f, -32 * np.cos(4 * X) * np.sin(8 * Y)]
             for k in range(5):
                 e_or = rel(O.apply_op(rp, col, W["w"][k], f), exact[k])
+                print(f"gate sweep 64^2 op {k}: vs oracle "
+                      f"{rel(d[k], O.apply_op(rp, col, W['w'][k], f))}, error {e[k]} vs {e_or}")
                 assert abs(e[k] - e_or) <= 1e-6 * e_or, k
-                assert rel(d[k], O.apply_op(rp, col, W["w"][k], f)) <= 1e-9, k
+                assert rel(d[k], O.apply_op(rp, col, W["w"][k], f)) <= 1e-10, k
     errs = np.array(errs)
     slopes = -np.diff(np.log(errs), axis=0) / math.log(2.0)
     # asymptotic range: 128 -> 256 -> 512
@@ -327,8 +334,9 @@ def test_variable_resolution_convergence(dev, m):
             rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box)
             W = O.weights_batched(nodes.x, nodes.y, nodes.h, nodes.s, m, rp, col, nodes.box)
             ref = [O.apply_op(rp, col, W["w"][k], phi) for k in range(3)]
+            print(f"gate varres m={m}: {[rel(d[k], ref[k]) for k in range(3)]}")
             for k in range(3):
-                assert rel(d[k], ref[k]) <= 1e-10, k
+                assert rel(d[k], ref[k]) <= 1e-12, k
     e = np.array(errs)
     slopes = -np.diff(np.log(e), axis=0) / np.log(np.array(res[1:]) / np.array(res[:-1]))[:, None]
     assert np.all(slopes[1:, 0] > m - 0.7), slopes

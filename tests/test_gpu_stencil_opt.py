@@ -35,15 +35,45 @@ def _gpu_opt(nodes, dev, **kw):
     return h.cpu().numpy(), k.cpu().numpy()
 
 
+def _disputed_step_margins(nodes, i, k_lo):
+    """The oracle's test values at the scale where the GPU and the oracle
+    decided differently, h* = h0 0.99^(k_lo + 1): the Laplacian residual
+    over its bound, and the largest amplitude response."""
+    h0 = O.STENCIL_H0_OVER_S * nodes.s
+    rp, col = O.neighbours_rows(nodes.x, nodes.y, h0, nodes.box, [i])
+    dx, dy = O.stencil_offsets(nodes.x, nodes.y, nodes.box, rp, col, i)
+    hh = h0[i]
+    for _ in range(k_lo + 1):
+        hh = hh * O.STENCIL_SHRINK
+    m = int(nodes.m[i])
+    r = O.node_weights(dx, dy, hh, float(nodes.s[i]), m)
+    alpha = O.laplacian_residual(r, hh, m)
+    alpha0 = O.STENCIL_RES_COEF * np.finfo(float).eps * O.n_moments(m) ** 4 / (hh * m)
+    ax, ay, al = O.amplitude_responses(dx, dy, r["w"], float(nodes.s[i]))
+    return alpha / alpha0, float(max(ax.max(), ay.max(), al.max()))
+
+
 def _check_against_oracle(nodes, h, k, sample):
     """Same number of shrinks as the oracle at (nearly) every sampled node:
-    at most one step apart, where rounding decides a marginal test; the
-    scales are h0 0.99^k formed by repeated multiplication."""
+    at most one step apart, and only where the step in dispute is marginal
+    for the oracle itself: its Laplacian residual within a factor 10 of the
+    bound (the residual is a rounding-level quantity, which two float64
+    solvers reproduce only to within such a factor), or the residual test
+    passed and the largest amplitude response within 1e-6 of 1.01 (the
+    responses of two correct solves differ by about cond(M) eps). The scales
+    are h0 0.99^k formed by repeated multiplication."""
     ho, ko = O.optimise_stencils(nodes.x, nodes.y, nodes.s, nodes.m, nodes.box,
                                  h0=O.STENCIL_H0_OVER_S * nodes.s, nodes=sample)
     d = np.abs(k[sample] - ko[sample])
     assert d.max() <= 1, (sample, k[sample], ko[sample])
     assert np.mean(d > 0) <= 0.05, np.mean(d > 0)
+    for i in np.asarray(sample)[d > 0]:
+        ratio, amax = _disputed_step_margins(nodes, int(i), int(min(k[i], ko[i])))
+        print(f"disputed node {i}: gpu {k[i]} oracle {ko[i]} shrinks; at the disputed step "
+              f"residual/bound {ratio:.3g}, largest response {amax:.12f}")
+        marginal_residual = 0.1 <= ratio <= 10.0
+        marginal_gain = ratio <= 1.0 and abs(amax - O.STENCIL_GAIN_MAX) <= 1e-6
+        assert marginal_residual or marginal_gain, (i, ratio, amax)
     for i in sample:
         hh = O.STENCIL_H0_OVER_S * nodes.s[i]
         for _ in range(int(k[i])):
