@@ -606,7 +606,7 @@ def lagrangian_bench(args, inputs, labfm, torch, np, dev, rk_steps=10):
         "stage_and_filter_ms_per_job": stage_ms,
         "max_nnz": stats[-1]["max_nnz"], "nnz_capacity": cap,
         "final_state_finite": finite,
-        "roofline": {"bound": "mfma", "kernel": "build_block_kernel<%d>" % wl.m,
+        "roofline": {"bound": "mfma", "kernel": build_kernel_name(labfm, wl.m),
                      "achieved": br["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": br["frac"], "traffic": None,
                      "gflop_per_build": br["gflop"], "mean_build_ms": br["weights_ms"]},
@@ -895,6 +895,17 @@ def stream_copy_rate(torch, dev, reps=5):
             "read_ms": t_sum, "bytes": nb, "frac_of_hbm_peak": best / HBM_PEAK_GBS}
 
 
+def build_kernel_name(labfm, m):
+    """The weight-build kernel the library launches for order m under the
+    installed distribution: one wavefront per node with the rows in
+    registers for orders up to 9 (the default), else the workgroup-per-node
+    kernel."""
+    mode = labfm.get_build_config()[0]
+    if mode == labfm.BUILD_ROWS and m <= 9:
+        return "build_rows_kernel<%d>" % m
+    return "build_block_kernel<%d>" % m
+
+
 def build_flops(m, K):
     """Algorithmic FP64 flops of one node's weight build: assembly 2Kn^2,
     LU (2/3)n^3, six solves 12n^2, weights 12Kn, basis K(3n + 4m + 20)."""
@@ -927,7 +938,9 @@ def build_rate(labfm, torch, np, nodes, x, y, h, s, m):
             "measured_mfma_f64_TFLOPs": measured,
             "frac_of_measured_mfma": fl / (best[1] * 1e-3) / 1e12 / measured,
             "distribution": {1: "wavefront-per-node", 2: "workgroup-per-node",
-                             3: "persistent", 4: "per-order-class"}.get(mode[0], str(mode[0]))}
+                             3: "persistent", 4: "per-order-class",
+                             5: "rows-in-registers"}.get(mode[0], str(mode[0])),
+            "kernel": build_kernel_name(labfm, int(np.max(nodes.m)))}
 
 
 def _oracle_sample(args):

@@ -1125,15 +1125,16 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
 //      through LDS instead makes every lane pull every value: 64 x 8 bytes per
 //      value through the CU's shared LDS data path, which then bounds the
 //      kernel.)
-//   4. back substitution from the last column: the pivot lane of column c
-//      (a ballot) forms x_c = y_c / u_cc (times its stored reciprocal), which
-//      every lane reads and subtracts from its right-hand sides, and writes it
-//      into Psi in LDS;
+//   4. back substitution from the last column: every lane reads y_c and
+//      1/u_cc from the pivot lane of column c (a ballot) and subtracts
+//      (u_rc / u_cc) y_c from its right-hand sides; at the end each lane
+//      forms its own x = y / u_cc and writes it into Psi in LDS;
 //   5. one lane per neighbour: w^d_j = psi_j sum_q He_a(x_j) He_b(y_j) Psi^d_q
 //      (Psi read from LDS a row at a time: there the reads cost less than
 //      reading each row out of its lane, measured), then the float32 copy,
 //      the filter calibration sum, the row sums and the first moments,
-//      reduced over the wave in a fixed order.
+//      reduced over the wave in a fixed order. A last pass over at most 32
+//      neighbours gives each neighbour two lanes, one per three operators.
 // The register arrays are indexed by compile-time constants only (every loop
 // over columns is unrolled), so the order is a template parameter.
 
@@ -1408,28 +1409,26 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   int st = (K < N) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
   if (!singular) {
     // ---- 4: back substitution ------------------------------------------------
-    // the pivot lane of column c forms x_c = y_c / u_cc, writes it into Psi
-    // (LDS) and every lane reads it from that lane (the value is consumed at
-    // once, so nothing uniform stays live across columns)
+    // column c's pivot lane holds y_c, final once the later columns have
+    // been subtracted; every lane reads y_c and 1/u_cc from that lane and
+    // subtracts (u_rc / u_cc) y_c. Each lane then forms its own
+    // x = y / u_cc once and writes it into Psi (LDS) at its column.
     double* psi_t = sm.buf;  // Psi[q][d], q < n (the strips are done)
 #pragma unroll
     for (int c = N - 1; c >= 0; --c) {
       const unsigned long long b = __builtin_amdgcn_ballot_w64(mycol == c);
       const int pc = static_cast<int>(__builtin_ctzll(b));
-      const double coef = (mycol < c) ? a[c] : 0.0;
-      double xv[LABFM_NUM_OPS];
-#pragma unroll
-      for (int d = 0; d < LABFM_NUM_OPS; ++d) xv[d] = a[N + d] * myinv;
-      if (lane == pc) {
-#pragma unroll
-        for (int d = 0; d < LABFM_NUM_OPS; d += 2)
-          *reinterpret_cast<double2*>(&psi_t[c * LABFM_NUM_OPS + d]) =
-              make_double2(xv[d], xv[d + 1]);
-      }
+      const double coef = (mycol < c) ? a[c] * readlane_f64(myinv, pc) : 0.0;
 #pragma unroll
       for (int d = 0; d < LABFM_NUM_OPS; ++d)
-        a[N + d] = fma(-coef, readlane_f64(xv[d], pc), a[N + d]);
+        a[N + d] = fma(-coef, readlane_f64(a[N + d], pc), a[N + d]);
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if (mycol < N) {
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; d += 2)
+        *reinterpret_cast<double2*>(&psi_t[mycol * LABFM_NUM_OPS + d]) =
+            make_double2(a[N + d] * myinv, a[N + d + 1] * myinv);
     }
     lds_barrier();
 
@@ -1441,7 +1440,36 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
     double rs[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mo[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const long long s32 = w32_stride(g.nnz);
-    for (int k0 = 0; k0 < K; k0 += 64) {
+    // offsets of neighbour k and its Hermite ABF factors: hx[a] = psi He_a(x),
+    // hy[b] = He_b(y) (scaled offsets)
+    auto basis_of = [&](int k, double& dx, double& dy, double* hx, double* hy) {
+      const int j = g.col[e0 + k];
+      dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
+      dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
+      const double xs = dx * hinv, ys = dy * hinv;
+      const double psi = wendland_c2(sqrt(xs * xs + ys * ys));
+      hx[0] = psi;
+      hy[0] = 1.0;
+      hx[1] = psi * xs;
+      hy[1] = ys;
+      double a0 = 1.0, a1 = xs, b0 = 1.0, b1 = ys;
+#pragma unroll
+      for (int q = 1; q < M; ++q) {
+        const double a2 = xs * a1 - static_cast<double>(q) * a0;
+        const double b2 = ys * b1 - static_cast<double>(q) * b0;
+        a0 = a1;
+        a1 = a2;
+        b0 = b1;
+        b1 = b2;
+        hx[q + 1] = psi * a2;
+        hy[q + 1] = b2;
+      }
+    };
+    // full passes of 64 neighbours, then a last pass over at most 32
+    // neighbours in which lanes l and l + 32 share neighbour k0 + l, the
+    // first forming operators x, y, L, the second xx, xy, hyp (og = 0, 1)
+    int k0 = 0;
+    for (; K - k0 > 32; k0 += 64) {
       const int k = k0 + lane;
       // Psi's offset passes through an empty asm statement every pass, so the
       // compiler does not hoist all of its reads out of the loop (n * 6
@@ -1449,31 +1477,10 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       int pbase = 0;
       asm volatile("" : "+v"(pbase));
       if (k < K) {
-        const int j = g.col[e0 + k];
-        const double dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
-        const double dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-        const double xs = dx * hinv, ys = dy * hinv;
-        const double psi = wendland_c2(sqrt(xs * xs + ys * ys));
-        double hx[M + 1], hy[M + 1];
-        hx[0] = psi;
-        hy[0] = 1.0;
-        hx[1] = psi * xs;
-        hy[1] = ys;
-        {
-          double a0 = 1.0, a1 = xs, b0 = 1.0, b1 = ys;
-#pragma unroll
-          for (int q = 1; q < M; ++q) {
-            const double a2 = xs * a1 - static_cast<double>(q) * a0;
-            const double b2 = ys * b1 - static_cast<double>(q) * b0;
-            a0 = a1;
-            a1 = a2;
-            b0 = b1;
-            b1 = b2;
-            hx[q + 1] = psi * a2;
-            hy[q + 1] = b2;
-          }
-        }
-        double wd[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double dx, dy, hx[M + 1], hy[M + 1];
+        basis_of(k, dx, dy, hx, hy);
+        const long long e = e0 + k;
+          double wd[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         // Psi row q in registers, row q+1 read from LDS while q is used
         double r0[LABFM_NUM_OPS], r1[LABFM_NUM_OPS];
 #pragma unroll
@@ -1497,7 +1504,6 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
             for (int d = 0; d < LABFM_NUM_OPS; ++d) r0[d] = r1[d];
           }
         }
-        const long long e = e0 + k;
 #pragma unroll
         for (int d = 0; d < LABFM_NUM_OPS; ++d) {
           const int r = op_row(g.rows, d);
@@ -1514,6 +1520,67 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
           mo[2 * (d - LABFM_OP_L) + 1] += v32 * dy;
         }
         f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * wd[LABFM_OP_HYP];
+      }
+    }
+    if (k0 < K) {
+      const int k = k0 + (lane & 31);
+      const int og = lane >> 5;
+      int pbase = 0;
+      asm volatile("" : "+v"(pbase));
+      if (k < K) {
+        double dx, dy, hx[M + 1], hy[M + 1];
+        basis_of(k, dx, dy, hx, hy);
+        const long long e = e0 + k;
+        constexpr int H3 = LABFM_NUM_OPS / 2;
+        static_assert(LABFM_OP_L == 2 && LABFM_OP_XX == 3 && LABFM_OP_XY == 4 &&
+                          LABFM_OP_HYP == 5,
+                      "operator groups of a half pass: (x, y, L), (xx, xy, hyp)");
+        const int ob = pbase + og * H3;  // this lane's operators in a Psi row
+        double wd[H3] = {0.0, 0.0, 0.0};
+        double r0[H3], r1[H3];
+#pragma unroll
+        for (int d = 0; d < H3; ++d) r0[d] = psi_t[ob + d];
+#pragma unroll
+        for (int deg = 1, q = 0; deg <= M; ++deg) {
+#pragma unroll
+          for (int bb = 0; bb <= deg; ++bb, ++q) {
+            if (q + 1 < N) {
+#pragma unroll
+              for (int d = 0; d < H3; ++d) r1[d] = psi_t[ob + (q + 1) * LABFM_NUM_OPS + d];
+            }
+            const double Wq = hx[deg - bb] * hy[bb];
+#pragma unroll
+            for (int d = 0; d < H3; ++d) {
+              wd[d] = fma(Wq, r0[d], wd[d]);
+              pin(wd[d]);
+            }
+#pragma unroll
+            for (int d = 0; d < H3; ++d) r0[d] = r1[d];
+          }
+        }
+#pragma unroll
+        for (int d = 0; d < H3; ++d) {
+          const int r = op_row(g.rows, og * H3 + d);
+          if (r != kNoRow) {
+            g.w[r * g.nnz + e] = wd[d];
+            if (g.w32) g.w32[r * s32 + e] = static_cast<float>(wd[d]);
+          }
+          // each sum takes this lane's value for its own operators only
+          rs[d] += og ? 0.0 : wd[d];
+          rs[H3 + d] += og ? wd[d] : 0.0;
+        }
+        // L is the first group's third operator, xx and xy the second's
+        // first two, hyp its third
+        const double vl = og ? 0.0 : static_cast<double>(static_cast<float>(wd[2]));
+        const double vxx = og ? static_cast<double>(static_cast<float>(wd[0])) : 0.0;
+        const double vxy = og ? static_cast<double>(static_cast<float>(wd[1])) : 0.0;
+        mo[0] += vl * dx;
+        mo[1] += vl * dy;
+        mo[2] += vxx * dx;
+        mo[3] += vxx * dy;
+        mo[4] += vxy * dx;
+        mo[5] += vxy * dy;
+        f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * (og ? wd[2] : 0.0);
       }
     }
     f0 = group_sum<64>(f0);
