@@ -405,7 +405,8 @@ typedef struct {
  *
  *   x, y, h, s, n, box, row_ptr, col, nnz  as for labfm_build_weights.
  *   strips        host pointer to the columns (device arrays inside).
- *   w             float64[6*nnz], updated in place.
+ *   w             float64[6*nnz], updated in place (a build with op_mask 0x3F:
+ *                 all six rows).
  *   w32, mom32    float32 copies and first moments, updated to match, or NULL.
  *   kappa         float64[n], updated at wall nodes.
  *   status        int8[n], updated: LABFM_NODE_SINGULAR when the 1D system is

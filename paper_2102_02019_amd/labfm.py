@@ -399,6 +399,9 @@ def boundary_weights(x, y, h, s, box, ops: Operators, column: torch.Tensor,
     written over ops (built by build_weights on the same node set); sets
     ops.wall_normal. column: int32 (count, 5) node indices of levels 0..4;
     normal: float64 (count, 2) unit normals into the fluid."""
+    if ops.op_mask != 0x3F:
+        raise ValueError("boundary_weights rewrites the rows of all six operators: build the "
+                         "operators with op_mask 0x3F")
     n = x.numel()
     count = int(column.shape[0]) if column.numel() else 0
     st = _Strips(count, _ptr(column).value if count else None,
