@@ -898,10 +898,10 @@ def stream_copy_rate(torch, dev, reps=5):
 def build_kernel_name(labfm, m):
     """The weight-build kernel the library launches for order m under the
     installed distribution: one wavefront per node with the rows in
-    registers for orders up to 9 (the default), else the workgroup-per-node
+    registers for orders up to 10 (the default), else the workgroup-per-node
     kernel."""
     mode = labfm.get_build_config()[0]
-    if mode == labfm.BUILD_ROWS and m <= 9:
+    if mode == labfm.BUILD_ROWS and m <= 10:
         return "build_rows_kernel<%d>" % m
     return "build_block_kernel<%d>" % m
 

@@ -281,9 +281,8 @@ int labfm_build_neighbours(const double* x, const double* y, const double* h, in
  * the (rank-deficient) solve when it completes. Nodes of different orders and
  * stencil sizes are built in one call; labfm_set_build_config selects how
  * they are spread over the GPU (default LABFM_BUILD_ROWS: one wavefront per
- * node holding the system's rows in registers for orders up to 9, one
- * workgroup per node for order 10, from a work list grouped by order;
- * labfm_tune_build picks). Synchronises once (the launches are sized on the
+ * node holding the system's rows in registers, from a work list grouped by
+ * order; labfm_tune_build picks). Synchronises once (the launches are sized on the
  * host from the order histogram); the build kernels are enqueued after that.
  */
 size_t labfm_build_workspace_bytes(int32_t n);
@@ -437,9 +436,12 @@ enum {
                                   nodes (highest order first) from a work counter */
   LABFM_BUILD_BUCKETED = 4,    /* one 256-thread-per-node launch per order class */
   LABFM_BUILD_ROWS = 5         /* one 64-lane wavefront per node holding the system's
-                                  rows in registers (orders 1..9, one launch per
-                                  order present); order 10 and out-of-range orders
-                                  take the workgroup-per-node kernel */
+                                  rows in registers (orders 1..10, one launch per
+                                  order present; at order 10 the pivot row of the
+                                  first column is kept in LDS and the other 64
+                                  rows fill the lanes);
+                                  out-of-range orders take the workgroup-per-node
+                                  kernel, which marks them unsupported */
 };
 typedef struct {
   int32_t mode;               /* LABFM_BUILD_*; default LABFM_BUILD_ROWS */

@@ -1099,13 +1099,17 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
 }
 
 // ---------------------------------------------------------------------------
-// One wavefront per node, the system's rows in registers (orders 1..9)
+// One wavefront per node, the system's rows in registers (orders 1..10)
 // ---------------------------------------------------------------------------
 //
 // For n <= 64 moments the whole augmented system [M~ | C~] fits one row per
 // lane: lane r keeps row r (n + 6 doubles, padded to an even count) in
 // registers, so the factorisation needs no workgroup barrier and no LDS
-// traffic for the trailing updates. Per node:
+// traffic for the trailing updates. Order 10 has n = 65: the pivot row of
+// column 0 is chosen from the first 16-column strip of M~, before the rows
+// reach the lanes, and kept in LDS; the other 64 rows fill the lanes, column
+// 0 is eliminated with the row from LDS, and the 64 remaining columns run on
+// 64 lanes as for the lower orders. Per node:
 //   1. the basis tables of 16 neighbours at a time in LDS and M~ on the FP64
 //      matrix cores, exactly as in the workgroup kernel (one wavefront
 //      accumulates every 16x16 tile);
@@ -1113,10 +1117,11 @@ build_persistent_kernel(BuildArgs g, const int* __restrict__ list, int count, in
 //      a time (a strip's accumulators die as its columns arrive); every lane
 //      forms its own row of C~ from its monomial's exponents;
 //   3. LU with partial pivoting, rows never swapped: at column c the pivot is
-//      the row (lane) not yet used with the largest |a_rc| (a 32-bit key: the
-//      high word of |a| with its 6 lowest bits replaced by 63 - lane, reduced
-//      over the wave with DPP and read lanes; candidates within about 2^-14
-//      relative of each other count as a tie and go to the lowest lane). The
+//      the row (lane) not yet used with the largest |a_rc|, compared exactly:
+//      the high words of |a| (sign, exponent and 20 mantissa bits) are
+//      reduced over the wave with DPP and read lanes, and only when several
+//      rows share the largest high word are their low words reduced too; of
+//      equal magnitudes the lowest lane wins. The
 //      pivot row reaches the other lanes through scalar registers (v_readlane)
 //      and the lanes not yet used subtract l_r = a_rc / u_cc times it (the
 //      multiplier from the reciprocal of the pivot, as LAPACK's unblocked
@@ -1143,6 +1148,9 @@ struct RowShape {
   static constexpr int N = moments_of(M);
   static constexpr int NB = (N + 15) / 16;        // 16-wide MFMA tiles per side
   static constexpr int RC = ((N + LABFM_NUM_OPS) + 1) & ~1;  // row length, even
+  // order 10: n = 65 rows, one more than the lanes (see step 3)
+  static constexpr bool kExtra = N > 64;
+  static_assert(N <= 65, "one row beyond the wavefront at most");
   static constexpr int TW = M + 1;                 // one basis table's length
   static constexpr int TABLE = 4 * TW + 1;         // four tables and a zero
   static constexpr int ZERO = 4 * TW;
@@ -1160,6 +1168,8 @@ struct RowShape {
 template <int M>
 struct alignas(16) RowSmem {
   double buf[RowShape<M>::kShared];
+  // order 10: the pivot row of column 0 of [M~ | C~]
+  double extra[RowShape<M>::kExtra ? RowShape<M>::RC : 2];
 };
 
 // Register fence: an empty asm statement that reads and writes v. Such
@@ -1240,7 +1250,7 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   const double hinv = 1.0 / h;
   double* T = sm.buf;
 
-  // ---- 1: basis tables and MFMA assembly -----------------------------------
+  // ---- 1, 2: basis tables, MFMA assembly, rows of M~ into registers ---------
   // exponents of this lane's moment index in each tile (row p or column q)
   int ea[NB], eb[NB];
 #pragma unroll
@@ -1253,106 +1263,168 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       eb[P] = -1;
     }
   }
-  double4_t acc[NB][NB];
-#pragma unroll
-  for (int P = 0; P < NB; ++P)
-#pragma unroll
-    for (int Q = 0; Q < NB; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
+  // Column tiles per pass over the neighbours: all of them up to order 9;
+  // at order 10 (5 x 5 tiles, 200 registers of accumulators) three, then
+  // two, each group moved into the rows before the next pass, so the
+  // accumulators of all 25 tiles are never live at once.
+  constexpr int QG = S::kExtra ? 3 : NB;
   const int kk = lane >> 2, t = lane & 3;  // table lanes: neighbour kk, table t
-  // coordinates of the lane's neighbour one chunk ahead
-  double xn = 0.0, yn = 0.0;
-  if (kk < K) {
-    const int j = g.col[e0 + kk];
-    xn = g.x[j];
-    yn = g.y[j];
-  }
-  if (lane < kChunk) T[lane * S::TABLE + S::ZERO] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += kChunk) {
-    const bool have = k0 + kk < K;
-    const double xj = xn, yj = yn;
-    if (k0 + kChunk + kk < K) {  // the next chunk's coordinates, in flight meanwhile
-      const int j = g.col[e0 + k0 + kChunk + kk];
-      xn = g.x[j];
-      yn = g.y[j];
-    }
-    double* tab = &T[kk * S::TABLE + t * TW];
-    if (have) {
-      const double dx = wrap_axis(xj - xi, g.box.Lx, px);
-      const double dy = wrap_axis(yj - yi, g.box.Ly, py);
-      const double xs = dx * hinv, ys = dy * hinv;
-      const double z = (t == 0 || t == 2) ? xs : ys;
-      if (t < 2) {
-        double v = 1.0;
-        tab[0] = 1.0;
-#pragma unroll
-        for (int a = 1; a <= M; ++a) {
-          v = v * z * (1.0 / static_cast<double>(a));  // z^a / a!
-          tab[a] = v;
-        }
-      } else {
-        const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
-        double h0 = 1.0, h1 = z;
-        tab[0] = psi;
-        if (M >= 1) tab[1] = psi * z;
-#pragma unroll
-        for (int a = 1; a < M; ++a) {
-          const double h2 = z * h1 - static_cast<double>(a) * h0;
-          h0 = h1;
-          h1 = h2;
-          tab[a + 1] = psi * h2;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a <= M; ++a) tab[a] = 0.0;
-    }
-    lds_barrier();
-#pragma unroll
-    for (int ks = 0; ks < kChunk / 4; ++ks) {
-      const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
-      double av[NB], bv[NB];
-#pragma unroll
-      for (int P = 0; P < NB; ++P) {
-        const int oa = ea[P] >= 0 ? ea[P] : S::ZERO, ob = ea[P] >= 0 ? TW + eb[P] : S::ZERO;
-        const int oc = ea[P] >= 0 ? 2 * TW + ea[P] : S::ZERO;
-        const int od = ea[P] >= 0 ? 3 * TW + eb[P] : S::ZERO;
-        av[P] = tk[oa] * tk[ob];
-        bv[P] = tk[oc] * tk[od];
-      }
-#pragma unroll
-      for (int P = 0; P < NB; ++P)
-#pragma unroll
-        for (int Q = 0; Q < NB; ++Q)
-          acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
-    }
-    lds_barrier();
-  }
-
-  // ---- 2: rows of [M~ | C~] into registers ----------------------------------
-  // element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
   double a[RC];
-  double* strip = sm.buf;
+  double* strip = sm.buf;  // the strips reuse the tables' LDS
+  // Order 10: p0, the pivot row of column 0 (the largest |M~_r0| of the 65
+  // rows, compared exactly, the lowest row on ties), is found in the first
+  // strip; it goes to LDS (sm.extra) and lane l takes row l, or l + 1 from p0
+  // on, so the other 64 rows fill the 64 lanes in order.
+  int p0 = 64, myrow = lane;
 #pragma unroll
-  for (int Q = 0; Q < NB; ++Q) {
+  for (int Q0 = 0; Q0 < NB; Q0 += QG) {
+    const int QN = (NB - Q0 < QG) ? NB - Q0 : QG;
+    double4_t acc[NB][QG];
 #pragma unroll
     for (int P = 0; P < NB; ++P)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        strip[(P * 16 + (lane >> 4) + 4 * v) * S::SS + (lane & 15)] = acc[P][Q][v];
-    lds_barrier();
+      for (int Q = 0; Q < QG; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
+    // coordinates of the lane's neighbour one chunk ahead
+    double xn = 0.0, yn = 0.0;
+    if (kk < K) {
+      const int j = g.col[e0 + kk];
+      xn = g.x[j];
+      yn = g.y[j];
+    }
+    if (lane < kChunk) T[lane * S::TABLE + S::ZERO] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += kChunk) {
+      const bool have = k0 + kk < K;
+      const double xj = xn, yj = yn;
+      if (k0 + kChunk + kk < K) {  // the next chunk's coordinates, in flight meanwhile
+        const int j = g.col[e0 + k0 + kChunk + kk];
+        xn = g.x[j];
+        yn = g.y[j];
+      }
+      double* tab = &T[kk * S::TABLE + t * TW];
+      if (have) {
+        const double dx = wrap_axis(xj - xi, g.box.Lx, px);
+        const double dy = wrap_axis(yj - yi, g.box.Ly, py);
+        const double xs = dx * hinv, ys = dy * hinv;
+        const double z = (t == 0 || t == 2) ? xs : ys;
+        if (t < 2) {
+          double v = 1.0;
+          tab[0] = 1.0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (Q * 16 + j < N) a[Q * 16 + j] = (lane < N) ? strip[lane * S::SS + j] : 0.0;
-    lds_barrier();
+          for (int a2 = 1; a2 <= M; ++a2) {
+            v = v * z * (1.0 / static_cast<double>(a2));  // z^a / a!
+            tab[a2] = v;
+          }
+        } else {
+          const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+          double h0 = 1.0, h1 = z;
+          tab[0] = psi;
+          if (M >= 1) tab[1] = psi * z;
+#pragma unroll
+          for (int a2 = 1; a2 < M; ++a2) {
+            const double h2 = z * h1 - static_cast<double>(a2) * h0;
+            h0 = h1;
+            h1 = h2;
+            tab[a2 + 1] = psi * h2;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a2 = 0; a2 <= M; ++a2) tab[a2] = 0.0;
+      }
+      lds_barrier();
+#pragma unroll
+      for (int ks = 0; ks < kChunk / 4; ++ks) {
+        const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
+        double av[NB], bv[QG];
+#pragma unroll
+        for (int P = 0; P < NB; ++P) {
+          const int oa = ea[P] >= 0 ? ea[P] : S::ZERO, ob = ea[P] >= 0 ? TW + eb[P] : S::ZERO;
+          av[P] = tk[oa] * tk[ob];
+        }
+#pragma unroll
+        for (int Q = 0; Q < QG; ++Q) {
+          if (Q < QN) {
+            const int P = Q0 + Q;
+            const int oc = ea[P] >= 0 ? 2 * TW + ea[P] : S::ZERO;
+            const int od = ea[P] >= 0 ? 3 * TW + eb[P] : S::ZERO;
+            bv[Q] = tk[oc] * tk[od];
+          }
+        }
+#pragma unroll
+        for (int P = 0; P < NB; ++P)
+#pragma unroll
+          for (int Q = 0; Q < QG; ++Q)
+            if (Q < QN)
+              acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
+      }
+      lds_barrier();
+    }
+
+    // rows of this group's columns into registers, one 16-column strip at a
+    // time; element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
+#pragma unroll
+    for (int Q = 0; Q < QG; ++Q) {
+      if (Q < QN) {
+        const int QC = Q0 + Q;
+#pragma unroll
+        for (int P = 0; P < NB; ++P)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            strip[(P * 16 + (lane >> 4) + 4 * v) * S::SS + (lane & 15)] = acc[P][Q][v];
+        lds_barrier();
+        if constexpr (S::kExtra) {
+          if (QC == 0) {
+            const double c0 = strip[lane * S::SS];
+            const unsigned long long bits =
+                static_cast<unsigned long long>(__double_as_longlong(fabs(c0)));
+            const unsigned hi = static_cast<unsigned>(bits >> 32);
+            const unsigned khi = wave_max_u32(hi);
+            unsigned long long cand = __builtin_amdgcn_ballot_w64(hi == khi);
+            if (__builtin_popcountll(cand) > 1) {
+              const unsigned lo = hi == khi ? static_cast<unsigned>(bits) : 0u;
+              const unsigned klo = wave_max_u32(lo);
+              cand = __builtin_amdgcn_ballot_w64(hi == khi && lo == klo);
+            }
+            const int pl = static_cast<int>(__builtin_ctzll(cand));
+            const double vl = readlane_f64(c0, pl);
+            const double v64 = readlane_f64(strip[64 * S::SS], 0);
+            // row 64 only when strictly larger
+            p0 = static_cast<unsigned long long>(__double_as_longlong(fabs(v64))) >
+                         static_cast<unsigned long long>(__double_as_longlong(fabs(vl)))
+                     ? 64
+                     : pl;
+            myrow = lane + (lane >= p0 ? 1 : 0);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (QC * 16 + j < N) a[QC * 16 + j] = (lane < N) ? strip[myrow * S::SS + j] : 0.0;
+        if constexpr (S::kExtra) {
+          if (lane < 16 && QC * 16 + lane < N) sm.extra[QC * 16 + lane] = strip[p0 * S::SS + lane];
+        }
+        lds_barrier();
+      }
+    }
   }
   int ra = 0, rb = 0;
-  if (lane < N) exponents_of(lane, ra, rb);
+  if (lane < N) exponents_of(myrow, ra, rb);
   {
     double c[LABFM_NUM_OPS];
     rhs_row(ra, rb, M, h, c);
 #pragma unroll
     for (int d = 0; d < LABFM_NUM_OPS; ++d) a[N + d] = (lane < N) ? c[d] : 0.0;
     if (RC > N + LABFM_NUM_OPS) a[RC - 1] = 0.0;
+    if constexpr (S::kExtra) {
+      if (lane == 0) {
+        int a64, b64;
+        exponents_of(p0, a64, b64);
+        rhs_row(a64, b64, M, h, c);
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; ++d) sm.extra[N + d] = c[d];
+        if (RC > N + LABFM_NUM_OPS) sm.extra[RC - 1] = 0.0;
+      }
+      lds_barrier();
+    }
   }
 
   // ---- 3: LU with partial pivoting, rows in place ---------------------------
@@ -1363,21 +1435,56 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   int mycol = used ? N : -1;
   double myinv = 0.0;
   bool singular = false;
-#pragma unroll
-  for (int c = 0; c < N; ++c) {
+  // order 10: column 0 is eliminated with its pivot row p0 from LDS (pr);
+  // the lanes then hold the 64 rows that columns 1..64 factor
+  const double* pr = nullptr;
+  double inv0 = 0.0;
+  if constexpr (S::kExtra) {
+    // the offset passes through an empty asm statement, so the reads of the
+    // row count as per lane (vector registers), not as wave-uniform values
+    // the compiler would hold in scalar registers
+    int xo = 0;
+    asm volatile("" : "+v"(xo));
+    pr = sm.extra + xo;
+    const double ucc = readlane_f64(pr[0], 0);
+    singular = (ucc == 0.0 || !isfinite(ucc));  // wave-uniform
     if (!singular) {
-      const unsigned mag = static_cast<unsigned>(
-          static_cast<unsigned long long>(__double_as_longlong(fabs(a[c]))) >> 32);
-      const unsigned key = used ? 0u : ((mag & ~63u) | static_cast<unsigned>(63 - lane));
-      const unsigned kmax = wave_max_u32(key);
-      const int p = 63 - static_cast<int>(kmax & 63u);
+      double inv = __builtin_amdgcn_rcp(ucc);
+      inv = fma(inv, fma(-ucc, inv, 1.0), inv);
+      inv0 = inv;
+      const double l = a[0] * inv;
+#pragma unroll
+      for (int j = 1; j < RC; ++j) {
+        a[j] = fma(-l, pr[j], a[j]);
+        pin(a[j]);
+        // eight reads of the pivot row in flight at a time, not all of them
+        if (j % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = S::kExtra ? 1 : 0; c < N; ++c) {
+    if (!singular) {
+      // |a| of a finite double orders as its bit pattern
+      const unsigned long long bits =
+          static_cast<unsigned long long>(__double_as_longlong(fabs(a[c])));
+      const unsigned hi = used ? 0u : static_cast<unsigned>(bits >> 32);
+      const unsigned khi = wave_max_u32(hi);
+      const bool top = !used && hi == khi;
+      unsigned long long cand = __builtin_amdgcn_ballot_w64(top);  // never empty
+      if (__builtin_popcountll(cand) > 1) {  // equal high words: compare the low words
+        const unsigned lo = top ? static_cast<unsigned>(bits) : 0u;
+        const unsigned klo = wave_max_u32(lo);
+        cand = __builtin_amdgcn_ballot_w64(top && lo == klo);
+      }
+      const int p = static_cast<int>(__builtin_ctzll(cand));
       // the pivot row is broadcast lane to scalar registers (v_readlane):
       // through LDS every lane would pull the whole row (64 lanes x 8 bytes
       // per value), more than the CU's shared LDS data path feeds (measured:
       // 8.7 ms against 7.3 ms at m = 8, 262,144 nodes; splitting each row
       // between the two ways was slower than read lanes alone)
       const double ucc = readlane_f64(a[c], p);
-      singular = (kmax == 0u || ucc == 0.0 || !isfinite(ucc));  // wave-uniform
+      singular = (ucc == 0.0 || !isfinite(ucc));  // wave-uniform
       if (!singular) {
         // 1 / u_cc: hardware reciprocal and one Newton step
         double inv = __builtin_amdgcn_rcp(ucc);
@@ -1414,14 +1521,30 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
     // subtracts (u_rc / u_cc) y_c. Each lane then forms its own
     // x = y / u_cc once and writes it into Psi (LDS) at its column.
     double* psi_t = sm.buf;  // Psi[q][d], q < n (the strips are done)
+    // order 10: the right-hand sides of column 0's pivot row (in LDS), kept
+    // in every lane and updated as the lanes' own
+    double ypr[LABFM_NUM_OPS];
+    if constexpr (S::kExtra) {
 #pragma unroll
-    for (int c = N - 1; c >= 0; --c) {
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) ypr[d] = pr[N + d];
+    }
+#pragma unroll
+    for (int c = N - 1; c >= (S::kExtra ? 1 : 0); --c) {
       const unsigned long long b = __builtin_amdgcn_ballot_w64(mycol == c);
       const int pc = static_cast<int>(__builtin_ctzll(b));
-      const double coef = (mycol < c) ? a[c] * readlane_f64(myinv, pc) : 0.0;
+      const double ipc = readlane_f64(myinv, pc);
+      const double coef = (mycol < c) ? a[c] * ipc : 0.0;
+      double cpr = 0.0;
+      if constexpr (S::kExtra) cpr = pr[c] * ipc;
 #pragma unroll
-      for (int d = 0; d < LABFM_NUM_OPS; ++d)
-        a[N + d] = fma(-coef, readlane_f64(a[N + d], pc), a[N + d]);
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) {
+        const double yc = readlane_f64(a[N + d], pc);
+        a[N + d] = fma(-coef, yc, a[N + d]);
+        if constexpr (S::kExtra) {
+          ypr[d] = fma(-cpr, yc, ypr[d]);
+          pin(ypr[d]);  // formed here, not deferred with every y_c held
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
     if (mycol < N) {
@@ -1429,6 +1552,13 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       for (int d = 0; d < LABFM_NUM_OPS; d += 2)
         *reinterpret_cast<double2*>(&psi_t[mycol * LABFM_NUM_OPS + d]) =
             make_double2(a[N + d] * myinv, a[N + d + 1] * myinv);
+    }
+    if constexpr (S::kExtra) {
+      if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < LABFM_NUM_OPS; d += 2)
+          *reinterpret_cast<double2*>(&psi_t[d]) = make_double2(ypr[d] * inv0, ypr[d + 1] * inv0);
+      }
     }
     lds_barrier();
 
@@ -1629,7 +1759,7 @@ hipError_t launch_rows(const BuildArgs& g, const int* list, int count, hipStream
   return hipGetLastError();
 }
 
-// Calls fn(integral_constant<M>) for an order 1..9 of the rows kernel.
+// Calls fn(integral_constant<M>) for an order 1..10 of the rows kernel.
 template <class Fn>
 hipError_t with_rows_order(int m, Fn&& fn) {
   using std::integral_constant;
@@ -1643,6 +1773,7 @@ hipError_t with_rows_order(int m, Fn&& fn) {
     case 7: return fn(integral_constant<int, 7>{});
     case 8: return fn(integral_constant<int, 8>{});
     case 9: return fn(integral_constant<int, 9>{});
+    case 10: return fn(integral_constant<int, 10>{});
   }
   return hipErrorInvalidValue;
 }
@@ -2092,10 +2223,11 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
       });
       break;
     case LABFM_BUILD_ROWS: {
-      // orders 1..9: one wavefront per node with the rows in registers, one
-      // launch per order present; order 10 and out-of-range orders (buckets
-      // of orders 15..10, and the bucket of orders <= 0): the workgroup kernel
-      for (int m = 1; m <= 9 && e == hipSuccess; ++m) {
+      // orders 1..10: one wavefront per node with the rows in registers, one
+      // launch per order present; out-of-range orders (buckets of orders
+      // 15..11, and the bucket of orders <= 0) go to the workgroup kernel,
+      // which marks them unsupported
+      for (int m = 1; m <= 10 && e == hipSuccess; ++m) {
         const int b = 15 - m;
         const int first = starts[b], count = starts[b + 1] - first;
         if (count <= 0) continue;
@@ -2103,8 +2235,8 @@ int build_weights_with(const double* x, const double* y, const double* h, const 
           return launch_rows<decltype(M)::value>(g, list + first, count, st);
         });
       }
-      if (e == hipSuccess && starts[6] > starts[0])
-        e = launch_block<10>(g, list + starts[0], starts[6] - starts[0], st);
+      if (e == hipSuccess && starts[5] > starts[0])
+        e = launch_block<10>(g, list + starts[0], starts[5] - starts[0], st);
       if (e == hipSuccess && starts[16] > starts[15])
         e = launch_block<10>(g, list + starts[15], starts[16] - starts[15], st);
       break;

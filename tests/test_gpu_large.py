@@ -275,7 +275,9 @@ def test_graded_holes_1m_build(dev):
     """About 1.0M nodes graded around 24 holes, orders 10 / 6 / 4 by wall
     distance: the build autotuner's choice, the persistent launch and the
     per-node launch give identical weights; sampled nodes of every order
-    match the oracle; only nodes cut off by a hole lack neighbours."""
+    match the oracle, from the workgroup-per-node kernel and from the
+    default rows-in-registers kernel; only nodes cut off by a hole lack
+    neighbours."""
     from paper_2102_02019_amd import labfm
 
     nodes = inputs.graded_holes(1_000_000, seed=3)
@@ -287,6 +289,8 @@ def test_graded_holes_1m_build(dev):
         pers = gpu_setup(nodes, dev)
         labfm.set_build_config(labfm.BUILD_BLOCK)
         blk = gpu_setup(nodes, dev)
+        labfm.set_build_config(labfm.BUILD_ROWS)
+        rows = gpu_setup(nodes, dev)
     finally:
         labfm.set_build_config(0)
     assert mode in (labfm.BUILD_WAVE, labfm.BUILD_BLOCK, labfm.BUILD_PERSISTENT,
@@ -304,6 +308,8 @@ def test_graded_holes_1m_build(dev):
         assert idx.size > 0
         sample += list(idx[:: max(1, idx.size // 10)][:10])
     check_sampled_rows(nodes, blk, sample)
+    assert torch.equal(rows.status, blk.status)
+    check_sampled_rows(nodes, rows, sample)
 
 
 # ------------------------------------------------------- variable resolution

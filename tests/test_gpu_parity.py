@@ -907,8 +907,8 @@ def test_build_modes_agree(dev, holes20k):
     cond(M~) eps, which is large for some m = 10 nodes whose stencils a hole
     cuts: every node whose weights differ by more than 1e-9 is checked against
     100 cond(M~) eps with the oracle's moment matrix. (The graded set has
-    orders 4, 6 and 10: the rows kernel builds the first two, its order-10
-    nodes take the workgroup kernel.)"""
+    orders 4, 6 and 10, all three built by the rows kernel in this mode; at
+    order 10 it keeps the first column's pivot row in LDS.)"""
     from paper_2102_02019_amd import labfm
 
     nodes = holes20k
