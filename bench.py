@@ -41,7 +41,9 @@ Other lines (each one JSON line of its own, same conventions):
 --lagrangian  the Lagrangian mode on the workload's nodes (stencils and
               weights rebuilt at every RK stage);
 --adjoint     the adjoint of the filtered RK loop (65,536 nodes, 200 steps);
---stencil-opt the stencil optimisation on the workload and 1.0M graded nodes.
+--stencil-opt the stencil optimisation on the workload and 1.0M graded nodes;
+--batched-build the weight build of the 1.0M graded nodes (orders 10 / 6 / 4,
+              uneven stencils) in each distribution and the autotuner's.
 
 Prints one JSON line.
 """
@@ -98,6 +100,9 @@ def parse():
     ap.add_argument("--stencil-opt", action="store_true",
                     help="instead of the solver job: time the stencil optimisation on the "
                          "workload and on the 1.0M-node graded set (one JSON line)")
+    ap.add_argument("--batched-build", action="store_true",
+                    help="instead of the solver job: the weight build of the 1.0M-node graded "
+                         "set (orders 10 / 6 / 4) in each distribution (one JSON line)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: a 1 GiB copy, then warmup jobs only")
     return ap.parse_args()
@@ -107,7 +112,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over several GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -118,6 +123,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.stencil_opt:
         print(json.dumps(stencil_opt_bench(args, inputs, labfm, torch, np, dev)))
+        return
+    if args.batched_build:
+        print(json.dumps(batched_build_bench(args, inputs, labfm, torch, np, dev)))
         return
     if args.poiseuille:
         print(json.dumps(poiseuille_bench(args, inputs, labfm, torch, np, dev)))
@@ -381,6 +389,87 @@ def stencil_opt_bench(args, inputs, labfm, torch, np, dev):
     t1 = time.perf_counter()
     res["cpu_baseline"] = {"value": len(sample) / (t1 - t0), "unit": "nodes/s", "cores": 1,
                            "kind": "oracle", "sample": f"{len(sample)} nodes of {sets[0][0]}"}
+    return res
+
+
+def batched_build_bench(args, inputs, labfm, torch, np, dev):
+    """The weight build of the 1.0M-node graded set (24 holes, orders 10 / 6
+    / 4 by wall distance, uneven stencils; node arrays and stencils resident
+    on the device): each distribution timed with HIP events (best of 3), its
+    FP64 FLOP/s against the spec peak and the measured MFMA rate, the
+    autotuner's choice; and the oracle's build timed on a sample of nodes of
+    every order."""
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    nodes = inputs.graded_holes(1_000_000, seed=3)
+    log(f"graded set: {nodes.n} nodes")
+    x, y, h, s, m = T(nodes.x), T(nodes.y), T(nodes.h), T(nodes.s), T(nodes.m)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    rp, col = labfm.build_neighbours(x, y, h, nodes.box)
+    ev[1].record()
+    torch.cuda.synchronize()
+    nb_ms = ev[0].elapsed_time(ev[1])
+    K = np.diff(rp.cpu().numpy()).astype(np.float64)
+    fl = float(np.sum(build_flops(nodes.m.astype(np.float64), K)))
+    measured = labfm.mfma_f64_rate()
+    modes = {"rows-in-registers": labfm.BUILD_ROWS, "workgroup-per-node": labfm.BUILD_BLOCK,
+             "persistent": labfm.BUILD_PERSISTENT, "per-order-class": labfm.BUILD_BUCKETED}
+    runs = {}
+    status = None
+    try:
+        for name, mode in modes.items():
+            labfm.set_build_config(mode)
+            labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True, tiles=False)
+            best = None
+            for _ in range(3):
+                ev[0].record()
+                ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True,
+                                          tiles=False)
+                ev[1].record()
+                torch.cuda.synchronize()
+                t = ev[0].elapsed_time(ev[1])
+                best = t if best is None else min(best, t)
+            tf = fl / (best * 1e-3) / 1e12
+            runs[name] = {"ms": best, "achieved_TFLOPs": tf, "frac": tf / FP64_PEAK_TFLOPS,
+                          "frac_of_measured_mfma": tf / measured}
+            log(f"{name}: {best:.2f} ms")
+            if mode == labfm.BUILD_ROWS:
+                status = np.bincount(ops.status.cpu().numpy().astype(np.int64), minlength=5)
+        labfm.set_build_config(0)
+        labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True, tiles=False, tune=True)
+        tuned = labfm.build_weights.last_tuned
+    finally:
+        labfm.set_build_config(0)
+    names = {v: k for k, v in modes.items()}
+    names[labfm.BUILD_WAVE] = "wavefront-per-node"
+    dominant = runs["rows-in-registers"]
+    res = {"metric": "batched weight build: FP64 FLOP/s, orders 10 / 6 / 4 in one call",
+           "value": dominant["achieved_TFLOPs"], "unit": "TFLOP/s", "dtype": "f64",
+           "config": {"workload": "holes1m", "nodes": nodes.n,
+                      "orders": {int(o): int(np.sum(nodes.m == o)) for o in np.unique(nodes.m)},
+                      "mean_neighbours": float(K.mean())},
+           "gflop": fl / 1e9, "neighbours_ms": nb_ms,
+           "roofline": {"bound": "mfma", "kernel": "build_rows_kernel<10>",
+                        "achieved": dominant["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": dominant["frac"], "traffic": None},
+           "measured_mfma_f64_TFLOPs": measured, "distributions": runs,
+           "autotuner": {"choice": names.get(tuned[0], str(tuned[0])),
+                         "workgroups_per_cu": tuned[1], "ms": tuned[2]},
+           "node_status_histogram": [int(v) for v in status]}
+    # the oracle's build on a sample of every order (one core)
+    from oracle import labfm_oracle as O
+
+    sample = []
+    for o in np.unique(nodes.m):
+        idx = np.nonzero(nodes.m == o)[0]
+        sample += [int(i) for i in idx[:: max(1, idx.size // 8)][:8]]
+    t0 = time.perf_counter()
+    srp, scol = O.neighbours_rows(nodes.x, nodes.y, nodes.h, nodes.box, sample)
+    O.weights(nodes.x, nodes.y, nodes.h, nodes.s, nodes.m, srp, scol, nodes.box, nodes=sample)
+    t1 = time.perf_counter()
+    res["cpu_baseline"] = {"value": len(sample) / (t1 - t0), "unit": "nodes/s", "cores": 1,
+                           "kind": "oracle",
+                           "sample": f"{len(sample)} nodes, 8 of each order: stencils + weights"}
     return res
 
 
