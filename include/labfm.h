@@ -331,7 +331,11 @@ int labfm_build_weights_noalloc(const double* x, const double* y, const double* 
  *        A^x = L^x(sin k x)/k, A^y = L^y(sin k y)/k,
  *        A^L = L^L(1/2 - cos(k x) cos(k y)/2)/k^2.
  * Each test at scale h builds the node's system on its h0 stencil
- * (neighbours beyond 2h have psi = 0 and drop out). The paper prints
+ * (neighbours beyond 2h have psi = 0 and drop out). The loop runs in passes
+ * over all nodes: the x, y and L weights of every node still shrinking, at
+ * its current scale (the rows-in-registers build), then the tests; a node
+ * leaves at its first failed test, at a singular system, or after max_iter
+ * accepted shrinks. The paper prints
  * res_coef = 1e-4 for its own solver and notes it is solver-specific; with
  * this residual even the initial stencils fail at 1e-4, and below about 1e4
  * the test acts on rounding noise. The default, 1e4, stops the shrinking
@@ -345,10 +349,13 @@ int labfm_build_weights_noalloc(const double* x, const double* y, const double* 
  *   h_out              float64[n] output scales.
  *   iters              int32[n] output k with h_out = h0 shrink^k (by repeated
  *                      multiplication), or NULL.
- *   workspace          labfm_build_workspace_bytes(n) bytes (the node list).
- * Nodes with orders outside 1..10 keep h0. Synchronises once (to size the
- * launch).
+ *   workspace          labfm_optimise_workspace_bytes(n, nnz) bytes: the node
+ *                      list, one pass's x, y and L weights (3 nnz doubles)
+ *                      and the per-node state.
+ * Nodes with orders outside 1..10 keep h0. Synchronises once to size the
+ * launches, then once per pass (to see whether any node is still shrinking).
  */
+size_t labfm_optimise_workspace_bytes(int32_t n, int64_t nnz);
 typedef struct {
   double shrink;    /* factor applied to h per accepted step (paper: 0.99) */
   double gain_max;  /* largest accepted amplitude response (paper: 1.01) */

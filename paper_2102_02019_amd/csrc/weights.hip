@@ -465,6 +465,9 @@ struct BuildArgs {
   double* rowsum;
   int8_t* status;
   unsigned rows;  // output row of each operator (op_row)
+  // the rows kernel skips nodes whose flag is 0 (the stencil optimiser's
+  // passes); null: every node is built
+  const int8_t* active = nullptr;
 };
 
 constexpr int kBlock = 256;
@@ -1243,6 +1246,7 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
   if (k_ >= count) return;
   const int lane = threadIdx.x;
   const int i = uniform(list ? list[k_] : k_);
+  if (g.active && uniform(g.active[i]) == 0) return;
   const int e0 = uniform(g.row_ptr[i]);
   const int K = uniform(g.row_ptr[i + 1]) - e0;
   const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
@@ -1779,225 +1783,187 @@ hipError_t with_rows_order(int m, Fn&& fn) {
 }
 
 // ---- stencil optimisation (section "Stencil optimisation") -------------------
+//
+// The shrinking loop runs in passes over the nodes: each pass builds the x, y
+// and L weights of every node still shrinking at its current scale h (the
+// rows-in-registers build on the h0 stencils, so neighbours beyond 2h have
+// psi = 0 and drop out of the system and the weights), then one wavefront per
+// node tests them. A node whose test fails, whose system is singular, or that
+// has taken max_iter + 1 shrinks keeps its last accepted scale and leaves the
+// loop; the host runs passes until no node is left.
 
-// Parameters of the shrinking loop (labfm_stencil_opt_params) and the nodes'
-// initial stencils (the CSR of radius 2 h0).
+constexpr int kNk = 16;  // wavenumbers of the amplitude test
+
+// Nodes, this pass's weights and the loop's state.
 struct OptArgs {
-  BuildArgs b;        // x, y, s, order, CSR of the h0 stencils; b.h = h0
-  double* h_out;
-  int* iters;
+  const double* x;
+  const double* y;
+  const double* s;
+  const int8_t* order;
+  labfm_box box;
+  const int* row_ptr;  // CSR of the h0 stencils
+  const int* col;
+  long long nnz;
+  const double* w;        // this pass's weights, rows x, y, L ([3][nnz])
+  const int8_t* status;   // this pass's build status
+  double* h;              // current scale
+  int* k;                 // shrinks taken to reach it
+  int8_t* active;         // 1 while the node shrinks
+  int* remaining;         // nodes still shrinking
+  double* h_out;          // last accepted scale (h0 until one is)
+  int* iters;             // its shrink count
   double shrink, gain_max, res_coef;
   int max_iter;
 };
 
-constexpr int kNk = 16;  // wavenumbers of the amplitude test
-
-// Scratch of the acceptance test beside BlockSmem: neighbour trig sequences
-// sin(k_q x), sin(k_q y), cos(k_q x), cos(k_q y) for q = 1..16 of a chunk, the
-// chunk's x, y and L weights, and the reductions.
+// LDS of the test (one wavefront per node) for a chunk of neighbours: the
+// scaled monomial factors x^a/a! and y^b/b!, the sequences sin(k_q x),
+// sin(k_q y), cos(k_q x), cos(k_q y) for q = 1..16, and the weights.
 template <int MMAX>
-struct OptSmem {
+struct AcceptSmem {
+  double tab[kChunk][2][MMAX + 1];
   double trig[4][kNk][kChunk];
   double wv[3][kChunk];
-  double red[Shape<MMAX>::NMAX];
-  double amp[3 * kNk];
-  int pass;
 };
 
-// One node's acceptance test at stencil scale h (the solution Psi in
-// sm.psi): the residual of the unscaled Laplacian system,
-//   alpha_L = || sum_j X_j w^L_j - C^L ||_2  (X_j the monomials x^a y^b/(a!b!)),
-// below res_coef eps n^4 / (h m), and the amplitude responses
-//   A^x(k) = L^x(sin k x)/k, A^y(k) = L^y(sin k y)/k,
-//   A^L(k) = L^L(1/2 - cos k x cos k y / 2)/k^2
-// at k = q k_Ny / 16, q = 1..16, k_Ny = pi/s, none above gain_max. Returns
-// the same value in every thread; ends with a barrier.
+__global__ void __launch_bounds__(256)
+stencil_opt_init_kernel(const double* __restrict__ h0, const int8_t* __restrict__ order, int n,
+                        double* __restrict__ h, int* __restrict__ k, int8_t* __restrict__ active,
+                        double* __restrict__ h_out, int* __restrict__ iters,
+                        int* __restrict__ remaining, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *remaining = count;
+  if (i >= n) return;
+  h[i] = h0[i];
+  k[i] = 0;
+  h_out[i] = h0[i];
+  iters[i] = 0;
+  active[i] = (order[i] >= 1 && order[i] <= 10) ? 1 : 0;
+}
+
+// The test of node i at its current scale h:
+//   1. the residual of the unscaled Laplacian system,
+//        alpha_L = || sum_j X_j w^L_j - C^L ||_2  (X_j the monomials
+//        x^a y^b/(a!b!)), at most res_coef eps n^4 / (h m);
+//   2. the amplitude responses A^x(k) = L^x(sin k x)/k,
+//      A^y(k) = L^y(sin k y)/k, A^L(k) = L^L(1/2 - cos k x cos k y / 2)/k^2
+//      at k = q k_Ny / 16, q = 1..16, k_Ny = pi/s: none above gain_max and
+//      none NaN.
+// Passed, h becomes the node's accepted scale and is shrunk for the next
+// pass; failed (or singular, or past max_iter), the node leaves the loop.
 template <int MMAX>
-__device__ bool stencil_accepts(const OptArgs& a, int i, int m, int n, int e0, int K, double h,
-                                double s, BlockSmem<MMAX>& sm, OptSmem<MMAX>& os, int tid) {
-  using S = Shape<MMAX>;
-  const BuildArgs& g = a.b;
-  const int lane = tid & 63;
-  const double xi = g.x[i], yi = g.y[i];
-  const int px = g.box.periodic_x, py = g.box.periodic_y;
+__global__ void __launch_bounds__(64)
+stencil_accept_kernel(OptArgs a, const int* __restrict__ list, int count) {
+  __shared__ AcceptSmem<MMAX> sm;
+  const int kn = blockIdx.x;
+  if (kn >= count) return;
+  const int i = uniform(list[kn]);
+  if (uniform(a.active[i]) == 0) return;
+  const int lane = threadIdx.x;
+  const int m = uniform(a.order[i]);
+  const int n = moments_of(m);
+  const int e0 = uniform(a.row_ptr[i]);
+  const int K = uniform(a.row_ptr[i + 1]) - e0;
+  const int kcur = uniform(a.k[i]);
+  const double h = a.h[i], s = a.s[i], xi = a.x[i], yi = a.y[i];
+  const int px = a.box.periodic_x, py = a.box.periodic_y;
   const double hinv = 1.0 / h;
   const double k1 = M_PI / (s * kNk);
-  double res = 0.0;  // thread p < n: sum_j X~^p_j w^L_j
-  double amp = 0.0;  // thread 192 + 16 op + q: sum_j w^op_j f_op(k_q r_j)
-  const int aidx = tid - 192, aop = aidx >> 4, aq = aidx & 15;
-  // threads 0..95 form the weights: slot = t/6, operator (x, y, L) = (t/2)%3, half = t%2
-  const int slot = tid / 6, wop = (tid / 2) % 3, half = tid & 1;
-  const int wcol = (wop == 0) ? LABFM_OP_X : (wop == 1 ? LABFM_OP_Y : LABFM_OP_L);
-  NbrPrefetch pf;
-  if (tid < 64) pf.init(g, e0, K, lane >> 2);
+  // residual lanes: moments p = lane and lane + 64 (order 10 has 65)
+  int pa0 = 0, pb0 = 0, pa1 = 0, pb1 = 0;
+  if (lane < n) exponents_of(lane, pa0, pb0);
+  if (lane + 64 < n) exponents_of(lane + 64, pa1, pb1);
+  double res0 = 0.0, res1 = 0.0;  // sum_j X~^p_j w^L_j (scaled monomials)
+  // amplitude lanes 0..47: operator aop (x, y, L), wavenumber aq
+  const int aop = lane >> 4, aq = lane & 15;
+  double amp = 0.0;
+  // chunk lanes: neighbour kk of the chunk, sequence t
+  const int kk = lane >> 2, t = lane & 3;
   for (int k0 = 0; k0 < K; k0 += kChunk) {
-    if (tid < 64) {
-      const int kk = lane >> 2, t = lane & 3;
-      double xj, yj;
-      const bool have = pf.advance(g, e0, K, k0, kk, xj, yj);
-      double* tab = &sm.T()[kk * S::TABLE + t * S::TW];
-      const double dx = have ? wrap_axis(xj - xi, g.box.Lx, px) : 0.0;
-      const double dy = have ? wrap_axis(yj - yi, g.box.Ly, py) : 0.0;
-      const double xs = dx * hinv, ys = dy * hinv;
-      const double z = (t == 0 || t == 2) ? xs : ys;
-      if (!have) {
+    const bool have = k0 + kk < K;
+    double dx = 0.0, dy = 0.0;
+    if (have) {
+      const int j = a.col[e0 + k0 + kk];
+      dx = wrap_axis(a.x[j] - xi, a.box.Lx, px);
+      dy = wrap_axis(a.y[j] - yi, a.box.Ly, py);
+    }
+    if (t < 2) {
+      const double z = (t == 0 ? dx : dy) * hinv;
+      double v = 1.0;
+      sm.tab[kk][t][0] = have ? 1.0 : 0.0;
 #pragma unroll
-        for (int a2 = 0; a2 <= MMAX; ++a2) tab[a2] = 0.0;
-      } else if (t < 2) {
-        double v = 1.0;
-        tab[0] = 1.0;
-#pragma unroll
-        for (int a2 = 1; a2 <= MMAX; ++a2) {
-          v = v * z * (1.0 / static_cast<double>(a2));
-          tab[a2] = v;
-        }
-      } else {
-        const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
-        double h0 = 1.0, h1 = z;
-        tab[0] = psi;
-        tab[1] = psi * z;
-#pragma unroll
-        for (int a2 = 1; a2 < MMAX; ++a2) {
-          const double h2 = z * h1 - static_cast<double>(a2) * h0;
-          h0 = h1;
-          h1 = h2;
-          tab[a2 + 1] = psi * h2;
-        }
+      for (int q = 1; q <= MMAX; ++q) {
+        v = v * z * (1.0 / static_cast<double>(q));  // z^q / q!
+        sm.tab[kk][t][q] = have ? v : 0.0;
       }
-      // trig sequences by the recurrences f(q+1) = 2 cos(theta) f(q) - f(q-1)
+    }
+    if (t < 3) sm.wv[t][kk] = have ? a.w[t * a.nnz + e0 + k0 + kk] : 0.0;
+    {
+      // f(q+1) = 2 cos(theta) f(q) - f(q-1), from sin or cos of theta
       const double d = (t == 0 || t == 2) ? dx : dy;
       double sn, cs;
       sincos(k1 * d, &sn, &cs);
       double f0 = (t < 2) ? 0.0 : 1.0, f1 = (t < 2) ? sn : cs;
-      os.trig[t][0][kk] = f1;
+      sm.trig[t][0][kk] = f1;
 #pragma unroll
       for (int q = 1; q < kNk; ++q) {
         const double f2 = 2.0 * cs * f1 - f0;
         f0 = f1;
         f1 = f2;
-        os.trig[t][q][kk] = f1;
+        sm.trig[t][q][kk] = f1;
       }
     }
     lds_barrier();
-    if (tid < 6 * kChunk) {
-      const double* tk = &sm.T()[slot * S::TABLE];
-      double acc = 0.0;
-#pragma unroll 4
-      for (int q = half; q < n; q += 2)
-        acc += (tk[2 * S::TW + sm.qa[q]] * tk[3 * S::TW + sm.qb[q]]) *
-               sm.psi[q * LABFM_NUM_OPS + wcol];
-      acc += __shfl_xor(acc, 1);
-      if (half == 0) os.wv[wop][slot] = acc;
-    }
-    lds_barrier();
-    if (tid < n) {
-      for (int k = 0; k < kChunk; ++k) {
-        const double* tk = &sm.T()[k * S::TABLE];
-        res += (tk[sm.qa[tid]] * tk[S::TW + sm.qb[tid]]) * os.wv[2][k];
-      }
-    }
-    if (aidx >= 0 && aidx < 3 * kNk) {
-      for (int k = 0; k < kChunk; ++k) {
-        const double f = (aop == 2) ? 0.5 - 0.5 * os.trig[2][aq][k] * os.trig[3][aq][k]
-                                    : os.trig[aop][aq][k];
-        amp += os.wv[aop][k] * f;
+    for (int c = 0; c < kChunk; ++c) {
+      const double wl = sm.wv[2][c];
+      if (lane < n) res0 += (sm.tab[c][0][pa0] * sm.tab[c][1][pb0]) * wl;
+      if (lane + 64 < n) res1 += (sm.tab[c][0][pa1] * sm.tab[c][1][pb1]) * wl;
+      if (lane < 3 * kNk) {
+        const double f = (aop == 2) ? 0.5 - 0.5 * sm.trig[2][aq][c] * sm.trig[3][aq][c]
+                                    : sm.trig[aop][aq][c];
+        amp += sm.wv[aop][c] * f;
       }
     }
     lds_barrier();
   }
-  if (tid < n) {
-    const int deg = sm.qa[tid] + sm.qb[tid];
+  // r_p = h^(a+b) res_p - C^L_p of the unscaled system
+  auto rsq = [&](int pa, int pb, double res) {
     double hp = 1.0;
-    for (int d2 = 0; d2 < deg; ++d2) hp *= h;
-    const double target = ((sm.qa[tid] == 2 && sm.qb[tid] == 0) ||
-                           (sm.qa[tid] == 0 && sm.qb[tid] == 2)) ? 1.0 : 0.0;
+    for (int d = 0; d < pa + pb; ++d) hp *= h;
+    const double target = ((pa == 2 && pb == 0) || (pa == 0 && pb == 2)) ? 1.0 : 0.0;
     const double r = hp * res - target;
-    os.red[tid] = r * r;
+    return r * r;
+  };
+  double sq = 0.0;
+  if (lane < n) sq += rsq(pa0, pb0, res0);
+  if (lane + 64 < n) sq += rsq(pa1, pb1, res1);
+  const double ss = group_sum<64>(sq);
+  double av = -1.0;
+  bool bad = false;
+  if (lane < 3 * kNk) {
+    const double kq = k1 * static_cast<double>(aq + 1);
+    av = (aop == 2) ? amp / (kq * kq) : amp / kq;
+    bad = !(av == av);
   }
-  if (aidx >= 0 && aidx < 3 * kNk) {
-    const double k = k1 * static_cast<double>(aq + 1);
-    os.amp[aidx] = (aop == 2) ? amp / (k * k) : amp / k;
-  }
-  lds_barrier();
-  if (tid == 0) {
-    double ss = 0.0;
-    for (int p = 0; p < n; ++p) ss += os.red[p];
-    double amax = -1.0;
-    bool nan_amp = false;
-    for (int q = 0; q < 3 * kNk; ++q) {
-      const double v = os.amp[q];
-      if (!(v == v)) nan_amp = true;
-      amax = v > amax ? v : amax;
-    }
-    double n4 = static_cast<double>(n);
-    n4 = n4 * n4 * n4 * n4;
-    const double alpha0 = a.res_coef * 2.220446049250313e-16 * n4 / (h * static_cast<double>(m));
-    const double alpha = sqrt(ss);
-    os.pass = (alpha <= alpha0) && !nan_amp && (amax <= a.gain_max) ? 1 : 0;
-  }
-  lds_barrier();
-  return uniform(os.pass) != 0;
-}
-
-// Shrinks h_i of node i from h0 by the factor `shrink` while the stencil
-// passes the acceptance test; the result is the last scale that passed (h0
-// when none did). The h0 stencil is used throughout: neighbours beyond 2h
-// have psi = 0 and drop out of the system and the weights.
-template <int MMAX>
-__device__ void optimise_node_block(int i_in, const OptArgs& a, BlockSmem<MMAX>& sm,
-                                    OptSmem<MMAX>& os, int tid) {
-  const BuildArgs& g = a.b;
-  const int i = uniform(i_in);
-  const int m = uniform(g.order[i]);
-  const int e0 = uniform(g.row_ptr[i]);
-  const int K = uniform(g.row_ptr[i + 1]) - e0;
-  const double h0 = g.h[i];
-  double best = h0;
-  int kbest = 0;
-  if (m >= 1 && m <= MMAX) {
-    const int n = moments_of(m);
-    const double s = g.s[i];
-    double h = h0;
-    int k = 0;
-    for (;;) {
-      // as in the persistent build: nothing derived from the thread index
-      // stays live across iterations
-      int tl = tid;
-      asm volatile("" : "+v"(tl));
-      assemble_system<MMAX>(g, i, m, n, e0, K, h, sm, tl);
-      bool ok = !factor_solve<MMAX>(n, sm, tl);
-      if (ok) {
-        for (int t = tl; t < n * LABFM_NUM_OPS; t += kBlock)
-          sm.psi[t] = sm.A[(t / LABFM_NUM_OPS) * Shape<MMAX>::LDA + Shape<MMAX>::NMAX +
-                           t % LABFM_NUM_OPS];
-        lds_barrier();
-        ok = stencil_accepts<MMAX>(a, i, m, n, e0, K, h, s, sm, os, tl);
-      }
-      if (!ok || k > a.max_iter) break;
-      best = h;
-      kbest = k;
-      h *= a.shrink;
-      ++k;
+  const bool nan_amp = __builtin_amdgcn_ballot_w64(bad) != 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) av = fmax(av, __shfl_xor(av, off, 64));
+  double n4 = static_cast<double>(n);
+  n4 = n4 * n4 * n4 * n4;
+  const double alpha0 = a.res_coef * 2.220446049250313e-16 * n4 / (h * static_cast<double>(m));
+  const bool ok = a.status[i] != LABFM_NODE_SINGULAR && sqrt(ss) <= alpha0 && !nan_amp &&
+                  av <= a.gain_max;
+  if (lane == 0) {
+    if (!ok || kcur > a.max_iter) {
+      a.active[i] = 0;
+      atomicSub(a.remaining, 1);
+    } else {
+      a.h_out[i] = h;
+      a.iters[i] = kcur;
+      a.h[i] = h * a.shrink;
+      a.k[i] = kcur + 1;
     }
   }
-  if (tid == 0) {
-    a.h_out[i] = best;
-    if (a.iters) a.iters[i] = kbest;
-  }
-  lds_barrier();
-}
-
-// five workgroups per CU up to m = 8 (96 VGPRs, some spilled; their LDS fits
-// five): 6.6% faster than four at m = 8; m = 10 is bounded by its LDS (three)
-template <int MMAX>
-__global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(MMAX <= 8 ? 5 : 3)))
-optimise_block_kernel(OptArgs a, const int* __restrict__ list, int count) {
-  __shared__ BlockSmem<MMAX> sm;
-  __shared__ OptSmem<MMAX> os;
-  const int k = blockIdx.x;
-  if (k >= count) return;
-  optimise_node_block<MMAX>(list[k], a, sm, os, threadIdx.x);
 }
 
 // Work list: node indices grouped by order, highest order first (counting
@@ -2464,6 +2430,34 @@ extern "C" int labfm_tune_build(const double* x, const double* y, const double* 
   return LABFM_OK;
 }
 
+// Workspace of labfm_optimise_stencils: the node list, the x, y and L
+// weights of a pass, and the per-node state.
+struct OptLayout {
+  size_t list, w, h, kappa, k, iters, active, status, remaining, total;
+  OptLayout(int32_t n, int64_t nnz) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+      const size_t at = o;
+      o += align256(bytes);
+      return at;
+    };
+    list = take(build_work_bytes(n));
+    w = take(sizeof(double) * 3 * static_cast<size_t>(nnz));
+    h = take(sizeof(double) * static_cast<size_t>(n));
+    kappa = take(sizeof(double) * static_cast<size_t>(n));
+    k = take(sizeof(int) * static_cast<size_t>(n));
+    iters = take(sizeof(int) * static_cast<size_t>(n));
+    active = take(static_cast<size_t>(n));
+    status = take(static_cast<size_t>(n));
+    remaining = take(sizeof(int));
+    total = o;
+  }
+};
+
+extern "C" size_t labfm_optimise_workspace_bytes(int32_t n, int64_t nnz) {
+  return (n > 0 && nnz >= 0) ? OptLayout(n, nnz).total : 0;
+}
+
 extern "C" int labfm_optimise_stencils(const double* x, const double* y, const double* h0,
                                        const double* s, const int8_t* order_m, int32_t n,
                                        labfm_box box, const int32_t* row_ptr, const int32_t* col,
@@ -2480,31 +2474,76 @@ extern "C" int labfm_optimise_stencils(const double* x, const double* y, const d
   LABFM_REQUIRE(p.shrink > 0.0 && p.shrink < 1.0 && p.gain_max > 0.0 && p.res_coef > 0.0 &&
                     p.max_iter >= 0 && p.max_iter <= 10000,
                 "optimise_stencils: bad parameters");
-  LABFM_WORKSPACE(workspace, workspace_bytes, build_work_bytes(n), "optimise_stencils");
+  const OptLayout L(n, nnz);
+  LABFM_WORKSPACE(workspace, workspace_bytes, L.total, "optimise_stencils");
   hipStream_t st = as_stream(stream_);
-  int* list = static_cast<int*>(workspace) + kBuildWorkInts;
+  char* base = static_cast<char*>(workspace);
+  int* work = reinterpret_cast<int*>(base + L.list);
+  int* list = work + kBuildWorkInts;
   int starts[17] = {0};
-  if (int r = order_buckets(order_m, n, static_cast<int*>(workspace), starts, st)) return r;
+  if (int r = order_buckets(order_m, n, work, starts, st)) return r;
+  // bucket b holds order 15 - b: orders 10..1 are buckets 5..14
   int mmax = 0;
-  for (int b = 0; b < 16; ++b)
+  for (int b = 5; b <= 14; ++b)
     if (starts[b + 1] > starts[b]) {
       mmax = 15 - b;
       break;
     }
+  const int first = starts[5], count = starts[15] - starts[5];
   OptArgs a{};
-  a.b = BuildArgs{x, y, h0, s, order_m, n, box, row_ptr, col, nnz, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, rows_of_mask(0x3F)};
+  a.x = x;
+  a.y = y;
+  a.s = s;
+  a.order = order_m;
+  a.box = box;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.nnz = nnz;
+  a.w = reinterpret_cast<double*>(base + L.w);
+  a.status = reinterpret_cast<int8_t*>(base + L.status);
+  a.h = reinterpret_cast<double*>(base + L.h);
+  a.k = reinterpret_cast<int*>(base + L.k);
+  a.active = reinterpret_cast<int8_t*>(base + L.active);
+  a.remaining = reinterpret_cast<int*>(base + L.remaining);
   a.h_out = h_out;
-  a.iters = iters;
+  a.iters = iters ? iters : reinterpret_cast<int*>(base + L.iters);
   a.shrink = p.shrink;
   a.gain_max = p.gain_max;
   a.res_coef = p.res_coef;
   a.max_iter = p.max_iter;
-  const hipError_t e = with_mmax(mmax, [&](auto M) {
-    hipLaunchKernelGGL(optimise_block_kernel<decltype(M)::value>, dim3(n), dim3(kBlock), 0, st,
-                       a, list, n);
-    return hipGetLastError();
-  });
-  LABFM_HIP(e);
-  return LABFM_OK;
+  hipLaunchKernelGGL(stencil_opt_init_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, h0,
+                     order_m, n, a.h, a.k, a.active, a.h_out, a.iters, a.remaining, count);
+  LABFM_HIP(hipGetLastError());
+  if (count == 0) return LABFM_OK;
+  // x, y and L weights of the nodes still shrinking, at their current scales
+  BuildArgs g{x, y, a.h, s, order_m, n, box, row_ptr, col, nnz,
+              reinterpret_cast<double*>(base + L.w), nullptr, nullptr,
+              reinterpret_cast<double*>(base + L.kappa), nullptr,
+              reinterpret_cast<int8_t*>(base + L.status),
+              rows_of_mask((1u << LABFM_OP_X) | (1u << LABFM_OP_Y) | (1u << LABFM_OP_L))};
+  g.active = a.active;
+  // a node takes at most max_iter + 2 tests (the last one rejected)
+  for (int pass = 0; pass <= p.max_iter + 1; ++pass) {
+    for (int m = 1; m <= kMaxOrder; ++m) {
+      const int b = 15 - m;
+      const int cnt = starts[b + 1] - starts[b];
+      if (cnt <= 0) continue;
+      const hipError_t e = with_rows_order(m, [&](auto M) {
+        return launch_rows<decltype(M)::value>(g, list + starts[b], cnt, st);
+      });
+      LABFM_HIP(e);
+    }
+    const hipError_t e = with_mmax(mmax, [&](auto M) {
+      hipLaunchKernelGGL(stencil_accept_kernel<decltype(M)::value>, dim3(count), dim3(64), 0, st,
+                         a, list + first, count);
+      return hipGetLastError();
+    });
+    LABFM_HIP(e);
+    int left = 0;
+    LABFM_HIP(hipMemcpyAsync(&left, a.remaining, sizeof(int), hipMemcpyDeviceToHost, st));
+    LABFM_HIP(hipStreamSynchronize(st));
+    if (left == 0) return LABFM_OK;
+  }
+  set_error("optimise_stencils: %s", "nodes still shrinking after max_iter + 2 passes");
+  return LABFM_ERR_HIP;
 }

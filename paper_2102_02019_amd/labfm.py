@@ -120,6 +120,7 @@ _SIGNATURES = {
                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P,
                                               ctypes.c_size_t, _P]),
     "labfm_build_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "labfm_optimise_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64]),
     "labfm_build_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P, _P,
                                            ctypes.c_int64, ctypes.c_uint32, _P, _P, _P, _P, _P,
                                            _P, _P, ctypes.c_size_t, _P]),
@@ -700,7 +701,7 @@ def optimise_stencils(x, y, s, m, box, h0=None, shrink: float = 0.99, gain_max: 
     h = torch.empty(n, dtype=torch.float64, device=dev)
     iters = torch.empty(n, dtype=torch.int32, device=dev)
     prm = _StencilOptParams(float(shrink), float(gain_max), float(res_coef), int(max_iter))
-    ws = _workspace(lib().labfm_build_workspace_bytes(n), dev)
+    ws = _workspace(lib().labfm_optimise_workspace_bytes(n, col.numel()), dev)
     _check(lib().labfm_optimise_stencils(_ptr(x), _ptr(y), _ptr(h0), _ptr(s), _ptr(m), n,
                                          _box(box), _ptr(rp), _ptr(col), col.numel(),
                                          ctypes.byref(prm), _ptr(h), _ptr(iters), _ptr(ws),

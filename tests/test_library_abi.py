@@ -94,7 +94,7 @@ def test_calls_refuse_a_missing_or_short_workspace(lib):
     sizes = {"morton_order": lib.labfm_morton_workspace_bytes(n),
              "build_neighbours": lib.labfm_neighbours_workspace_bytes(n),
              "build_weights": lib.labfm_build_workspace_bytes(n),
-             "optimise_stencils": lib.labfm_build_workspace_bytes(n),
+             "optimise_stencils": lib.labfm_optimise_workspace_bytes(n, 10),
              "build_tiles": lib.labfm_tiles_workspace_bytes(),
              "time_step": lib.labfm_time_step_workspace_bytes()}
     for name, call in calls.items():
