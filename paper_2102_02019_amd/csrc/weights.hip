@@ -1818,11 +1818,13 @@ struct OptArgs {
 
 // LDS of the test (one wavefront per node) for a chunk of neighbours: the
 // scaled monomial factors x^a/a! and y^b/b!, the sequences sin(k_q x),
-// sin(k_q y), cos(k_q x), cos(k_q y) for q = 1..16, and the weights.
+// sin(k_q y), cos(k_q x), cos(k_q y) for q = 1..16 (wavenumber innermost,
+// so the amplitude lanes of one operator read consecutive words; padded to
+// 17 against conflicts of the lanes writing them), and the weights.
 template <int MMAX>
 struct AcceptSmem {
   double tab[kChunk][2][MMAX + 1];
-  double trig[4][kNk][kChunk];
+  double trig[kChunk][4][kNk + 1];
   double wv[3][kChunk];
 };
 
@@ -1879,13 +1881,27 @@ stencil_accept_kernel(OptArgs a, const int* __restrict__ list, int count) {
   double amp = 0.0;
   // chunk lanes: neighbour kk of the chunk, sequence t
   const int kk = lane >> 2, t = lane & 3;
+  // the lane's neighbour one chunk ahead: coordinates and weight (t < 3)
+  double xn = 0.0, yn = 0.0, wn = 0.0;
+  if (kk < K) {
+    const int j = a.col[e0 + kk];
+    xn = a.x[j];
+    yn = a.y[j];
+    if (t < 3) wn = a.w[t * a.nnz + e0 + kk];
+  }
   for (int k0 = 0; k0 < K; k0 += kChunk) {
     const bool have = k0 + kk < K;
+    const double xj = xn, yj = yn, wj = wn;
+    if (k0 + kChunk + kk < K) {  // in flight while this chunk is tested
+      const int j = a.col[e0 + k0 + kChunk + kk];
+      xn = a.x[j];
+      yn = a.y[j];
+      if (t < 3) wn = a.w[t * a.nnz + e0 + k0 + kChunk + kk];
+    }
     double dx = 0.0, dy = 0.0;
     if (have) {
-      const int j = a.col[e0 + k0 + kk];
-      dx = wrap_axis(a.x[j] - xi, a.box.Lx, px);
-      dy = wrap_axis(a.y[j] - yi, a.box.Ly, py);
+      dx = wrap_axis(xj - xi, a.box.Lx, px);
+      dy = wrap_axis(yj - yi, a.box.Ly, py);
     }
     if (t < 2) {
       const double z = (t == 0 ? dx : dy) * hinv;
@@ -1897,20 +1913,24 @@ stencil_accept_kernel(OptArgs a, const int* __restrict__ list, int count) {
         sm.tab[kk][t][q] = have ? v : 0.0;
       }
     }
-    if (t < 3) sm.wv[t][kk] = have ? a.w[t * a.nnz + e0 + k0 + kk] : 0.0;
+    if (t < 3) sm.wv[t][kk] = have ? wj : 0.0;
     {
-      // f(q+1) = 2 cos(theta) f(q) - f(q-1), from sin or cos of theta
-      const double d = (t == 0 || t == 2) ? dx : dy;
-      double sn, cs;
-      sincos(k1 * d, &sn, &cs);
+      // f(q+1) = 2 cos(theta) f(q) - f(q-1), from sin or cos of theta; the
+      // sine lanes (t = 0: x, 1: y) form sin and cos of their angle once and
+      // pass them to the cosine lanes (t = 2, 3) of the same neighbour
+      double sn = 0.0, cs = 0.0;
+      if (t < 2) sincos(k1 * (t == 0 ? dx : dy), &sn, &cs);
+      const int from = (lane & ~3) | (t & 1);
+      sn = __shfl(sn, from, 64);
+      cs = __shfl(cs, from, 64);
       double f0 = (t < 2) ? 0.0 : 1.0, f1 = (t < 2) ? sn : cs;
-      sm.trig[t][0][kk] = f1;
+      sm.trig[kk][t][0] = f1;
 #pragma unroll
       for (int q = 1; q < kNk; ++q) {
         const double f2 = 2.0 * cs * f1 - f0;
         f0 = f1;
         f1 = f2;
-        sm.trig[t][q][kk] = f1;
+        sm.trig[kk][t][q] = f1;
       }
     }
     lds_barrier();
@@ -1919,8 +1939,8 @@ stencil_accept_kernel(OptArgs a, const int* __restrict__ list, int count) {
       if (lane < n) res0 += (sm.tab[c][0][pa0] * sm.tab[c][1][pb0]) * wl;
       if (lane + 64 < n) res1 += (sm.tab[c][0][pa1] * sm.tab[c][1][pb1]) * wl;
       if (lane < 3 * kNk) {
-        const double f = (aop == 2) ? 0.5 - 0.5 * sm.trig[2][aq][c] * sm.trig[3][aq][c]
-                                    : sm.trig[aop][aq][c];
+        const double f = (aop == 2) ? 0.5 - 0.5 * sm.trig[c][2][aq] * sm.trig[c][3][aq]
+                                    : sm.trig[c][aop][aq];
         amp += sm.wv[aop][c] * f;
       }
     }
