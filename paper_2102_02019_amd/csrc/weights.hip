@@ -1229,10 +1229,14 @@ __device__ __forceinline__ void rhs_row(int a, int b, int m, double h, double* c
 }
 
 // Wavefronts per SIMD the rows kernel is compiled for (its registers: the
-// rows, n + 6 doubles each, plus the assembly's accumulators in AGPRs).
+// row, n + 6 doubles, and the assembly's accumulators). Measured at m = 8:
+// four waves (128 registers; the LU keeps everything in registers, the
+// assembly reloads a few values per neighbour chunk) take 6.89 ms against
+// 7.06 ms at three (164 registers, no spills), with the same results; five at
+// m <= 6 gain nothing; three at m = 9 would spill in the LU.
 template <int M>
 constexpr int rows_waves() {
-  return M <= 6 ? 4 : (M <= 8 ? 3 : 2);
+  return M <= 8 ? 4 : 2;
 }
 
 template <int M>
