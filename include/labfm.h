@@ -156,12 +156,15 @@ typedef struct {
 
 /* Kernel timings collected by labfm_rk_step when requested. Durations are
  * measured with HIP events recorded on the call's stream around each launch
- * (summed over the launches of the call). */
+ * of the timed steps (summed over them). `every` is read: one step in every
+ * `every` is timed (0 or 1: all of them), the others run without events, so
+ * a long run is sampled without an event pair and a host query per launch. */
 typedef struct {
-  double stage_ms;        /* all Runge-Kutta stage launches */
-  double filter_ms;       /* all filter launches */
-  int64_t stage_launches;
+  double stage_ms;        /* timed Runge-Kutta stage launches */
+  double filter_ms;       /* timed filter launches */
+  int64_t stage_launches; /* launches timed */
   int64_t filter_launches;
+  int32_t every;          /* input: time steps 0, every, 2 every, ... */
 } labfm_timing;
 
 /* Gather kernels whose launch shape can be chosen (labfm_set_launch_config,

@@ -116,17 +116,21 @@ extern "C" int labfm_rk_step(double* q, const labfm_operators* ops, const labfm_
   plan.Yb = Yb;
 
   if (timing) {
-    // event-timed launches (no graph); 6 marks per step
+    // event-timed launches (no graph); 6 marks per timed step, one step in
+    // every `every` timed
     std::lock_guard<std::mutex> lock(g_event_mutex);
     const int per_step = 6;
-    LABFM_HIP(reserve_events(static_cast<size_t>(per_step) * n_steps));
+    const int every = timing->every > 1 ? timing->every : 1;
+    const int timed = (n_steps + every - 1) / every;
+    LABFM_HIP(reserve_events(static_cast<size_t>(per_step) * timed));
     double stage = 0.0, filt = 0.0;
     long long ns = 0, nf = 0;
     Marks mk{g_events.data(), 0};
     hipError_t e = hipSuccess;
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = enqueue_step_any(plan, st, &mk);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k)
+      e = enqueue_step_any(plan, st, (k % every == 0) ? &mk : nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+    for (int k = 0; k < timed && e == hipSuccess; ++k) {
       for (int l = 0; l < 5 && e == hipSuccess; ++l) {
         float ms = 0.0f;
         e = hipEventElapsedTime(&ms, g_events[k * per_step + l], g_events[k * per_step + l + 1]);

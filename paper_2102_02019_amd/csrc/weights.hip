@@ -1844,7 +1844,7 @@ stencil_opt_init_kernel(const double* __restrict__ h0, const int8_t* __restrict_
   k[i] = 0;
   h_out[i] = h0[i];
   iters[i] = 0;
-  active[i] = (order[i] >= 1 && order[i] <= 10) ? 1 : 0;
+  active[i] = (order[i] >= 1 && order[i] <= kMaxOrder) ? 1 : 0;
 }
 
 // The test of node i at its current scale h:

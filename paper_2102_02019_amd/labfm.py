@@ -104,7 +104,8 @@ class _BuildConfig(ctypes.Structure):
 
 class _Timing(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double), ("filter_ms", ctypes.c_double),
-                ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64)]
+                ("stage_launches", ctypes.c_int64), ("filter_launches", ctypes.c_int64),
+                ("every", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -529,15 +530,18 @@ def rk_workspace(n: int, device) -> torch.Tensor:
 
 def rk_step(q: torch.Tensor, ops: Operators, flow, dt: float, n_steps: int, prec: int = F64,
             use_graph: bool = False, filter: bool = True, check_finite: bool = False,
-            workspace: Optional[torch.Tensor] = None, timing: bool = False):
+            workspace: Optional[torch.Tensor] = None, timing: bool = False,
+            timing_every: int = 1):
     """Advance q = [ln rho | u | v] (float64, 3n) in place by n_steps RK steps.
-    Returns the per-kernel timing dict when ``timing`` is set."""
+    Returns the per-kernel timing dict when ``timing`` is set (event timings
+    of one step in every ``timing_every``)."""
     if workspace is None:
         workspace = rk_workspace(ops.n, q.device)
     prm = _RKParams(float(flow.c2), float(flow.mu), float(getattr(flow, "gx", 0.0)),
                     float(getattr(flow, "gy", 0.0)), float(dt), int(filter), int(check_finite))
     c = ops._c()
     tm = _Timing()
+    tm.every = int(timing_every)
     code = lib().labfm_rk_step(_ptr(q), ctypes.byref(c), ctypes.byref(prm), int(n_steps), prec,
                                int(use_graph), _ptr(workspace), workspace.numel(),
                                ctypes.byref(tm) if timing else None, _stream())

@@ -449,6 +449,22 @@ def test_rk_timing_counts(dev, tg64):
     assert tm["stage_ms"] > 0 and tm["filter_ms"] > 0
 
 
+def test_rk_timing_one_step_in_every(dev, tg64):
+    """Timing steps 0, 2 and 4 of five: three steps' launches are timed, and
+    the state is the one of the same steps run without events."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops, _ = tg64
+    prm = inputs.taylor_green_params()
+    q0 = T(np.concatenate(_tg_state(nodes)), dev)
+    q1, q2 = q0.clone(), q0.clone()
+    tm = labfm.rk_step(q1, ops, prm, 0.008, 5, timing=True, timing_every=2)
+    labfm.rk_step(q2, ops, prm, 0.008, 5)
+    assert tm["stage_launches"] == 12 and tm["filter_launches"] == 3
+    assert tm["stage_ms"] > 0 and tm["filter_ms"] > 0
+    assert torch.equal(q1, q2)
+
+
 # -------------------------------------------------- full size (262,144 nodes)
 
 @pytest.fixture(scope="module")
