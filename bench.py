@@ -169,13 +169,20 @@ def main():
         ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=True)
         return labfm.tune(ops, q0, prec, reps=10, workspace=ws)
 
+    setup_ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
     def job(prec):
+        setup_ev[0].record()
         rp, col = labfm.build_neighbours(x, y, h, nodes.box)
         ops = labfm.build_weights(x, y, h, s, m, nodes.box, rp, col, f32=(prec != labfm.F64))
         q.copy_(q0)
         dt = labfm.time_step(q, s, prm.c2, prm.mu, visc=wl.visc_coef)
+        setup_ev[1].record()
         tm = labfm.rk_step(q, ops, prm, dt, rk_steps, prec=prec, workspace=ws, timing=True,
                            timing_every=TIMING_EVERY)
+        # the stencil search, build, tiles and dt of this job (the RK call
+        # synchronises, so both events have completed)
+        tm["setup_ms"] = setup_ev[0].elapsed_time(setup_ev[1])
         return ops, tm
 
     def timed(prec, steps, warmup):
@@ -286,7 +293,7 @@ def main():
                           "frac": bytes_filter / (filter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "bytes_per_node": 12.0 * kbar + 56.0},
         "build": build,
-        "setup_ms_per_job": sec * 1e3 - rk_steps * (4 * stage_ms + filter_ms),
+        "setup_ms_per_job": sum(t["setup_ms"] for t in tms) / len(tms),
         "timed_launches": f"one RK step in {TIMING_EVERY} of every job carries HIP events",
         "final_state_finite": finite,
         "node_status_histogram": status_hist,
