@@ -125,15 +125,18 @@ def neighbours_bruteforce(x, y, h, box) -> tuple:
     return row_ptr, col
 
 
-def neighbours(x, y, h, box) -> tuple:
-    """Same set as ``neighbours_bruteforce``. Above a few thousand nodes the
-    candidates come from scipy's k-d tree with a slightly enlarged radius and
-    every candidate is then tested with the exact predicate above."""
+def neighbours(x, y, h, box, nodes=None) -> tuple:
+    """Same set as ``neighbours_bruteforce``. Above a few thousand nodes (or
+    for a range of rows) the candidates come from scipy's k-d tree with a
+    slightly enlarged radius and every candidate is then tested with the
+    exact predicate above. ``nodes``: a range of rows to compute (the CSR
+    then has the other rows empty), for node sets split over processes."""
     n = x.size
-    if n <= 4096:
+    if n <= 4096 and nodes is None:
         return neighbours_bruteforce(x, y, h, box)
     from scipy.spatial import cKDTree
 
+    rows_of = range(n) if nodes is None else nodes
     pts = np.stack([x, y], axis=1)
     boxsize = None
     if box.periodic_x and box.periodic_y:
@@ -144,16 +147,20 @@ def neighbours(x, y, h, box) -> tuple:
     rows = []
     hmax = float(h.max())
     # candidates within the largest radius, then the per-node predicate
-    cand = tree.query_ball_point(pts, r=2.0 * hmax * (1.0 + 1e-9), return_sorted=True)
-    for i in range(n):
-        c = np.asarray(cand[i], dtype=np.int64)
+    sel = np.asarray(rows_of, dtype=np.int64)
+    assert np.all(np.diff(sel) > 0), "rows in increasing order"
+    cand = tree.query_ball_point(pts[sel], r=2.0 * hmax * (1.0 + 1e-9), return_sorted=True)
+    for k, i in enumerate(sel):
+        c = np.asarray(cand[k], dtype=np.int64)
         c = c[c != i]
         dx = min_image(x[c] - x[i], box.Lx, box.periodic_x)
         dy = min_image(y[c] - y[i], box.Ly, box.periodic_y)
         rows.append(np.sort(c[in_stencil(dx, dy, h[i])]))
+    counts = np.zeros(n, dtype=np.int64)
+    counts[sel] = [r.size for r in rows]
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    row_ptr[1:] = np.cumsum([r.size for r in rows])
-    col = np.concatenate(rows).astype(np.int64)
+    row_ptr[1:] = np.cumsum(counts)
+    col = np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, np.int64)
     return row_ptr, col
 
 

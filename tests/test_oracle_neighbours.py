@@ -63,6 +63,18 @@ def test_tree_path_matches_bruteforce():
     assert np.array_equal(rp1, rp2) and np.array_equal(col1, col2)
 
 
+def test_row_ranges_match_bruteforce():
+    """Rows computed a range at a time (as when a large node set is split over
+    processes) are the brute-force rows, and the other rows stay empty."""
+    nodes = inputs.jittered_lattice(40, seed=9, m=8)
+    rp2, col2 = O.neighbours_bruteforce(nodes.x, nodes.y, nodes.h, nodes.box)
+    for a, b in ((0, 1), (100, 517), (1590, nodes.n)):
+        rp, col = O.neighbours(nodes.x, nodes.y, nodes.h, nodes.box, nodes=range(a, b))
+        assert np.all(np.diff(rp)[:a] == 0) and np.all(np.diff(rp)[b:] == 0)
+        for i in range(a, b):
+            assert np.array_equal(col[rp[i]:rp[i + 1]], col2[rp2[i]:rp2[i + 1]]), i
+
+
 def test_periodic_wrap_and_tie_included():
     # four points: a corner pair that only touch through both periodic edges,
     # and a pair at exactly 2h (0.5 = 2 * 0.25, all exactly representable)
