@@ -293,9 +293,37 @@ if __name__ == "__main__":
 """
 
 
-@pytest.mark.skipif(os.environ.get("LABFM_FULL_ORACLE") != "1",
-                    reason="opt-in (LABFM_FULL_ORACLE=1): the oracle on all 4,194,304 nodes "
-                           "takes about 16 CPU processes for several minutes")
+def _run_oracle_child(text, tmp_path, timeout):
+    """Runs a child script in a session of its own (its worker processes
+    with it); on a time-out or a failure the whole group is killed."""
+    import signal
+    import subprocess
+    import sys
+
+    script = tmp_path / "oracle_child.py"
+    script.write_text(text)
+    # the child's progress lines go to this process's output (run with -s to
+    # see them as they come)
+    p = subprocess.Popen([sys.executable, "-u", str(script)], start_new_session=True)
+    try:
+        rc = p.wait(timeout=timeout)
+    finally:
+        if p.poll() is None or p.returncode != 0:
+            try:
+                os.killpg(p.pid, signal.SIGKILL)
+            except ProcessLookupError:
+                pass
+            p.wait()
+    assert rc == 0, rc
+
+
+FULL_ORACLE_SKIP = pytest.mark.skipif(
+    os.environ.get("LABFM_FULL_ORACLE") != "1",
+    reason="opt-in (LABFM_FULL_ORACLE=1): the oracle on all 4,194,304 nodes takes 16 CPU "
+           "processes for several minutes")
+
+
+@FULL_ORACLE_SKIP
 def test_full_field_oracle_4m(dev, tg2048, tmp_path):
     """Every node of the 4,194,304-node set against the oracle: its stencil
     bit-exact, and the right-hand side of eq. icns (every operator of the
@@ -303,9 +331,6 @@ def test_full_field_oracle_4m(dev, tg2048, tmp_path):
     accuracy against the closed form, node by node: the float64 path's
     largest error at most 10 times the oracle's (floor 1e-13 of the field's
     scale), as in the sampled test, whose reasons hold here."""
-    import subprocess
-    import sys
-
     from paper_2102_02019_amd import labfm
 
     nodes, ops = tg2048
@@ -324,12 +349,7 @@ def test_full_field_oracle_4m(dev, tg2048, tmp_path):
     procs = max(1, min(16, os.cpu_count() or 1))
     child = FULL_ORACLE_CHILD.format(root=ROOT, d=str(tmp_path), Lx=float(nodes.box.Lx),
                                      Ly=float(nodes.box.Ly), chunk=65536, procs=procs)
-    script = tmp_path / "full_oracle.py"
-    script.write_text(child)
-    # the child's progress lines go to this process's output (run with -s to
-    # see them as they come)
-    r = subprocess.run([sys.executable, "-u", str(script)], timeout=3000)
-    assert r.returncode == 0, r.returncode
+    _run_oracle_child(child, tmp_path, 3000)
     assert int((tmp_path / "bad_rows.txt").read_text()) == 0
     ref = np.load(tmp_path / "rhs_oracle.npy")
     exact = _tg_rhs_exact(x, y, amp, prm)
@@ -340,6 +360,156 @@ def test_full_field_oracle_4m(dev, tg2048, tmp_path):
     print(f"all {nodes.n} nodes: gpu vs closed form {e_gpu.tolist()}, oracle vs closed form "
           f"{e_oracle.tolist()}, gpu vs oracle relative l2 {l2.tolist()}")
     assert np.all(e_gpu <= 10 * np.maximum(e_oracle, 1e-13 * scale)), (e_gpu, e_oracle)
+
+
+# The oracle's filtered RK steps over every node of the 4,194,304-node set:
+# each of the child's workers owns a contiguous range of rows, builds the
+# oracle stencils and weights of its rows once, and evaluates the oracle's
+# right-hand side and filter on them whenever the driver (the oracle's own
+# rk_integrate) asks; the fields pass through shared memory.
+FULL_RK_CHILD = r"""
+import os, sys
+os.environ["OPENBLAS_NUM_THREADS"] = "1"
+os.environ["OMP_NUM_THREADS"] = "1"
+sys.path.insert(0, {root!r})
+import numpy as np
+from multiprocessing import get_context, shared_memory
+from oracle import labfm_oracle as O
+from paper_2102_02019_amd import inputs
+
+D = {d!r}
+A = {{k: np.load(os.path.join(D, k + ".npy"), mmap_mode="r")
+     for k in ("x", "y", "h", "s", "m", "lnrho", "u", "v")}}
+BOX = inputs.Box({Lx!r}, {Ly!r}, True, True)
+PRM = inputs.taylor_green_params(L={L!r})
+N = A["x"].size
+
+
+def worker(conn, a, b, shm_name):
+    shm = shared_memory.SharedMemory(name=shm_name)
+    F = np.ndarray((3, N), dtype=np.float64, buffer=shm.buf)
+    x, y, h, s, m = (np.asarray(A[k]) for k in ("x", "y", "h", "s", "m"))
+    rp, col = O.neighbours(x, y, h, BOX, nodes=range(a, b))
+    W = None
+    for i0 in range(a, b, 32768):  # a sub-range at a time, each reported
+        i1 = min(b, i0 + 32768)
+        Wi = O.weights(x, y, h, s, m, rp, col, BOX, nodes=range(i0, i1))
+        if W is None:
+            W = Wi
+        else:
+            W["w"][:, rp[i0]:rp[i1]] = Wi["w"][:, rp[i0]:rp[i1]]
+            W["rowsum"][:, i0:i1] = Wi["rowsum"][:, i0:i1]
+            W["kappa"][i0:i1] = Wi["kappa"][i0:i1]
+            W["status"][i0:i1] = Wi["status"][i0:i1]
+        print(f"oracle weights of rows {{i0}}..{{i1}} done", flush=True)
+    W.update(row_ptr=rp, col=col)
+    conn.send(int(np.sum(W["status"][a:b] != 0)))
+    while True:
+        cmd = conn.recv()
+        if cmd == "stop":
+            break
+        fields = (F[0], F[1], F[2])
+        out = O.ns_rhs(*fields, W, PRM) if cmd == "rhs" else O.filter_fields(fields, W)
+        conn.send(np.stack([c[a:b] for c in out]))
+    del F, fields
+    shm.close()
+
+
+if __name__ == "__main__":
+    procs = {procs!r}
+    steps = {steps!r}
+    ctx = get_context("fork")
+    shm = shared_memory.SharedMemory(create=True, size=3 * N * 8)
+    F = np.ndarray((3, N), dtype=np.float64, buffer=shm.buf)
+    bounds = np.linspace(0, N, procs + 1).astype(int)
+    pipes, workers = [], []
+    try:
+        for k in range(procs):
+            mine, theirs = ctx.Pipe()
+            w = ctx.Process(target=worker, args=(theirs, bounds[k], bounds[k + 1], shm.name),
+                            daemon=True)
+            w.start()
+            theirs.close()
+            pipes.append(mine)
+            workers.append(w)
+        flagged = sum(p.recv() for p in pipes)
+        print(f"oracle stencils and weights on all {{N}} nodes; nodes with a status: {{flagged}}",
+              flush=True)
+
+        def fan(cmd, fields):
+            for k in range(3):
+                F[k] = fields[k]
+            for p in pipes:
+                p.send(cmd)
+            out = np.empty((3, N))
+            for k, p in enumerate(pipes):
+                out[:, bounds[k]:bounds[k + 1]] = p.recv()
+            return tuple(out)
+
+        done = [0]
+
+        def filt(q):
+            done[0] += 1
+            print(f"oracle step {{done[0]}} / {{steps}}", flush=True)
+            return fan("filter", q)
+
+        l0, u0, v0 = (np.array(A[k]) for k in ("lnrho", "u", "v"))
+        dt = O.time_step(np.asarray(A["s"]), l0, u0, v0, PRM, visc_coef={visc!r})
+        q = O.rk_integrate((l0, u0, v0), lambda l, u, v: fan("rhs", (l, u, v)), dt, steps,
+                           after_step=filt)
+        for p in pipes:
+            p.send("stop")
+        for w in workers:
+            w.join()
+        np.save(os.path.join(D, "q_oracle.npy"), np.stack(q))
+        with open(os.path.join(D, "oracle.txt"), "w") as f:
+            f.write(f"{{dt!r}} {{flagged}}")
+    finally:
+        for w in workers:
+            if w.is_alive():
+                w.kill()
+        del F
+        shm.close()
+        shm.unlink()
+"""
+
+
+@FULL_ORACLE_SKIP
+def test_full_field_rk_oracle_4m(dev, tg2048, tmp_path):
+    """Ten filtered RK steps of the 4,194,304-node set from a perturbed
+    Taylor-Green state, on the GPU and in the oracle over every node (its own
+    stencils, weights, right-hand sides, filter and dt, eq. dt with the
+    workload's viscous coefficient): the same dt, and every field of the
+    final state (density as rho = exp(ln rho)) within 1e-12 relative."""
+    from paper_2102_02019_amd import labfm
+
+    nodes, ops = tg2048
+    wl = inputs.TG2048_M8
+    prm = inputs.taylor_green_params(L=wl.L)
+    rho, u, v = inputs.taylor_green_state(nodes.x, nodes.y, L=wl.L)
+    lnrho = np.log(rho) + 0.05 * np.sin(nodes.x + 2 * nodes.y)
+    q = T(np.concatenate([lnrho, u, v]), dev)
+    dt = labfm.time_step(q, T(nodes.s, dev), prm.c2, prm.mu, visc=wl.visc_coef)
+    steps = 10
+    labfm.rk_step(q, ops, prm, dt, steps)
+    got = q.cpu().numpy().reshape(3, -1)
+    arrays = {"x": nodes.x, "y": nodes.y, "h": nodes.h, "s": nodes.s, "m": nodes.m,
+              "lnrho": lnrho, "u": u, "v": v}
+    for k, a in arrays.items():
+        np.save(tmp_path / f"{k}.npy", np.ascontiguousarray(a))
+    procs = max(1, min(16, os.cpu_count() or 1))
+    child = FULL_RK_CHILD.format(root=ROOT, d=str(tmp_path), Lx=float(nodes.box.Lx),
+                                 Ly=float(nodes.box.Ly), L=float(wl.L), procs=procs,
+                                 steps=steps, visc=float(wl.visc_coef))
+    _run_oracle_child(child, tmp_path, 3000)
+    dt_o, flagged = (tmp_path / "oracle.txt").read_text().split()
+    assert int(flagged) == 0
+    assert math.isclose(dt, float(dt_o), rel_tol=1e-14), (dt, dt_o)
+    ref = np.load(tmp_path / "q_oracle.npy")
+    pairs = ((np.exp(got[0]), np.exp(ref[0])), (got[1], ref[1]), (got[2], ref[2]))
+    rel = [float(np.linalg.norm(g - r) / np.linalg.norm(r)) for g, r in pairs]
+    print(f"all {nodes.n} nodes after {steps} steps: relative l2 (rho, u, v) {rel}")
+    assert max(rel) <= 1e-12, rel
 
 
 def test_mixed_precision_run_4m(dev, tg2048):
