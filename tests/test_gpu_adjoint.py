@@ -2,8 +2,6 @@
 (itself pinned by complex-step derivatives), independence from the checkpoint
 interval, and central finite differences on the adjoint workload
 (65,536 nodes, m = 6, 200 RK steps, checkpoints every 20)."""
-import math
-
 import numpy as np
 import pytest
 

@@ -1,7 +1,5 @@
 """Stencil optimisation on the GPU (section "Stencil optimisation") against
 the oracle's per-node loop, and the optimised stencils in use."""
-import math
-
 import numpy as np
 import pytest
 import torch

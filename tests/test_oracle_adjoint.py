@@ -1,7 +1,5 @@
 """Pins of the oracle's adjoint: exact transposes (dot-product tests) and
 complex-step directional derivatives of the filtered RK loop (CPU only)."""
-import math
-
 import numpy as np
 import pytest
 

@@ -1,9 +1,6 @@
 """Pins of the oracle's weight construction (equations disc_form, lsys, w_abf
 and hermite of the paper) by exactness, extended-precision solves and
 invariants (CPU only)."""
-import math
-
-import mpmath
 import numpy as np
 import pytest
 import sympy
