@@ -321,6 +321,34 @@ int labfm_build_weights_noalloc(const double* x, const double* y, const double* 
                                 double* kappa, double* rowsum, int8_t* status, void* stream);
 
 /*
+ * The weight build's LU with partial pivoting and back substitution on
+ * given systems M~ Psi = C~ (section "The Local Anisotropic Basis Function
+ * Method", the linear system of each node and its solution by LU with
+ * partial pivoting): the rows-in-registers kernel of LABFM_BUILD_ROWS runs
+ * them in place of the systems it assembles, one wavefront per system, so
+ * its pivot rule and solution can be checked against a host solver.
+ *
+ *   m          order 1..10; n = (m^2+3m)/2.
+ *   systems    float64[count*n*(n+6)] device, row-major: row r of system k
+ *              at (k*n + r)*(n+6), its n entries of M~, then its six of C~.
+ *   psi        float64[count*n*6] device output: Psi[k][q][d], the solution
+ *              column d in the operators' order (labfm_op).
+ *   pivot_row  int32[count*n] device output: [k][c] = the row (0..n-1, the
+ *              given order) whose entry was column c's pivot. The pivot of a
+ *              column is its largest |entry| among the rows not yet used,
+ *              magnitudes compared exactly (as their float64 bit patterns),
+ *              the lowest row on equal magnitudes.
+ *   status     int8[count] device output: LABFM_NODE_OK, or
+ *              LABFM_NODE_SINGULAR when a pivot is zero or not finite (then
+ *              psi and pivot_row of that system are not written).
+ * The buffers belong to the caller; nothing is allocated and the call does
+ * not synchronise. Returns LABFM_ERR_ARG for m outside 1..10, count < 0 or
+ * a null buffer (count > 0); count = 0 does nothing.
+ */
+int labfm_solve_systems(int32_t m, const double* systems, int32_t count, double* psi,
+                        int32_t* pivot_row, int8_t* status, void* stream);
+
+/*
  * Stencil optimisation (section "Stencil optimisation"): for every node, the
  * stencil scale h_i shrinks from h0_i by the factor `shrink` while the
  * stencil passes two tests, and the last scale that passed is kept (h0_i

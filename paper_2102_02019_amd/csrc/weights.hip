@@ -1239,199 +1239,237 @@ constexpr int rows_waves() {
   return M <= 8 ? 4 : 2;
 }
 
-template <int M>
-__global__ void __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(rows_waves<M>())))
-build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
+// Order 10's first pivot row among its 65 rows: lane l holds row l's
+// column-0 value c0 and every lane row 64's (v64). The largest |value|,
+// compared exactly (high words, then low words on a tie), the lowest row on
+// equal magnitudes.
+__device__ __forceinline__ int first_pivot_of_65(double c0, double v64) {
+  const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(fabs(c0)));
+  const unsigned hi = static_cast<unsigned>(bits >> 32);
+  const unsigned khi = wave_max_u32(hi);
+  unsigned long long cand = __builtin_amdgcn_ballot_w64(hi == khi);
+  if (__builtin_popcountll(cand) > 1) {
+    const unsigned lo = hi == khi ? static_cast<unsigned>(bits) : 0u;
+    const unsigned klo = wave_max_u32(lo);
+    cand = __builtin_amdgcn_ballot_w64(hi == khi && lo == klo);
+  }
+  const int pl = static_cast<int>(__builtin_ctzll(cand));
+  const double vl = readlane_f64(c0, pl);
+  const double v = readlane_f64(v64, 0);
+  // row 64 only when strictly larger
+  return static_cast<unsigned long long>(__double_as_longlong(fabs(v))) >
+                 static_cast<unsigned long long>(__double_as_longlong(fabs(vl)))
+             ? 64
+             : pl;
+}
+
+// Systems given to the rows kernel's LU and back substitution directly (its
+// solve variant): row r of system k at sys + (k n + r)(n + 6), its n values
+// of M~, then its six of C~.
+struct SolveArgs {
+  const double* sys = nullptr;
+  int count = 0;
+  double* psi = nullptr;     // [k][q][d]: the solution Psi
+  int* pivot_row = nullptr;  // [k][c]: the row whose pivot column c took
+  int8_t* status = nullptr;  // [k]: LABFM_NODE_OK or LABFM_NODE_SINGULAR
+};
+
+// One wavefront's work of the rows kernel: node list[blockIdx.x]'s build or,
+// with kSolve, system blockIdx.x of sv through the same LU and back
+// substitution (steps 3 and 4) in place of the assembly and the weights.
+template <int M, bool kSolve>
+__device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ list, int count,
+                                          SolveArgs sv) {
   using S = RowShape<M>;
   constexpr int N = S::N, NB = S::NB, RC = S::RC, TW = S::TW;
   __shared__ RowSmem<M> sm;
   const int k_ = blockIdx.x;
   if (k_ >= count) return;
   const int lane = threadIdx.x;
-  const int i = uniform(list ? list[k_] : k_);
-  if (g.active && uniform(g.active[i]) == 0) return;
-  const int e0 = uniform(g.row_ptr[i]);
-  const int K = uniform(g.row_ptr[i + 1]) - e0;
-  const double xi = g.x[i], yi = g.y[i], h = g.h[i], s = g.s[i];
+  const int i = kSolve ? k_ : uniform(list ? list[k_] : k_);
+  if (!kSolve && g.active && uniform(g.active[i]) == 0) return;
+  const int e0 = kSolve ? 0 : uniform(g.row_ptr[i]);
+  const int K = kSolve ? N : uniform(g.row_ptr[i + 1]) - e0;
+  const double xi = kSolve ? 0.0 : g.x[i], yi = kSolve ? 0.0 : g.y[i];
+  const double h = kSolve ? 1.0 : g.h[i], s = kSolve ? 1.0 : g.s[i];
   const int px = g.box.periodic_x, py = g.box.periodic_y;
   const double hinv = 1.0 / h;
   double* T = sm.buf;
 
-  // ---- 1, 2: basis tables, MFMA assembly, rows of M~ into registers ---------
-  // exponents of this lane's moment index in each tile (row p or column q)
-  int ea[NB], eb[NB];
-#pragma unroll
-  for (int P = 0; P < NB; ++P) {
-    const int p = P * 16 + (lane & 15);
-    if (p < N) {
-      exponents_of(p, ea[P], eb[P]);
-    } else {
-      ea[P] = -1;
-      eb[P] = -1;
-    }
-  }
-  // Column tiles per pass over the neighbours: all of them up to order 9;
-  // at order 10 (5 x 5 tiles, 200 registers of accumulators) three, then
-  // two, each group moved into the rows before the next pass, so the
-  // accumulators of all 25 tiles are never live at once.
-  constexpr int QG = S::kExtra ? 3 : NB;
-  const int kk = lane >> 2, t = lane & 3;  // table lanes: neighbour kk, table t
+  // lane l's row of [M~ | C~] (row myrow: l, or l + 1 from p0 on at order 10)
   double a[RC];
-  double* strip = sm.buf;  // the strips reuse the tables' LDS
-  // Order 10: p0, the pivot row of column 0 (the largest |M~_r0| of the 65
-  // rows, compared exactly, the lowest row on ties), is found in the first
-  // strip; it goes to LDS (sm.extra) and lane l takes row l, or l + 1 from p0
-  // on, so the other 64 rows fill the 64 lanes in order.
   int p0 = 64, myrow = lane;
-#pragma unroll
-  for (int Q0 = 0; Q0 < NB; Q0 += QG) {
-    const int QN = (NB - Q0 < QG) ? NB - Q0 : QG;
-    double4_t acc[NB][QG];
-#pragma unroll
-    for (int P = 0; P < NB; ++P)
-#pragma unroll
-      for (int Q = 0; Q < QG; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
-    // coordinates of the lane's neighbour one chunk ahead
-    double xn = 0.0, yn = 0.0;
-    if (kk < K) {
-      const int j = g.col[e0 + kk];
-      xn = g.x[j];
-      yn = g.y[j];
+  if constexpr (kSolve) {
+    // the given system's rows where the assembly leaves a node's (order 10:
+    // the first pivot row chosen as from the first strip, kept in LDS)
+    constexpr int W = N + LABFM_NUM_OPS;
+    const double* A = sv.sys + static_cast<long long>(k_) * N * W;
+    if constexpr (S::kExtra) {
+      p0 = first_pivot_of_65(A[static_cast<long long>(lane) * W], A[64LL * W]);
+      myrow = lane + (lane >= p0 ? 1 : 0);
+      for (int j = lane; j < RC; j += 64)
+        sm.extra[j] = j < W ? A[static_cast<long long>(p0) * W + j] : 0.0;
     }
-    if (lane < kChunk) T[lane * S::TABLE + S::ZERO] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += kChunk) {
-      const bool have = k0 + kk < K;
-      const double xj = xn, yj = yn;
-      if (k0 + kChunk + kk < K) {  // the next chunk's coordinates, in flight meanwhile
-        const int j = g.col[e0 + k0 + kChunk + kk];
+    const long long r = lane < N ? myrow : 0;
+#pragma unroll
+    for (int j = 0; j < RC; ++j) a[j] = (lane < N && j < W) ? A[r * W + j] : 0.0;
+    lds_barrier();
+  } else {
+    // ---- 1, 2: basis tables, MFMA assembly, rows of M~ into registers ---------
+    // exponents of this lane's moment index in each tile (row p or column q)
+    int ea[NB], eb[NB];
+#pragma unroll
+    for (int P = 0; P < NB; ++P) {
+      const int p = P * 16 + (lane & 15);
+      if (p < N) {
+        exponents_of(p, ea[P], eb[P]);
+      } else {
+        ea[P] = -1;
+        eb[P] = -1;
+      }
+    }
+    // Column tiles per pass over the neighbours: all of them up to order 9;
+    // at order 10 (5 x 5 tiles, 200 registers of accumulators) three, then
+    // two, each group moved into the rows before the next pass, so the
+    // accumulators of all 25 tiles are never live at once.
+    constexpr int QG = S::kExtra ? 3 : NB;
+    const int kk = lane >> 2, t = lane & 3;  // table lanes: neighbour kk, table t
+    double* strip = sm.buf;  // the strips reuse the tables' LDS
+    // Order 10: p0, the pivot row of column 0 (the largest |M~_r0| of the 65
+    // rows, compared exactly, the lowest row on ties), is found in the first
+    // strip; it goes to LDS (sm.extra) and lane l takes row l, or l + 1 from p0
+    // on, so the other 64 rows fill the 64 lanes in order.
+#pragma unroll
+    for (int Q0 = 0; Q0 < NB; Q0 += QG) {
+      const int QN = (NB - Q0 < QG) ? NB - Q0 : QG;
+      double4_t acc[NB][QG];
+#pragma unroll
+      for (int P = 0; P < NB; ++P)
+#pragma unroll
+        for (int Q = 0; Q < QG; ++Q) acc[P][Q] = double4_t{0.0, 0.0, 0.0, 0.0};
+      // coordinates of the lane's neighbour one chunk ahead
+      double xn = 0.0, yn = 0.0;
+      if (kk < K) {
+        const int j = g.col[e0 + kk];
         xn = g.x[j];
         yn = g.y[j];
       }
-      double* tab = &T[kk * S::TABLE + t * TW];
-      if (have) {
-        const double dx = wrap_axis(xj - xi, g.box.Lx, px);
-        const double dy = wrap_axis(yj - yi, g.box.Ly, py);
-        const double xs = dx * hinv, ys = dy * hinv;
-        const double z = (t == 0 || t == 2) ? xs : ys;
-        if (t < 2) {
-          double v = 1.0;
-          tab[0] = 1.0;
+      if (lane < kChunk) T[lane * S::TABLE + S::ZERO] = 0.0;
+      for (int k0 = 0; k0 < K; k0 += kChunk) {
+        const bool have = k0 + kk < K;
+        const double xj = xn, yj = yn;
+        if (k0 + kChunk + kk < K) {  // the next chunk's coordinates, in flight meanwhile
+          const int j = g.col[e0 + k0 + kChunk + kk];
+          xn = g.x[j];
+          yn = g.y[j];
+        }
+        double* tab = &T[kk * S::TABLE + t * TW];
+        if (have) {
+          const double dx = wrap_axis(xj - xi, g.box.Lx, px);
+          const double dy = wrap_axis(yj - yi, g.box.Ly, py);
+          const double xs = dx * hinv, ys = dy * hinv;
+          const double z = (t == 0 || t == 2) ? xs : ys;
+          if (t < 2) {
+            double v = 1.0;
+            tab[0] = 1.0;
 #pragma unroll
-          for (int a2 = 1; a2 <= M; ++a2) {
-            v = v * z * (1.0 / static_cast<double>(a2));  // z^a / a!
-            tab[a2] = v;
+            for (int a2 = 1; a2 <= M; ++a2) {
+              v = v * z * (1.0 / static_cast<double>(a2));  // z^a / a!
+              tab[a2] = v;
+            }
+          } else {
+            const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
+            double h0 = 1.0, h1 = z;
+            tab[0] = psi;
+            if (M >= 1) tab[1] = psi * z;
+#pragma unroll
+            for (int a2 = 1; a2 < M; ++a2) {
+              const double h2 = z * h1 - static_cast<double>(a2) * h0;
+              h0 = h1;
+              h1 = h2;
+              tab[a2 + 1] = psi * h2;
+            }
           }
         } else {
-          const double psi = (t == 2) ? wendland_c2(sqrt(xs * xs + ys * ys)) : 1.0;
-          double h0 = 1.0, h1 = z;
-          tab[0] = psi;
-          if (M >= 1) tab[1] = psi * z;
 #pragma unroll
-          for (int a2 = 1; a2 < M; ++a2) {
-            const double h2 = z * h1 - static_cast<double>(a2) * h0;
-            h0 = h1;
-            h1 = h2;
-            tab[a2 + 1] = psi * h2;
-          }
+          for (int a2 = 0; a2 <= M; ++a2) tab[a2] = 0.0;
         }
-      } else {
-#pragma unroll
-        for (int a2 = 0; a2 <= M; ++a2) tab[a2] = 0.0;
-      }
-      lds_barrier();
-#pragma unroll
-      for (int ks = 0; ks < kChunk / 4; ++ks) {
-        const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
-        double av[NB], bv[QG];
-#pragma unroll
-        for (int P = 0; P < NB; ++P) {
-          const int oa = ea[P] >= 0 ? ea[P] : S::ZERO, ob = ea[P] >= 0 ? TW + eb[P] : S::ZERO;
-          av[P] = tk[oa] * tk[ob];
-        }
-#pragma unroll
-        for (int Q = 0; Q < QG; ++Q) {
-          if (Q < QN) {
-            const int P = Q0 + Q;
-            const int oc = ea[P] >= 0 ? 2 * TW + ea[P] : S::ZERO;
-            const int od = ea[P] >= 0 ? 3 * TW + eb[P] : S::ZERO;
-            bv[Q] = tk[oc] * tk[od];
-          }
-        }
-#pragma unroll
-        for (int P = 0; P < NB; ++P)
-#pragma unroll
-          for (int Q = 0; Q < QG; ++Q)
-            if (Q < QN)
-              acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
-      }
-      lds_barrier();
-    }
-
-    // rows of this group's columns into registers, one 16-column strip at a
-    // time; element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
-#pragma unroll
-    for (int Q = 0; Q < QG; ++Q) {
-      if (Q < QN) {
-        const int QC = Q0 + Q;
-#pragma unroll
-        for (int P = 0; P < NB; ++P)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            strip[(P * 16 + (lane >> 4) + 4 * v) * S::SS + (lane & 15)] = acc[P][Q][v];
         lds_barrier();
-        if constexpr (S::kExtra) {
-          if (QC == 0) {
-            const double c0 = strip[lane * S::SS];
-            const unsigned long long bits =
-                static_cast<unsigned long long>(__double_as_longlong(fabs(c0)));
-            const unsigned hi = static_cast<unsigned>(bits >> 32);
-            const unsigned khi = wave_max_u32(hi);
-            unsigned long long cand = __builtin_amdgcn_ballot_w64(hi == khi);
-            if (__builtin_popcountll(cand) > 1) {
-              const unsigned lo = hi == khi ? static_cast<unsigned>(bits) : 0u;
-              const unsigned klo = wave_max_u32(lo);
-              cand = __builtin_amdgcn_ballot_w64(hi == khi && lo == klo);
+#pragma unroll
+        for (int ks = 0; ks < kChunk / 4; ++ks) {
+          const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
+          double av[NB], bv[QG];
+#pragma unroll
+          for (int P = 0; P < NB; ++P) {
+            const int oa = ea[P] >= 0 ? ea[P] : S::ZERO, ob = ea[P] >= 0 ? TW + eb[P] : S::ZERO;
+            av[P] = tk[oa] * tk[ob];
+          }
+#pragma unroll
+          for (int Q = 0; Q < QG; ++Q) {
+            if (Q < QN) {
+              const int P = Q0 + Q;
+              const int oc = ea[P] >= 0 ? 2 * TW + ea[P] : S::ZERO;
+              const int od = ea[P] >= 0 ? 3 * TW + eb[P] : S::ZERO;
+              bv[Q] = tk[oc] * tk[od];
             }
-            const int pl = static_cast<int>(__builtin_ctzll(cand));
-            const double vl = readlane_f64(c0, pl);
-            const double v64 = readlane_f64(strip[64 * S::SS], 0);
-            // row 64 only when strictly larger
-            p0 = static_cast<unsigned long long>(__double_as_longlong(fabs(v64))) >
-                         static_cast<unsigned long long>(__double_as_longlong(fabs(vl)))
-                     ? 64
-                     : pl;
-            myrow = lane + (lane >= p0 ? 1 : 0);
           }
-        }
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (QC * 16 + j < N) a[QC * 16 + j] = (lane < N) ? strip[myrow * S::SS + j] : 0.0;
-        if constexpr (S::kExtra) {
-          if (lane < 16 && QC * 16 + lane < N) sm.extra[QC * 16 + lane] = strip[p0 * S::SS + lane];
+          for (int P = 0; P < NB; ++P)
+#pragma unroll
+            for (int Q = 0; Q < QG; ++Q)
+              if (Q < QN)
+                acc[P][Q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[P], bv[Q], acc[P][Q], 0, 0, 0);
         }
         lds_barrier();
       }
-    }
-  }
-  int ra = 0, rb = 0;
-  if (lane < N) exponents_of(myrow, ra, rb);
-  {
-    double c[LABFM_NUM_OPS];
-    rhs_row(ra, rb, M, h, c);
+
+      // rows of this group's columns into registers, one 16-column strip at a
+      // time; element v of lane l holds D[l/16 + 4v][l%16] of its 16x16 tile
 #pragma unroll
-    for (int d = 0; d < LABFM_NUM_OPS; ++d) a[N + d] = (lane < N) ? c[d] : 0.0;
-    if (RC > N + LABFM_NUM_OPS) a[RC - 1] = 0.0;
-    if constexpr (S::kExtra) {
-      if (lane == 0) {
-        int a64, b64;
-        exponents_of(p0, a64, b64);
-        rhs_row(a64, b64, M, h, c);
+      for (int Q = 0; Q < QG; ++Q) {
+        if (Q < QN) {
+          const int QC = Q0 + Q;
 #pragma unroll
-        for (int d = 0; d < LABFM_NUM_OPS; ++d) sm.extra[N + d] = c[d];
-        if (RC > N + LABFM_NUM_OPS) sm.extra[RC - 1] = 0.0;
+          for (int P = 0; P < NB; ++P)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              strip[(P * 16 + (lane >> 4) + 4 * v) * S::SS + (lane & 15)] = acc[P][Q][v];
+          lds_barrier();
+          if constexpr (S::kExtra) {
+            if (QC == 0) {
+              p0 = first_pivot_of_65(strip[lane * S::SS], strip[64 * S::SS]);
+              myrow = lane + (lane >= p0 ? 1 : 0);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (QC * 16 + j < N) a[QC * 16 + j] = (lane < N) ? strip[myrow * S::SS + j] : 0.0;
+          if constexpr (S::kExtra) {
+            if (lane < 16 && QC * 16 + lane < N) sm.extra[QC * 16 + lane] = strip[p0 * S::SS + lane];
+          }
+          lds_barrier();
+        }
       }
-      lds_barrier();
+    }
+    int ra = 0, rb = 0;
+    if (lane < N) exponents_of(myrow, ra, rb);
+    {
+      double c[LABFM_NUM_OPS];
+      rhs_row(ra, rb, M, h, c);
+#pragma unroll
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) a[N + d] = (lane < N) ? c[d] : 0.0;
+      if (RC > N + LABFM_NUM_OPS) a[RC - 1] = 0.0;
+      if constexpr (S::kExtra) {
+        if (lane == 0) {
+          int a64, b64;
+          exponents_of(p0, a64, b64);
+          rhs_row(a64, b64, M, h, c);
+#pragma unroll
+          for (int d = 0; d < LABFM_NUM_OPS; ++d) sm.extra[N + d] = c[d];
+          if (RC > N + LABFM_NUM_OPS) sm.extra[RC - 1] = 0.0;
+        }
+        lds_barrier();
+      }
     }
   }
 
@@ -1569,6 +1607,14 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
       }
     }
     lds_barrier();
+    if constexpr (kSolve) {
+      const long long k = k_;
+      for (int j = lane; j < N * LABFM_NUM_OPS; j += 64) sv.psi[k * N * LABFM_NUM_OPS + j] = psi_t[j];
+      if (mycol >= 0 && mycol < N) sv.pivot_row[k * N + mycol] = myrow;
+      if (S::kExtra && lane == 0) sv.pivot_row[k * N] = p0;
+      if (lane == 0) sv.status[k] = LABFM_NODE_OK;
+      return;
+    }
 
     // ---- 5: weights, filter calibration, row sums, first moments -------------
     // one lane per neighbour; Psi read from LDS a row at a time (the lanes'
@@ -1740,6 +1786,10 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
           if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = rs[d];
     }
   } else {
+    if constexpr (kSolve) {
+      if (lane == 0) sv.status[k_] = LABFM_NODE_SINGULAR;
+      return;
+    }
     const long long s32 = w32_stride(g.nnz);
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
@@ -1758,6 +1808,20 @@ build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
         for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = 0.0f;
     }
   }
+}
+
+template <int M>
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(rows_waves<M>())))
+build_rows_kernel(BuildArgs g, const int* __restrict__ list, int count) {
+  rows_node<M, false>(g, list, count, SolveArgs{});
+}
+
+template <int M>
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(rows_waves<M>())))
+rows_solve_kernel(SolveArgs sv) {
+  rows_node<M, true>(BuildArgs{}, nullptr, sv.count, sv);
 }
 
 template <int M>
@@ -2353,6 +2417,28 @@ extern "C" int labfm_build_weights_noalloc(const double* x, const double* y, con
   if (int r = scratch_of_current_device(&work)) return r;
   return build_weights_with(x, y, h, s, order_m, n, box, row_ptr, col, nnz, op_mask, w, w32,
                             mom32, kappa, rowsum, status, work, as_stream(stream_));
+}
+
+extern "C" int labfm_solve_systems(int32_t m, const double* systems, int32_t count,
+                                   double* psi, int32_t* pivot_row, int8_t* status,
+                                   void* stream_) {
+  clear_error();
+  LABFM_REQUIRE(m >= 1 && m <= 10, "solve_systems: order %d outside 1..10", m);
+  LABFM_REQUIRE(count >= 0, "solve_systems: count %d < 0", count);
+  if (count == 0) return LABFM_OK;
+  LABFM_REQUIRE(systems && psi && pivot_row && status, "solve_systems: null pointer");
+  SolveArgs sv;
+  sv.sys = systems;
+  sv.count = count;
+  sv.psi = psi;
+  sv.pivot_row = pivot_row;
+  sv.status = status;
+  const hipStream_t st = as_stream(stream_);
+  LABFM_HIP(with_rows_order(m, [&](auto mc) -> hipError_t {
+    hipLaunchKernelGGL(rows_solve_kernel<decltype(mc)::value>, dim3(count), dim3(64), 0, st, sv);
+    return hipGetLastError();
+  }));
+  return LABFM_OK;
 }
 
 extern "C" int labfm_tune_build(const double* x, const double* y, const double* h,

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LABFM_LIBRARY") or os.path.join(_HERE, "liblabfm.so")
 
 OPS = ("x", "y", "L", "xx", "xy", "hyp")
+NUM_OPS = len(OPS)
 OP_X, OP_Y, OP_L, OP_XX, OP_XY, OP_HYP = range(6)
 F64, F32W, F32_COMP = 0, 1, 2
 
@@ -128,6 +129,7 @@ _SIGNATURES = {
     "labfm_build_weights_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _Box, _P,
                                                    _P, ctypes.c_int64, ctypes.c_uint32, _P, _P,
                                                    _P, _P, _P, _P, _P]),
+    "labfm_solve_systems": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "labfm_apply_operators": (ctypes.c_int, [ctypes.POINTER(_Operators), ctypes.c_uint32, _P, _P,
                                              ctypes.c_int, _P]),
     "labfm_time_step_workspace_bytes": (ctypes.c_size_t, []),
@@ -655,6 +657,27 @@ class RKSolve(torch.autograd.Function):
         g0 = rk_adjoint(q0, qbar, ops, flow, dt, n_steps, ckpt_every, filter)
         rho0 = torch.exp(q0[:n])
         return (g0[:n] / rho0, g0[n:2 * n], g0[2 * n:], None, None, None, None, None, None)
+
+
+def solve_systems(m: int, systems: torch.Tensor):
+    """The weight build's LU with partial pivoting and back substitution
+    (the rows-in-registers kernel) on given systems: systems is float64
+    [count, n, n + 6] on the GPU ([M~ | C~] per system, n = (m^2+3m)/2).
+    Returns Psi [count, n, 6], the pivot row of each column [count, n] and
+    the status of each system [count] (LABFM_NODE_OK or _SINGULAR)."""
+    m = int(m)
+    n = (m * m + 3 * m) // 2
+    if systems.dtype != torch.float64 or not systems.is_cuda or systems.dim() != 3 \
+            or tuple(systems.shape[1:]) != (n, n + NUM_OPS):
+        raise ValueError(f"systems must be float64 [count, {n}, {n + NUM_OPS}] on the GPU")
+    sys_c = systems.contiguous()
+    count = sys_c.shape[0]
+    psi = torch.zeros((count, n, NUM_OPS), dtype=torch.float64, device=sys_c.device)
+    piv = torch.full((count, n), -1, dtype=torch.int32, device=sys_c.device)
+    status = torch.full((count,), -1, dtype=torch.int8, device=sys_c.device)
+    _check(lib().labfm_solve_systems(m, _ptr(sys_c), count, _ptr(psi), _ptr(piv), _ptr(status),
+                                     _stream()))
+    return psi, piv, status
 
 
 def mfma_f64_rate(iters: int = 4096, device=None) -> float:

@@ -61,6 +61,10 @@ def test_argument_errors_return_codes_without_gpu(lib):
     assert code == labfm.ERR_ARG
     assert lib.labfm_rk_workspace_bytes(0) == 0
     assert lib.labfm_rk_workspace_bytes(1000) >= 6 * 1000 * 8
+    # the LU on given systems: order, count and buffers (count 0 does nothing)
+    for m, count in ((0, 1), (11, 1), (4, -1), (4, 1)):
+        assert lib.labfm_solve_systems(m, None, count, None, None, None, None) == labfm.ERR_ARG
+    assert lib.labfm_solve_systems(4, None, 0, None, None, None, None) == labfm.OK
 
 
 def test_calls_refuse_a_missing_or_short_workspace(lib):
