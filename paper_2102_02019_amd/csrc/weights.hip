@@ -1182,7 +1182,10 @@ struct alignas(16) RowSmem {
 // in registers). It emits no instruction.
 __device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
 
-// Largest 32-bit key of the wavefront (all 64 lanes active).
+// Largest 32-bit key of the wavefront, in every lane (all 64 lanes active):
+// the max of each row of 16 lanes by DPP, then of row pairs and of the two
+// halves by gfx950's permlane swaps (each lane sees its own and its
+// partner's value in the swap's two results).
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xF,
                                                                0xF, false)));  // quad [1,0,3,2]
@@ -1192,9 +1195,10 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
                                                                0xF, false)));  // half-row mirror
   v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x140, 0xF,
                                                                0xF, false)));  // row mirror
-  const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
-  const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-  return max(max(r0, r1), max(r2, r3));
+  const auto rows = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = max(static_cast<unsigned>(rows[0]), static_cast<unsigned>(rows[1]));
+  const auto halves = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return max(static_cast<unsigned>(halves[0]), static_cast<unsigned>(halves[1]));
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -1397,6 +1401,8 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
         lds_barrier();
 #pragma unroll
         for (int ks = 0; ks < kChunk / 4; ++ks) {
+          // steps of the last chunk past the K neighbours add only zeros
+          if (k0 + ks * 4 >= K) break;
           const double* tk = &T[(ks * 4 + (lane >> 4)) * S::TABLE];
           double av[NB], bv[QG];
 #pragma unroll
@@ -1562,26 +1568,28 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
   int st = (K < N) ? LABFM_NODE_FEW_NEIGHBOURS : LABFM_NODE_OK;
   if (!singular) {
     // ---- 4: back substitution ------------------------------------------------
-    // column c's pivot lane holds y_c, final once the later columns have
-    // been subtracted; every lane reads y_c and 1/u_cc from that lane and
-    // subtracts (u_rc / u_cc) y_c. Each lane then forms its own
-    // x = y / u_cc once and writes it into Psi (LDS) at its column.
+    // each lane keeps its right-hand sides divided by its own pivot u_qq
+    // (q = mycol), so column c's pivot lane holds x_c = y_c / u_cc once the
+    // later columns have been subtracted; every lane reads x_c from that
+    // lane and subtracts (u_rc / u_qq) x_c, then writes its x into Psi (LDS)
+    // at its column.
     double* psi_t = sm.buf;  // Psi[q][d], q < n (the strips are done)
     // order 10: the right-hand sides of column 0's pivot row (in LDS), kept
     // in every lane and updated as the lanes' own
     double ypr[LABFM_NUM_OPS];
     if constexpr (S::kExtra) {
 #pragma unroll
-      for (int d = 0; d < LABFM_NUM_OPS; ++d) ypr[d] = pr[N + d];
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) ypr[d] = pr[N + d] * inv0;
     }
+#pragma unroll
+    for (int d = 0; d < LABFM_NUM_OPS; ++d) a[N + d] *= myinv;
 #pragma unroll
     for (int c = N - 1; c >= (S::kExtra ? 1 : 0); --c) {
       const unsigned long long b = __builtin_amdgcn_ballot_w64(mycol == c);
       const int pc = static_cast<int>(__builtin_ctzll(b));
-      const double ipc = readlane_f64(myinv, pc);
-      const double coef = (mycol < c) ? a[c] * ipc : 0.0;
+      const double coef = (mycol < c) ? a[c] * myinv : 0.0;
       double cpr = 0.0;
-      if constexpr (S::kExtra) cpr = pr[c] * ipc;
+      if constexpr (S::kExtra) cpr = pr[c] * inv0;
 #pragma unroll
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
         const double yc = readlane_f64(a[N + d], pc);
@@ -1597,13 +1605,13 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
 #pragma unroll
       for (int d = 0; d < LABFM_NUM_OPS; d += 2)
         *reinterpret_cast<double2*>(&psi_t[mycol * LABFM_NUM_OPS + d]) =
-            make_double2(a[N + d] * myinv, a[N + d + 1] * myinv);
+            make_double2(a[N + d], a[N + d + 1]);
     }
     if constexpr (S::kExtra) {
       if (lane == 0) {
 #pragma unroll
         for (int d = 0; d < LABFM_NUM_OPS; d += 2)
-          *reinterpret_cast<double2*>(&psi_t[d]) = make_double2(ypr[d] * inv0, ypr[d + 1] * inv0);
+          *reinterpret_cast<double2*>(&psi_t[d]) = make_double2(ypr[d], ypr[d + 1]);
       }
     }
     lds_barrier();
