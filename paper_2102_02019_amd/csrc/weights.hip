@@ -1233,14 +1233,14 @@ __device__ __forceinline__ void rhs_row(int a, int b, int m, double h, double* c
 }
 
 // Wavefronts per SIMD the rows kernel is compiled for (its registers: the
-// row, n + 6 doubles, and the assembly's accumulators). Measured at m = 8:
-// four waves (128 registers; the LU keeps everything in registers, the
-// assembly reloads a few values per neighbour chunk) take 6.89 ms against
-// 7.06 ms at three (164 registers, no spills), with the same results; five at
-// m <= 6 gain nothing; three at m = 9 would spill in the LU.
+// row, n + 6 doubles, and the assembly's accumulators). Measured on 262,144
+// nodes: at m = 8 four waves (now 123 registers, no spills) took 6.89 ms
+// against 7.06 ms at three when the choice was made; at m = 9 three waves
+// (168 registers, 17 of them spilled) take 10.72 ms against 11.19 ms at two
+// (200 registers, none spilled); five at m <= 6 gain nothing.
 template <int M>
 constexpr int rows_waves() {
-  return M <= 8 ? 4 : 2;
+  return M <= 8 ? 4 : (M == 9 ? 3 : 2);
 }
 
 // Order 10's first pivot row among its 65 rows: lane l holds row l's
@@ -1484,6 +1484,8 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
   // the remaining columns are skipped, so the loop unrolls fully and the rows
   // stay in registers)
   bool used = lane >= N;  // rows beyond n never pivot and are never updated
+  // the same as a wave-uniform mask
+  unsigned long long usedm = N >= 64 ? 0ull : (~0ull << (N < 64 ? N : 0));
   int mycol = used ? N : -1;
   double myinv = 0.0;
   bool singular = false;
@@ -1522,9 +1524,9 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
           static_cast<unsigned long long>(__double_as_longlong(fabs(a[c])));
       const unsigned hi = used ? 0u : static_cast<unsigned>(bits >> 32);
       const unsigned khi = wave_max_u32(hi);
-      const bool top = !used && hi == khi;
-      unsigned long long cand = __builtin_amdgcn_ballot_w64(top);  // never empty
+      unsigned long long cand = __builtin_amdgcn_ballot_w64(hi == khi) & ~usedm;  // never empty
       if (__builtin_popcountll(cand) > 1) {  // equal high words: compare the low words
+        const bool top = !used && hi == khi;
         const unsigned lo = top ? static_cast<unsigned>(bits) : 0u;
         const unsigned klo = wave_max_u32(lo);
         cand = __builtin_amdgcn_ballot_w64(top && lo == klo);
@@ -1541,12 +1543,14 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
         // 1 / u_cc: hardware reciprocal and one Newton step
         double inv = __builtin_amdgcn_rcp(ucc);
         inv = fma(inv, fma(-ucc, inv, 1.0), inv);
+        usedm |= 1ull << p;
         if (lane == p) {
           used = true;
           mycol = c;
           myinv = inv;
         }
-        const double l = used ? 0.0 : a[c] * inv;
+        // minus the multiplier (zero for used rows, +0.0)
+        const double ln = used ? 0.0 : a[c] * -inv;
         // 8 values of the pivot row read out first, then their updates (a
         // read lane's result is used a few instructions later, not at once)
 #pragma unroll
@@ -1557,7 +1561,7 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
 #pragma unroll
           for (int t = 0; t < 8; ++t)
             if (j0 + t < RC) {
-              a[j0 + t] = fma(-l, u[t], a[j0 + t]);
+              a[j0 + t] = fma(ln, u[t], a[j0 + t]);
               pin(a[j0 + t]);
             }
         }
