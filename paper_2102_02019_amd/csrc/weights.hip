@@ -1267,6 +1267,19 @@ __device__ __forceinline__ int first_pivot_of_65(double c0, double v64) {
              : pl;
 }
 
+// The build kernel's arguments read again from the kernel-argument segment
+// (a BuildArgs passed as the kernel's first argument sits at its offset 0).
+// The empty asm statement makes the pointer a new value, so the loads through
+// it are issued where they are used rather than at the kernel's entry: values
+// that the assembly reads need not then be kept (or spilled) across the LU,
+// the kernel's register peak, for the weights.
+typedef const __attribute__((address_space(4))) BuildArgs KernargBuildArgs;
+__device__ __forceinline__ KernargBuildArgs* build_args_again() {
+  KernargBuildArgs* p = (KernargBuildArgs*)(__builtin_amdgcn_kernarg_segment_ptr());
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // Systems given to the rows kernel's LU and back substitution directly (its
 // solve variant): row r of system k at sys + (k n + r)(n + 6), its n values
 // of M~, then its six of C~.
@@ -1630,19 +1643,23 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
 
     // ---- 5: weights, filter calibration, row sums, first moments -------------
     // one lane per neighbour; Psi read from LDS a row at a time (the lanes'
-    // reads of one row are a broadcast)
-    const double kf = 2.0 * M_PI / (3.0 * s);
+    // reads of one row are a broadcast). The arguments and the node's
+    // position, scale and spacing are read again here (see build_args_again).
+    KernargBuildArgs* ga = build_args_again();
+    const double xw = ga->x[i], yw = ga->y[i], hinvw = 1.0 / ga->h[i];
+    const int pxw = ga->box.periodic_x, pyw = ga->box.periodic_y;
+    const double kf = 2.0 * M_PI / (3.0 * ga->s[i]);
     double f0 = 0.0;
     double rs[LABFM_NUM_OPS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mo[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const long long s32 = w32_stride(g.nnz);
+    const long long s32 = w32_stride(ga->nnz);
     // offsets of neighbour k and its Hermite ABF factors: hx[a] = psi He_a(x),
     // hy[b] = He_b(y) (scaled offsets)
     auto basis_of = [&](int k, double& dx, double& dy, double* hx, double* hy) {
-      const int j = g.col[e0 + k];
-      dx = wrap_axis(g.x[j] - xi, g.box.Lx, px);
-      dy = wrap_axis(g.y[j] - yi, g.box.Ly, py);
-      const double xs = dx * hinv, ys = dy * hinv;
+      const int j = ga->col[e0 + k];
+      dx = wrap_axis(ga->x[j] - xw, ga->box.Lx, pxw);
+      dy = wrap_axis(ga->y[j] - yw, ga->box.Ly, pyw);
+      const double xs = dx * hinvw, ys = dy * hinvw;
       const double psi = wendland_c2(sqrt(xs * xs + ys * ys));
       hx[0] = psi;
       hy[0] = 1.0;
@@ -1702,10 +1719,10 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
         }
 #pragma unroll
         for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-          const int r = op_row(g.rows, d);
+          const int r = op_row(ga->rows, d);
           if (r != kNoRow) {
-            g.w[r * g.nnz + e] = wd[d];
-            if (g.w32) g.w32[r * s32 + e] = static_cast<float>(wd[d]);
+            ga->w[r * ga->nnz + e] = wd[d];
+            if (ga->w32) ga->w32[r * s32 + e] = static_cast<float>(wd[d]);
           }
           rs[d] += wd[d];
         }
@@ -1756,10 +1773,10 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
         }
 #pragma unroll
         for (int d = 0; d < H3; ++d) {
-          const int r = op_row(g.rows, og * H3 + d);
+          const int r = op_row(ga->rows, og * H3 + d);
           if (r != kNoRow) {
-            g.w[r * g.nnz + e] = wd[d];
-            if (g.w32) g.w32[r * s32 + e] = static_cast<float>(wd[d]);
+            ga->w[r * ga->nnz + e] = wd[d];
+            if (ga->w32) ga->w32[r * s32 + e] = static_cast<float>(wd[d]);
           }
           // each sum takes this lane's value for its own operators only
           rs[d] += og ? 0.0 : wd[d];
@@ -1785,39 +1802,40 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
 #pragma unroll
     for (int q = 0; q < kMoments; ++q) mo[q] = group_sum<64>(mo[q]);
     if (lane == 0) {
-      if (g.mom32)
+      if (ga->mom32)
 #pragma unroll
-        for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = static_cast<float>(mo[q]);
+        for (int q = 0; q < kMoments; ++q) ga->mom32[q * (long long)ga->n + i] = static_cast<float>(mo[q]);
       const bool bad = !isfinite(f0) || f0 == 0.0;
-      g.kappa[i] = bad ? 0.0 : 2.0 / (3.0 * f0);
+      ga->kappa[i] = bad ? 0.0 : 2.0 / (3.0 * f0);
       if (st == LABFM_NODE_OK && bad) st = LABFM_NODE_BAD_FILTER;
-      g.status[i] = static_cast<int8_t>(st);
-      if (g.rowsum)
+      ga->status[i] = static_cast<int8_t>(st);
+      if (ga->rowsum)
 #pragma unroll
         for (int d = 0; d < LABFM_NUM_OPS; ++d)
-          if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = rs[d];
+          if (op_row(ga->rows, d) != kNoRow) ga->rowsum[op_row(ga->rows, d) * (long long)ga->n + i] = rs[d];
     }
   } else {
     if constexpr (kSolve) {
       if (lane == 0) sv.status[k_] = LABFM_NODE_SINGULAR;
       return;
     }
-    const long long s32 = w32_stride(g.nnz);
+    KernargBuildArgs* ga = build_args_again();
+    const long long s32 = w32_stride(ga->nnz);
     for (int k = lane; k < K; k += 64)
       for (int d = 0; d < LABFM_NUM_OPS; ++d) {
-        const int r = op_row(g.rows, d);
+        const int r = op_row(ga->rows, d);
         if (r == kNoRow) continue;
-        g.w[r * g.nnz + e0 + k] = 0.0;
-        if (g.w32) g.w32[r * s32 + e0 + k] = 0.0f;
+        ga->w[r * ga->nnz + e0 + k] = 0.0;
+        if (ga->w32) ga->w32[r * s32 + e0 + k] = 0.0f;
       }
     if (lane == 0) {
-      g.kappa[i] = 0.0;
-      g.status[i] = LABFM_NODE_SINGULAR;
-      if (g.rowsum)
+      ga->kappa[i] = 0.0;
+      ga->status[i] = LABFM_NODE_SINGULAR;
+      if (ga->rowsum)
         for (int d = 0; d < LABFM_NUM_OPS; ++d)
-          if (op_row(g.rows, d) != kNoRow) g.rowsum[op_row(g.rows, d) * (long long)g.n + i] = 0.0;
-      if (g.mom32)
-        for (int q = 0; q < kMoments; ++q) g.mom32[q * (long long)g.n + i] = 0.0f;
+          if (op_row(ga->rows, d) != kNoRow) ga->rowsum[op_row(ga->rows, d) * (long long)ga->n + i] = 0.0;
+      if (ga->mom32)
+        for (int q = 0; q < kMoments; ++q) ga->mom32[q * (long long)ga->n + i] = 0.0f;
     }
   }
 }
