@@ -1797,10 +1797,15 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
       }
     }
     f0 = group_sum<64>(f0);
+    // the row sums and first moments are reduced only when they are asked for
+    if (ga->rowsum) {
 #pragma unroll
-    for (int d = 0; d < LABFM_NUM_OPS; ++d) rs[d] = group_sum<64>(rs[d]);
+      for (int d = 0; d < LABFM_NUM_OPS; ++d) rs[d] = group_sum<64>(rs[d]);
+    }
+    if (ga->mom32) {
 #pragma unroll
-    for (int q = 0; q < kMoments; ++q) mo[q] = group_sum<64>(mo[q]);
+      for (int q = 0; q < kMoments; ++q) mo[q] = group_sum<64>(mo[q]);
+    }
     if (lane == 0) {
       if (ga->mom32)
 #pragma unroll
