@@ -1793,7 +1793,12 @@ __device__ __forceinline__ void rows_node(BuildArgs g, const int* __restrict__ l
         mo[3] += vxx * dy;
         mo[4] += vxy * dx;
         mo[5] += vxy * dy;
-        f0 += (1.0 - cos(kf * dx) * cos(kf * dy)) * (og ? wd[2] : 0.0);
+        // one cosine per lane: the first half takes x, the second y and
+        // the x factor from its partner (lanes l and l + 32 share neighbour
+        // k and are active together); the second half holds hyp
+        const double cf = cos(kf * (og ? dy : dx));
+        const double cx = __shfl_xor(cf, 32);
+        f0 += og ? (1.0 - cx * cf) * wd[2] : 0.0;
       }
     }
     f0 = group_sum<64>(f0);
