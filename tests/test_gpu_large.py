@@ -365,7 +365,7 @@ def test_full_field_oracle_4m(dev, tg2048, tmp_path):
 # The oracle's filtered RK steps over every node of the 4,194,304-node set:
 # each of the child's workers owns a contiguous range of rows, builds the
 # oracle stencils and weights of its rows once, and evaluates the oracle's
-# right-hand side and filter on them whenever the driver (the oracle's own
+# right-hand side and filter on them whenever the integrator (the oracle's own
 # rk_integrate) asks; the fields pass through shared memory.
 FULL_RK_CHILD = r"""
 import os, sys
